@@ -1,0 +1,212 @@
+"""MRIP throughput on one MI355X: simulated events per second, WAVE (one
+replication per wavefront) against SIMT (one replication per lane), and the
+confidence-interval half-width per GPU-second.
+
+Timed workload (one step = one whole MRIP pass): M/M/1 queue, 1024
+replications x 100000 customers, lambda = 0.9, mu = 1, WAVE mapping; the
+step runs the replications and the fp64 mean/variance reduction on the
+device and builds the 95% interval. Inputs are generated on the device from
+the seed (nothing to stage). One JSON line on stdout.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+R, N, LAM, MU = 1024, 100000, 0.9, 1.0
+FULL_RATE_LANE_OPS = 256 * 4 * 16 * 2.4e9  # 256 CUs x 4 SIMD16 x 2.4 GHz
+
+# VALU issue cost (slots of a full-rate lane op) of the instruction classes in
+# the method's arithmetic, from the committed microbenchmark profile
+# (profiles/valu_rates_gfx950.txt).
+SLOT_COST = {"mad_u64_u32": 4.0, "log_f32": 4.0, "simple": 1.0}
+
+
+def mm1_slots_per_customer(c=SLOT_COST):
+    """Algorithmic VALU slots per customer: half a Philox4x32-10 block (10
+    32x32->64 multiplies, 10 three-input xors), two exponential variates
+    (shift, add, convert, scale, log2, scale), the Lindley step (two
+    subtract/max pairs and an add) and one add into each of three sums."""
+    philox = 10 * c["mad_u64_u32"] + 10 * c["simple"]
+    variates = 2 * (5 * c["simple"] + c["log_f32"])
+    lindley = 5 * c["simple"]
+    sums = 3 * c["simple"]
+    return philox + variates + lindley + sums
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary configs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the CPU-oracle sample")
+    return ap.parse_args()
+
+
+def timed_steps(ctx, steps, warmup, torch, mrip):
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        ctx.run(R, seed=1000 + i)
+        ctx.stats(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    half = None
+    for i in range(steps):
+        ctx.run(R, seed=42 + i, stream=stream.cuda_stream)
+        half = ctx.stats(0)  # the interval closes the step (synchronises)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = ctx.history_ms(steps)
+    return elapsed, kernel_ms, half
+
+
+def cpu_baseline(seconds):
+    """The CPU oracle, unchanged, on a bounded sample of the same workload:
+    whole replications of 1e5 customers run one per host thread."""
+    from oracle import core
+    threads = min(core.default_threads(), 16)
+    t0 = time.perf_counter()
+    core.mm1_many(7, 1, N, LAM, MU)  # calibrate one replication
+    one = time.perf_counter() - t0
+    reps = int(min(max(threads, seconds * threads / max(one, 1e-4)), 20000))
+    t0 = time.perf_counter()
+    core.mm1_many(7, reps, N, LAM, MU, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": reps * N / dt, "unit": "customers/s", "cores": threads, "kind": "oracle",
+            "sample": "%d replications x %d customers (of 1024 x 1e5), %.1f s wall" %
+                      (reps, N, dt)}
+
+
+def extras(torch, mrip, inputs):
+    """Secondary configurations, each timed by the library's kernel events."""
+    out = {}
+
+    def rate(ctx, n, events, runs=3, seed=42):
+        ms = []
+        for i in range(runs):
+            ctx.run(n, seed=seed + i)
+            ms.append(ctx.last_ms())
+        return events / (min(ms) * 1e-3), min(ms)
+
+    # random walk: 32 reps x 64 walkers x 1000 steps on a 64x64 torus
+    for name, mp in (("wave", mrip.MRIP_MAP_WAVE), ("simt", mrip.MRIP_MAP_SIMT)):
+        ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), mp)
+        v, ms = rate(ctx, 32, 32 * 64 * 1000)
+        out.setdefault("rw_32x64x1000", {})[name] = {"walker_steps_per_s": v, "kernel_ms": ms}
+    rw = out["rw_32x64x1000"]
+    rw["wave_over_simt"] = rw["wave"]["walker_steps_per_s"] / rw["simt"]["walker_steps_per_s"]
+
+    # forest fire: 4096 reps x 128^2 x 2000 steps
+    ev = 4096 * 128 * 128 * 2000
+    ctx = mrip.Context(mrip.MRIP_FF, mrip.ff_params(128, 2000, 0.01, 1e-5), mrip.MRIP_MAP_WAVE)
+    v, ms = rate(ctx, 4096, ev, runs=2)
+    s = ctx.stats(0)
+    ff = {"wave": {"cell_updates_per_s": v, "kernel_ms": ms, "mean_burnt": s["mean"],
+                   "half_width": s["half_width"]}}
+    ctx = mrip.Context(mrip.MRIP_FF, mrip.ff_params(128, 2000, 0.01, 1e-5), mrip.MRIP_MAP_SIMT)
+    v, ms = rate(ctx, 4096, ev, runs=1)
+    ff["simt"] = {"cell_updates_per_s": v, "kernel_ms": ms}
+    ff["wave_over_simt"] = ff["wave"]["cell_updates_per_s"] / ff["simt"]["cell_updates_per_s"]
+    out["ff_4096x128x128x2000"] = ff
+
+    # uneven plan: 64 dp x 32 reps, N log-uniform in [1e4, 1e6], one launch
+    items = inputs.plan_table()
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), mrip.MRIP_MAP_WAVE)
+    ctx.plan_set(items)
+    rpw, wg, tune_ms = ctx.autotune(42)
+    ms = []
+    for i in range(3):
+        ctx.run_plan(42 + i)
+        ms.append(ctx.last_ms())
+    total = float(items["customers"].sum())
+    out["plan_64x32"] = {"customers": total, "kernel_ms": min(ms),
+                         "customers_per_s": total / (min(ms) * 1e-3),
+                         "tuned_shape": {"reps_per_wave": rpw, "workgroup": wg},
+                         "longest_item": int(items["customers"].max())}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(replications shard trivially; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1501_01405_amd import inputs, mrip
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    mrip.load()
+
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_WAVE)
+    elapsed, kernel_ms, ci = timed_steps(ctx, args.steps, args.warmup, torch, mrip)
+    customers = R * N
+    value = customers * args.steps / elapsed
+    ms_step = elapsed / args.steps * 1e3
+    avg_kernel_ms = sum(kernel_ms) / len(kernel_ms)
+
+    slots = mm1_slots_per_customer()
+    achieved = slots * customers / (avg_kernel_ms * 1e-3)
+
+    # SIMT mapping on the same workload (kernel events, outside the timed loop)
+    simt = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_SIMT)
+    simt_ms = []
+    for i in range(3):
+        simt.run(R, seed=42 + i)
+        simt_ms.append(simt.last_ms())
+    simt_rate = customers / (min(simt_ms) * 1e-3)
+    simt_ci = simt.stats(0)
+
+    line = {
+        "metric": "simulated events/sec on 1 MI355X (WLP vs SIMT); CI half-width per GPU-second",
+        "value": value,
+        "unit": "customers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (Philox4x32-10 streams generated on the device, seed 42+step)",
+        "config": {"workload": "M/M/1 MRIP, 1024 replications x 100000 customers, "
+                               "lambda=0.9, mu=1, one replication per wavefront",
+                   "replications": R, "customers": N, "mapping": "WAVE"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                     "peak": FULL_RATE_LANE_OPS / 1e12, "unit": "Tslot/s",
+                     "frac": achieved / FULL_RATE_LANE_OPS, "traffic": None,
+                     "kernel": "mm1_wave_kernel<1>", "avg_kernel_ms": avg_kernel_ms,
+                     "slots_per_customer": slots},
+        "ci": {"mean_wq": ci["mean"], "half_width_95": ci["half_width"],
+               "gpu_seconds_per_step": ms_step * 1e-3,
+               "half_width_x_sqrt_gpu_s": ci["half_width"] * math.sqrt(ms_step * 1e-3)},
+        "simt": {"customers_per_s": simt_rate, "kernel_ms": min(simt_ms),
+                 "half_width_x_sqrt_gpu_s": simt_ci["half_width"] *
+                 math.sqrt(min(simt_ms) * 1e-3)},
+        "wave_over_simt": (customers / (avg_kernel_ms * 1e-3)) / simt_rate,
+        "paper_reference": "WLP up to ~6x faster than SIMT: Tesla C2050 (Fermi), random walk, "
+                           "1000 steps, taus88 PRNG (context, not a target)",
+    }
+    if not args.no_extras:
+        line["extras"] = extras(torch, mrip, inputs)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

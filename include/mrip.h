@@ -1,0 +1,272 @@
+/*
+ * mrip.h -- Multiple Replications In Parallel on one MI355X (gfx950).
+ *
+ * The method (Passerat-Palmbach et al., "Warp-Level Parallelism: Enabling
+ * Multiple Replications In Parallel on GPU", ESM 2011, section 1): run the
+ * same stochastic simulation many times with independent random sources,
+ * in parallel, and reduce the per-replication outputs to a mean, a variance
+ * and a confidence interval (at least 30 replications, central limit
+ * theorem). Section 3 compares one replication per thread (SIMT) with one
+ * replication per warp; here the second form is one replication per 64-lane
+ * wavefront with every lane working on it (MRIP_MAP_WAVE).
+ *
+ * Random streams: Philox4x32-10 (Salmon et al., SC'11), key = the 64-bit
+ * seed, counter = (draw index, entity, replication, model tag). Outputs are
+ * pure functions of (seed, replication id, parameters): they do not depend
+ * on the mapping's launch shape, on the number of replications run, or on
+ * the order in which the device schedules them.
+ *
+ * Conventions for every call:
+ *  - Every call returns mrip_status; nothing throws across this boundary.
+ *    HIP failures return MRIP_E_HIP with the HIP error text in
+ *    mrip_last_error(ctx).
+ *  - `hip_stream` is a caller-owned hipStream_t (NULL = the null stream).
+ *    Run calls only enqueue work and return; calls that hand results back
+ *    to the host synchronise that stream first.
+ *  - Pointers named *_dev are device pointers the caller owns (for example
+ *    torch tensors); pointers without the suffix are host pointers, read
+ *    during the call only. The context owns every buffer it allocates and
+ *    frees them in mrip_destroy.
+ *  - A context is not thread-safe: use one per host thread.
+ */
+#ifndef MRIP_H
+#define MRIP_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define MRIP_API __attribute__((visibility("default")))
+#else
+#define MRIP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrip_ctx_s *mrip_ctx;
+
+typedef enum {
+  MRIP_OK = 0,
+  MRIP_E_INVAL = -1,       /* bad argument or parameter                       */
+  MRIP_E_NOMEM = -2,       /* device or host allocation failed                */
+  MRIP_E_HIP = -3,         /* a HIP runtime call failed                       */
+  MRIP_E_STATE = -4,       /* call out of order (e.g. stats before any run)   */
+  MRIP_E_TOO_FEW = -5,     /* fewer than two replications for an interval     */
+  MRIP_E_UNSUPPORTED = -6  /* valid request this build does not implement     */
+} mrip_status;
+
+typedef enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3 } mrip_model;
+
+/* SIMT: one replication per lane. WAVE: one replication per 64-lane
+ * wavefront (or 2 / 4 replications per wavefront on 32 / 16 lanes each, see
+ * mrip_set_shape). AUTO picks WAVE. */
+typedef enum { MRIP_MAP_AUTO = 0, MRIP_MAP_SIMT = 1, MRIP_MAP_WAVE = 2 } mrip_mapping;
+
+/* Parameter structs: `size` must equal sizeof(the struct); they are copied
+ * by mrip_create. */
+
+/* Lattice random walk (paper section 5.1, third model): `walkers` walkers
+ * (1..64) on a grid x grid torus (grid in {16, 32, 64, 128}), `steps` unit
+ * moves each; walker w starts at ((w%8)*grid/8 + grid/16, (w/8)*grid/8 +
+ * grid/16). Move t of walker w in replication r is 2 bits of block
+ * (t>>6, w, r, 1): word (t>>4)&3, bits 2(t&15); 0:+x 1:-x 2:+y 3:-y.
+ * Outputs: 0 = int32 sum of squared unwrapped displacements,
+ *          1 = int32 number of distinct sites visited (starts included).
+ * Requires walkers * steps^2 < 2^31. */
+typedef struct {
+  uint32_t size;
+  uint32_t walkers, grid, steps;
+} mrip_rw_params;
+
+/* M/M/1 queue (paper section 5.1, second model), starting empty. Customer n
+ * draws interarrival A_n ~ Exp(lambda) and service S_n ~ Exp(mu) from words
+ * 2(n&1), 2(n&1)+1 of block (n>>1, dp, r, 2) as mean * -log(u),
+ * u = ((x>>8)+1) 2^-24; then W_n = max(0, T_{n-1} - A_n),
+ * I_n = max(0, A_n - T_{n-1}), T_n = W_n + S_n, T_{-1} = 0, all in fp32.
+ * Outputs: 0 = mean W (waiting time in queue), 1 = mean T (time in system),
+ *          2 = mean I (server idle time per arrival), all fp32;
+ *          3 = when feature_prefix K > 0, 10 fp32 features per replication
+ *              over customers 0..K-1: rho, mu, mean A, mean S, mean W,
+ *              mean T, fraction with W = 0, max W, mean I, T_{K-1}.
+ * mrip_run uses dp = 0. Requires 1 <= customers < 2^33, K <= customers. */
+typedef struct {
+  uint32_t size;
+  float lambda, mu;
+  uint64_t customers;
+  uint64_t feature_prefix;
+} mrip_mm1_params;
+
+/* Drossel-Schwabl forest fire, synchronous, grid x grid torus, von Neumann
+ * neighbourhood, starting empty. Per step, cell c = y*grid + x reads
+ * u = word c&3 of block (t, c>>2, r, 3): burning -> empty; tree -> burning
+ * if a neighbour burns or u < floor(f_light 2^32); empty -> tree if
+ * u < floor(p_grow 2^32). Output 0 = int32 count of tree -> burning
+ * transitions. grid in {64, 128} for WAVE, a multiple of 32 up to 256 for
+ * SIMT; grid^2 * steps < 2^31. */
+typedef struct {
+  uint32_t size;
+  uint32_t grid, steps;
+  double p_grow, f_light;
+} mrip_ff_params;
+
+typedef struct {
+  uint64_t n;
+  double mean, var;        /* var: unbiased, over replications          */
+  double half_width;       /* t_quantile * sqrt(var / n)                */
+  double t_quantile;       /* Student-t quantile, n - 1 degrees of freedom */
+  double confidence;
+} mrip_stats_t;
+
+/* One replication of an experimental plan (M/M/1 design point dp). */
+typedef struct {
+  uint32_t dp, rep;
+  uint64_t customers;
+  float lambda, mu;
+} mrip_plan_item;
+
+/* ---------------------------------------------------------------- context */
+
+/* Validate `params` (a struct matching `model`) and create a context; no
+ * kernel runs. */
+MRIP_API mrip_status mrip_create(mrip_ctx *out, mrip_model model, const void *params,
+                        mrip_mapping mapping);
+MRIP_API void mrip_destroy(mrip_ctx ctx);
+
+/* WAVE launch shape: replications per wavefront (1, 2 or 4) and workgroup
+ * size (64, 256 or 1024). Outputs do not depend on it. Defaults 1 and 256. */
+MRIP_API mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t reps_per_wave, uint32_t workgroup);
+
+/* --------------------------------------------------------------- the path */
+
+/* Run replications 0..n_reps-1 with key `seed` (paper section 1: MRIP),
+ * then reduce every scalar output over replications in fp64 on the device.
+ * Asynchronous on hip_stream. */
+MRIP_API mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_stream);
+
+/* Mean, unbiased variance and Student-t interval of output `output` of the
+ * last run (paper section 1). Synchronises the stream of that run.
+ * MRIP_E_TOO_FEW if fewer than two replications. */
+MRIP_API mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence, mrip_stats_t *out);
+
+/* Copy output `output` of the last run (n_reps values; 10 per replication
+ * for M/M/1 features) to dst, a device pointer if dst_is_device, else host.
+ * `bytes` must be at least the output's size. Synchronises. */
+MRIP_API mrip_status mrip_outputs(mrip_ctx ctx, uint32_t output, void *dst, uint64_t bytes,
+                         int dst_is_device);
+
+/* Device pointer to output `output` of the last run (valid until the next
+ * run or mrip_destroy); for zero-copy readers on the same stream. */
+MRIP_API mrip_status mrip_output_ptr(mrip_ctx ctx, uint32_t output, const void **ptr_dev);
+
+/* Milliseconds of the last run's simulation kernel (hipEvents around the
+ * launch on its stream). Synchronises. */
+MRIP_API mrip_status mrip_last_run_ms(mrip_ctx ctx, float *ms);
+
+/* Kernel milliseconds of the last min(max_n, launches, 256) simulation
+ * launches of this context (mrip_run, mrip_run_plan, autotune), oldest
+ * first, into ms[0..*n_out). Synchronises on those launches. */
+MRIP_API mrip_status mrip_run_history_ms(mrip_ctx ctx, float *ms, uint32_t max_n,
+                                         uint32_t *n_out);
+
+/* --------------------------------- batching: an uneven experimental plan */
+/* (paper section 1: an experimental plan runs sets of replications at
+ * different factor levels; here all of them in one persistent launch) */
+
+/* Upload a plan (M/M/1 contexts only). Items keep their index for outputs;
+ * the device queue serves them longest-first. Host pointer, n >= 1. */
+MRIP_API mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n);
+
+/* Run every item of the plan in one persistent-kernel launch whose waves
+ * pop work from a device queue, then reduce per design point. Outputs are
+ * indexed like the uploaded items. Asynchronous. */
+MRIP_API mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream);
+
+/* Stats of output 0 (mean W) over the items of design point `dp` in the
+ * last plan run. Synchronises. */
+MRIP_API mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_stats_t *out);
+
+/* Time every (reps_per_wave, workgroup) in {1,2,4} x {64,256,1024} on the
+ * uploaded plan (or on its first `calib_items` items, 0 = all), keep the
+ * fastest as the context's shape and report it. Synchronises. */
+MRIP_API mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, void *hip_stream,
+                          uint32_t *best_rpw, uint32_t *best_workgroup, float *best_ms);
+
+/* ----------------------------------------- learned control variate (CV) */
+/* Not in the paper: a small network g(x) maps the first K customers' summary
+ * features x of an M/M/1 replication to a prediction of its mean wait Y; the
+ * two-phase estimator mean(Y - beta g(X)) + beta mean(g(X')) over full and
+ * independent prefix-only replications stays unbiased for any g. */
+
+#define MRIP_MLP_PARAMS 18049 /* W1[128x10] b1[128] W2[128x128] b2[128] W3[1x128] b3[1] */
+
+/* Forward pass of the 10-128-128-1 ReLU network, bf16 operands with fp32
+ * accumulation. theta_dev: MRIP_MLP_PARAMS fp32; x_dev: n x 10 fp32
+ * (normalised features); y_dev: n fp32. */
+MRIP_API mrip_status mrip_mlp_forward(const float *theta_dev, const float *x_dev, uint64_t n,
+                             float *y_dev, void *hip_stream);
+
+/* Gradient of mean((g(x) - y)^2) over the n rows: grad_dev gets
+ * MRIP_MLP_PARAMS fp32 values, loss_dev one fp32 (nullable). n <= 65536. */
+MRIP_API mrip_status mrip_mlp_grad(const float *theta_dev, const float *x_dev, const float *y_dev,
+                          uint64_t n, float *grad_dev, float *loss_dev, void *hip_stream);
+
+/* One Adam step (Kingma and Ba 2015, Algorithm 1) on fp32 weights;
+ * `step` counts from 1. */
+MRIP_API mrip_status mrip_adam_step(float *theta_dev, float *m_dev, float *v_dev, const float *grad_dev,
+                           uint64_t n_params, uint64_t step, float lr, float beta1, float beta2,
+                           float eps, void *hip_stream);
+
+typedef struct {
+  uint32_t size;
+  uint32_t epochs, batch;      /* default 20, 1024 */
+  float lr, beta1, beta2, eps; /* default 1e-3, 0.9, 0.999, 1e-8 */
+} mrip_cv_hparams;
+
+/* Generate the training set with the M/M/1 engine (one replication per item,
+ * features over the context's feature_prefix customers, target = mean W),
+ * normalise features, train from theta0 (host, MRIP_MLP_PARAMS fp32) with
+ * Adam, and fix beta = 1. hparams nullable (defaults). Synchronises. */
+MRIP_API mrip_status mrip_cv_train(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n,
+                          const float *theta0, const mrip_cv_hparams *hparams, uint64_t seed,
+                          void *hip_stream);
+
+/* Copy the trained weights (MRIP_MLP_PARAMS) and the feature mean / std
+ * (10 + 10 fp32) to host buffers (any may be NULL). */
+MRIP_API mrip_status mrip_cv_model(mrip_ctx ctx, float *theta, float *feat_mean, float *feat_std,
+                          float *final_loss);
+
+/* Apply the trained control variate: full items (features + mean W) and
+ * prefix-only items (customers = feature prefix, stream ids disjoint from
+ * the full ones) grouped by dp; per design point compute the CV and plain
+ * estimates. Synchronises. */
+MRIP_API mrip_status mrip_cv_apply(mrip_ctx ctx, const mrip_plan_item *full, uint64_t n_full,
+                          const mrip_plan_item *prefix, uint64_t n_prefix, uint64_t seed,
+                          void *hip_stream);
+
+/* CV and plain estimates for design point `dp` of the last apply. */
+MRIP_API mrip_status mrip_cv_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_stats_t *cv,
+                          mrip_stats_t *plain);
+
+/* Milliseconds spent in the last apply on full replications, on prefix
+ * replications and on network inference. */
+MRIP_API mrip_status mrip_cv_times(mrip_ctx ctx, float *full_ms, float *prefix_ms, float *infer_ms);
+
+/* ------------------------------------------------------------ utilities */
+
+/* Raw Philox4x32-10 blocks: out_dev[4i..4i+3] = Philox(ctr_dev[4i..4i+3],
+ * key = seed). Device pointers, n blocks. */
+MRIP_API mrip_status mrip_philox(uint64_t seed, const uint32_t *ctr_dev, uint64_t n, uint32_t *out_dev,
+                        void *hip_stream);
+
+/* Student-t quantile t_{p, dof} for 0.5 <= p < 1, dof > 0 (host). */
+MRIP_API double mrip_t_quantile(double p, double dof);
+
+MRIP_API const char *mrip_status_string(mrip_status s);
+MRIP_API const char *mrip_last_error(mrip_ctx ctx); /* valid until the next call on ctx */
+MRIP_API const char *mrip_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRIP_H */

@@ -1,0 +1,517 @@
+// C ABI of the MRIP library (include/mrip.h): argument checks, device
+// buffers owned by the context, kernel launches and the host-side end of
+// the statistics. No C++ exception crosses the boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mrip.h"
+#include "context.hpp"
+#include "kernels.hpp"
+
+namespace mrip {
+double t_quantile(double p, double nu);
+}
+
+using namespace mrip;
+
+namespace {
+
+mrip_status hip_fail(mrip_ctx c, hipError_t e, const char *what) {
+  if (c) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return MRIP_E_HIP;
+}
+
+mrip_status inval(mrip_ctx c, const char *why) {
+  if (c) c->err = why;
+  return MRIP_E_INVAL;
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return hip_fail((ctx), _e, #expr); \
+  } while (0)
+
+uint32_t scalar_outputs(mrip_model m) { return m == MRIP_RW ? 2 : m == MRIP_MM1 ? 3 : 1; }
+
+bool is_pow2_grid(uint32_t g) { return g == 16 || g == 32 || g == 64 || g == 128; }
+
+mrip_mapping effective(mrip_mapping m) { return m == MRIP_MAP_SIMT ? MRIP_MAP_SIMT : MRIP_MAP_WAVE; }
+
+uint32_t ff_threshold(double prob) {
+  double v = std::floor(prob * 4294967296.0);
+  if (v < 0.0) v = 0.0;
+  if (v > 4294967295.0) v = 4294967295.0;
+  return (uint32_t)v;
+}
+
+mrip_status ensure_events(mrip_ctx c) {
+  if (!c->ev0) HIP_TRY(c, hipEventCreate(&c->ev0));
+  if (!c->ev1) HIP_TRY(c, hipEventCreate(&c->ev1));
+  return MRIP_OK;
+}
+
+// Events bracketing one simulation-kernel launch: the context's last-run
+// pair and the next slot of the run-history ring.
+mrip_status record_begin(mrip_ctx c, hipStream_t s) {
+  const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
+  if (!c->ring0[slot]) HIP_TRY(c, hipEventCreate(&c->ring0[slot]));
+  if (!c->ring1[slot]) HIP_TRY(c, hipEventCreate(&c->ring1[slot]));
+  HIP_TRY(c, hipEventRecord(c->ev0, s));
+  HIP_TRY(c, hipEventRecord(c->ring0[slot], s));
+  return MRIP_OK;
+}
+
+mrip_status record_end(mrip_ctx c, hipStream_t s) {
+  const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
+  HIP_TRY(c, hipEventRecord(c->ev1, s));
+  HIP_TRY(c, hipEventRecord(c->ring1[slot], s));
+  ++c->launches;
+  return MRIP_OK;
+}
+
+mrip_status finish_stats(const double *nmv, double confidence, mrip_stats_t *out) {
+  const uint64_t n = (uint64_t)nmv[0];
+  if (n < 2) return MRIP_E_TOO_FEW;
+  out->n = n;
+  out->mean = nmv[1];
+  out->var = nmv[2];
+  out->confidence = confidence;
+  out->t_quantile = mrip::t_quantile(0.5 + 0.5 * confidence, (double)(n - 1));
+  out->half_width = out->t_quantile * std::sqrt(nmv[2] / (double)n);
+  return MRIP_OK;
+}
+
+mrip_status validate(mrip_model model, const void *params, mrip_mapping map, std::string &why) {
+  if (!params) return why = "params is NULL", MRIP_E_INVAL;
+  if (map != MRIP_MAP_AUTO && map != MRIP_MAP_SIMT && map != MRIP_MAP_WAVE)
+    return why = "unknown mapping", MRIP_E_INVAL;
+  if (model == MRIP_RW) {
+    const mrip_rw_params *p = (const mrip_rw_params *)params;
+    if (p->size != sizeof(mrip_rw_params)) return why = "mrip_rw_params.size mismatch", MRIP_E_INVAL;
+    if (p->walkers < 1 || p->walkers > 64) return why = "walkers must be in 1..64", MRIP_E_INVAL;
+    if (!is_pow2_grid(p->grid)) return why = "grid must be 16, 32, 64 or 128", MRIP_E_INVAL;
+    if ((double)p->walkers * (double)p->steps * (double)p->steps >= 2147483648.0)
+      return why = "walkers * steps^2 must be < 2^31", MRIP_E_INVAL;
+    return MRIP_OK;
+  }
+  if (model == MRIP_MM1) {
+    const mrip_mm1_params *p = (const mrip_mm1_params *)params;
+    if (p->size != sizeof(mrip_mm1_params)) return why = "mrip_mm1_params.size mismatch", MRIP_E_INVAL;
+    if (!(p->lambda > 0.0f) || !(p->mu > 0.0f) || !std::isfinite(p->lambda) || !std::isfinite(p->mu))
+      return why = "lambda and mu must be finite and > 0", MRIP_E_INVAL;
+    if (p->customers < 1 || p->customers >= (1ull << 33))
+      return why = "customers must be in [1, 2^33)", MRIP_E_INVAL;
+    if (p->feature_prefix > p->customers) return why = "feature_prefix > customers", MRIP_E_INVAL;
+    return MRIP_OK;
+  }
+  if (model == MRIP_FF) {
+    const mrip_ff_params *p = (const mrip_ff_params *)params;
+    if (p->size != sizeof(mrip_ff_params)) return why = "mrip_ff_params.size mismatch", MRIP_E_INVAL;
+    if (p->grid < 32 || p->grid > 256 || p->grid % 32 != 0)
+      return why = "grid must be a multiple of 32 in 32..256", MRIP_E_INVAL;
+    if (effective(map) == MRIP_MAP_WAVE && p->grid != 64 && p->grid != 128)
+      return why = "the WAVE mapping supports grid 64 or 128", MRIP_E_INVAL;
+    if (!(p->p_grow >= 0.0 && p->p_grow <= 1.0) || !(p->f_light >= 0.0 && p->f_light <= 1.0))
+      return why = "probabilities must be in [0, 1]", MRIP_E_INVAL;
+    if ((double)p->grid * p->grid * (double)p->steps >= 2147483648.0)
+      return why = "grid^2 * steps must be < 2^31", MRIP_E_INVAL;
+    return MRIP_OK;
+  }
+  return why = "unknown model", MRIP_E_INVAL;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mrip_version(void) { return "mrip 0.1 (gfx950)"; }
+
+const char *mrip_status_string(mrip_status s) {
+  switch (s) {
+    case MRIP_OK: return "ok";
+    case MRIP_E_INVAL: return "invalid argument";
+    case MRIP_E_NOMEM: return "out of memory";
+    case MRIP_E_HIP: return "HIP error";
+    case MRIP_E_STATE: return "call out of order";
+    case MRIP_E_TOO_FEW: return "fewer than two replications";
+    case MRIP_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char *mrip_last_error(mrip_ctx ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+double mrip_t_quantile(double p, double dof) { return mrip::t_quantile(p, dof); }
+
+mrip_status mrip_create(mrip_ctx *out, mrip_model model, const void *params,
+                        mrip_mapping mapping) {
+  if (!out) return MRIP_E_INVAL;
+  *out = nullptr;
+  std::string why;
+  mrip_status st = validate(model, params, mapping, why);
+  if (st != MRIP_OK) return st;
+  mrip_ctx c = new (std::nothrow) mrip_ctx_s();
+  if (!c) return MRIP_E_NOMEM;
+  c->model = model;
+  c->mapping = effective(mapping);
+  if (model == MRIP_RW) c->rw = *(const mrip_rw_params *)params;
+  if (model == MRIP_MM1) c->mm1 = *(const mrip_mm1_params *)params;
+  if (model == MRIP_FF) c->ff = *(const mrip_ff_params *)params;
+  *out = c;
+  return MRIP_OK;
+}
+
+void mrip_destroy(mrip_ctx ctx) {
+  if (!ctx) return;
+  if (ctx->last_stream) (void)hipStreamSynchronize(ctx->last_stream);
+  delete ctx;
+}
+
+mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t rpw, uint32_t wg) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (rpw != 1 && rpw != 2 && rpw != 4) return inval(ctx, "reps_per_wave must be 1, 2 or 4");
+  if (wg != 64 && wg != 256 && wg != 1024) return inval(ctx, "workgroup must be 64, 256 or 1024");
+  if (rpw != 1 && ctx->model != MRIP_MM1)
+    return inval(ctx, "reps_per_wave > 1 is only defined for the M/M/1 engine");
+  ctx->rpw = rpw;
+  ctx->wg = wg;
+  return MRIP_OK;
+}
+
+mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_stream) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (n_reps == 0) return inval(ctx, "n_reps must be >= 1");
+  if (n_reps > 0xFFFFFFFFull) return inval(ctx, "n_reps must be < 2^32");
+  hipStream_t s = (hipStream_t)hip_stream;
+  mrip_status st = ensure_events(ctx);
+  if (st != MRIP_OK) return st;
+  const uint32_t nout = scalar_outputs(ctx->model);
+  for (uint32_t o = 0; o < nout; ++o) HIP_TRY(ctx, ctx->out[o].ensure(n_reps * 4));
+  HIP_TRY(ctx, ctx->stats.ensure(sizeof(double) * 3 * 4));
+  const bool wave = ctx->mapping == MRIP_MAP_WAVE;
+
+  st = record_begin(ctx, s);
+  if (st != MRIP_OK) return st;
+  if (ctx->model == MRIP_RW) {
+    RwArgs a{};
+    a.seed = seed;
+    a.walkers = ctx->rw.walkers;
+    a.grid = ctx->rw.grid;
+    a.steps = ctx->rw.steps;
+    a.n_reps = n_reps;
+    a.ssd = ctx->out[0].as<int32_t>();
+    a.distinct = ctx->out[1].as<int32_t>();
+    if (wave) {
+      HIP_TRY(ctx, launch_rw_wave(a, ctx->wg, s));
+    } else {
+      HIP_TRY(ctx, ctx->scratch.ensure(n_reps * (uint64_t)a.grid * a.grid / 8));
+      a.scratch_bitmaps = ctx->scratch.as<uint32_t>();
+      HIP_TRY(ctx, launch_rw_simt(a, s));
+    }
+  } else if (ctx->model == MRIP_MM1) {
+    Mm1Args a{};
+    a.seed = seed;
+    a.n_reps = n_reps;
+    a.lambda = ctx->mm1.lambda;
+    a.mu = ctx->mm1.mu;
+    a.customers = ctx->mm1.customers;
+    a.feature_prefix = ctx->mm1.feature_prefix;
+    a.mean_w = ctx->out[0].as<float>();
+    a.mean_t = ctx->out[1].as<float>();
+    a.mean_i = ctx->out[2].as<float>();
+    if (a.feature_prefix > 0) {
+      HIP_TRY(ctx, ctx->out[3].ensure(n_reps * 40));
+      a.features = ctx->out[3].as<float>();
+    }
+    if (wave) HIP_TRY(ctx, launch_mm1_wave(a, ctx->rpw, ctx->wg, s));
+    else HIP_TRY(ctx, launch_mm1_simt(a, s));
+  } else {
+    FfArgs a{};
+    a.seed = seed;
+    a.grid = ctx->ff.grid;
+    a.steps = ctx->ff.steps;
+    a.tp = ff_threshold(ctx->ff.p_grow);
+    a.tf = ff_threshold(ctx->ff.f_light);
+    a.n_reps = n_reps;
+    a.burnt = ctx->out[0].as<int32_t>();
+    if (wave) {
+      HIP_TRY(ctx, launch_ff_wave(a, ctx->wg, s));
+    } else {
+      HIP_TRY(ctx, ctx->scratch.ensure(n_reps * 2ull * a.grid * (a.grid / 32) * 4));
+      a.state = ctx->scratch.as<uint32_t>();
+      HIP_TRY(ctx, launch_ff_simt(a, s));
+    }
+  }
+  st = record_end(ctx, s);
+  if (st != MRIP_OK) return st;
+  const int dtype = ctx->model == MRIP_MM1 ? 1 : 0;
+  for (uint32_t o = 0; o < nout; ++o)
+    HIP_TRY(ctx, launch_reduce_f64(ctx->out[o].p, dtype, n_reps, nullptr, 1,
+                                   ctx->stats.as<double>() + 3 * o, s));
+  ctx->last = RUN_UNIFORM;
+  ctx->last_n = n_reps;
+  ctx->last_stream = s;
+  return MRIP_OK;
+}
+
+mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence, mrip_stats_t *out) {
+  if (!ctx || !out) return MRIP_E_INVAL;
+  if (!(confidence > 0.0 && confidence < 1.0)) return inval(ctx, "confidence must be in (0, 1)");
+  if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
+  if (output >= scalar_outputs(ctx->model)) return inval(ctx, "no such scalar output");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  double nmv[3];
+  HIP_TRY(ctx, hipMemcpy(nmv, ctx->stats.as<double>() + 3 * output, sizeof(nmv),
+                         hipMemcpyDeviceToHost));
+  mrip_status st = finish_stats(nmv, confidence, out);
+  if (st == MRIP_E_TOO_FEW) ctx->err = "fewer than two replications";
+  return st;
+}
+
+mrip_status mrip_output_ptr(mrip_ctx ctx, uint32_t output, const void **ptr) {
+  if (!ctx || !ptr) return MRIP_E_INVAL;
+  if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
+  const bool feat = ctx->model == MRIP_MM1 && output == 3 && ctx->mm1.feature_prefix > 0;
+  if (output >= scalar_outputs(ctx->model) && !feat) return inval(ctx, "no such output");
+  *ptr = ctx->out[output].p;
+  return MRIP_OK;
+}
+
+mrip_status mrip_outputs(mrip_ctx ctx, uint32_t output, void *dst, uint64_t bytes,
+                         int dst_is_device) {
+  if (!ctx || !dst) return MRIP_E_INVAL;
+  if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
+  const bool feat = ctx->model == MRIP_MM1 && output == 3 && ctx->mm1.feature_prefix > 0;
+  if (output >= scalar_outputs(ctx->model) && !feat) return inval(ctx, "no such output");
+  const uint64_t need = ctx->last_n * (feat ? 40 : 4);
+  if (bytes < need) return inval(ctx, "destination too small");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  HIP_TRY(ctx, hipMemcpy(dst, ctx->out[output].p, need,
+                         dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return MRIP_OK;
+}
+
+mrip_status mrip_run_history_ms(mrip_ctx ctx, float *ms, uint32_t max_n, uint32_t *n_out) {
+  if (!ctx || !n_out || (max_n > 0 && !ms)) return MRIP_E_INVAL;
+  uint64_t avail = std::min<uint64_t>(ctx->launches, mrip_ctx_s::RING);
+  uint32_t n = (uint32_t)std::min<uint64_t>(avail, max_n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint64_t launch = ctx->launches - n + i;
+    const uint32_t slot = (uint32_t)(launch % mrip_ctx_s::RING);
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ring1[slot]));
+    HIP_TRY(ctx, hipEventElapsedTime(&ms[i], ctx->ring0[slot], ctx->ring1[slot]));
+  }
+  *n_out = n;
+  return MRIP_OK;
+}
+
+mrip_status mrip_last_run_ms(mrip_ctx ctx, float *ms) {
+  if (!ctx || !ms) return MRIP_E_INVAL;
+  if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
+  HIP_TRY(ctx, hipEventElapsedTime(ms, ctx->ev0, ctx->ev1));
+  return MRIP_OK;
+}
+
+// ------------------------------------------------------------------ plan
+
+mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (ctx->model != MRIP_MM1) return (ctx->err = "plans need an M/M/1 context"), MRIP_E_UNSUPPORTED;
+  if (!items || n == 0) return inval(ctx, "empty plan");
+  if (n > 0xFFFFFFFFull) return inval(ctx, "plan too large");
+  std::vector<uint32_t> dp(n), rep(n), order(n), index(n);
+  std::vector<uint64_t> cust(n);
+  std::vector<float> lam(n), mu(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    const mrip_plan_item &it = items[i];
+    if (it.customers < 1 || it.customers >= (1ull << 33)) return inval(ctx, "item customers out of range");
+    if (!(it.lambda > 0.0f) || !(it.mu > 0.0f) || !std::isfinite(it.lambda) || !std::isfinite(it.mu))
+      return inval(ctx, "item rates must be finite and > 0");
+    if (ctx->mm1.feature_prefix > it.customers) return inval(ctx, "item shorter than the feature prefix");
+    dp[i] = it.dp;
+    rep[i] = it.rep;
+    cust[i] = it.customers;
+    lam[i] = it.lambda;
+    mu[i] = it.mu;
+    order[i] = (uint32_t)i;
+    index[i] = (uint32_t)i;
+  }
+  // longest-processing-time-first queue order
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t a, uint32_t b) { return cust[a] > cust[b]; });
+  // items grouped by design point for the per-dp reductions
+  std::stable_sort(index.begin(), index.end(), [&](uint32_t a, uint32_t b) { return dp[a] < dp[b]; });
+  std::vector<uint64_t> offsets;
+  std::vector<uint32_t> ids;
+  for (uint64_t j = 0; j < n; ++j) {
+    if (j == 0 || dp[index[j]] != dp[index[j - 1]]) {
+      offsets.push_back(j);
+      ids.push_back(dp[index[j]]);
+    }
+  }
+  offsets.push_back(n);
+  HIP_TRY(ctx, ctx->it_dp.ensure(4 * n));
+  HIP_TRY(ctx, ctx->it_rep.ensure(4 * n));
+  HIP_TRY(ctx, ctx->it_n.ensure(8 * n));
+  HIP_TRY(ctx, ctx->it_lambda.ensure(4 * n));
+  HIP_TRY(ctx, ctx->it_mu.ensure(4 * n));
+  HIP_TRY(ctx, ctx->it_order.ensure(4 * n));
+  HIP_TRY(ctx, ctx->dp_index.ensure(4 * n));
+  HIP_TRY(ctx, ctx->dp_offsets.ensure(8 * offsets.size()));
+  HIP_TRY(ctx, ctx->dp_stats.ensure(sizeof(double) * 3 * ids.size()));
+  HIP_TRY(ctx, ctx->queue.ensure(256));
+  HIP_TRY(ctx, hipMemcpy(ctx->it_dp.p, dp.data(), 4 * n, hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->it_rep.p, rep.data(), 4 * n, hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->it_n.p, cust.data(), 8 * n, hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->it_lambda.p, lam.data(), 4 * n, hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->it_mu.p, mu.data(), 4 * n, hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->it_order.p, order.data(), 4 * n, hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->dp_index.p, index.data(), 4 * n, hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(ctx->dp_offsets.p, offsets.data(), 8 * offsets.size(), hipMemcpyHostToDevice));
+  ctx->n_items = n;
+  ctx->dp_ids = ids;
+  return MRIP_OK;
+}
+
+static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, const uint32_t *order,
+                                 uint64_t n, uint32_t rpw, uint32_t wg, bool reduce) {
+  mrip_status st = ensure_events(ctx);
+  if (st != MRIP_OK) return st;
+  for (uint32_t o = 0; o < 3; ++o) HIP_TRY(ctx, ctx->out[o].ensure(ctx->n_items * 4));
+  HIP_TRY(ctx, ctx->stats.ensure(sizeof(double) * 3 * 4));
+  Mm1Args a{};
+  a.seed = seed;
+  a.feature_prefix = ctx->mm1.feature_prefix;
+  if (a.feature_prefix > 0) {
+    HIP_TRY(ctx, ctx->out[3].ensure(ctx->n_items * 40));
+    a.features = ctx->out[3].as<float>();
+  }
+  a.items.dp = ctx->it_dp.as<uint32_t>();
+  a.items.rep = ctx->it_rep.as<uint32_t>();
+  a.items.customers = ctx->it_n.as<uint64_t>();
+  a.items.lambda = ctx->it_lambda.as<float>();
+  a.items.mu = ctx->it_mu.as<float>();
+  a.items.order = order;
+  a.queue_head = ctx->queue.as<uint32_t>();
+  a.mean_w = ctx->out[0].as<float>();
+  a.mean_t = ctx->out[1].as<float>();
+  a.mean_i = ctx->out[2].as<float>();
+  HIP_TRY(ctx, launch_zero_u32(a.queue_head, 1, s));
+  st = record_begin(ctx, s);
+  if (st != MRIP_OK) return st;
+  HIP_TRY(ctx, launch_mm1_plan(a, n, rpw, wg, s));
+  st = record_end(ctx, s);
+  if (st != MRIP_OK) return st;
+  if (reduce) {
+    HIP_TRY(ctx, launch_reduce_f64_gather(ctx->out[0].p, 1, ctx->dp_index.as<uint32_t>(),
+                                          ctx->dp_offsets.as<uint64_t>(), (uint32_t)ctx->dp_ids.size(),
+                                          ctx->dp_stats.as<double>(), s));
+    for (uint32_t o = 0; o < 3; ++o)
+      HIP_TRY(ctx, launch_reduce_f64(ctx->out[o].p, 1, ctx->n_items, nullptr, 1,
+                                     ctx->stats.as<double>() + 3 * o, s));
+  }
+  ctx->last_stream = s;
+  return MRIP_OK;
+}
+
+mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
+  if (ctx->mapping != MRIP_MAP_WAVE)
+    return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
+  mrip_status st = run_plan_impl(ctx, seed, (hipStream_t)hip_stream, ctx->it_order.as<uint32_t>(),
+                                 ctx->n_items, ctx->rpw, ctx->wg, true);
+  if (st != MRIP_OK) return st;
+  ctx->last = RUN_PLAN;
+  ctx->last_n = ctx->n_items;
+  return MRIP_OK;
+}
+
+mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_stats_t *out) {
+  if (!ctx || !out) return MRIP_E_INVAL;
+  if (!(confidence > 0.0 && confidence < 1.0)) return inval(ctx, "confidence must be in (0, 1)");
+  if (ctx->last != RUN_PLAN) return (ctx->err = "no plan run yet"), MRIP_E_STATE;
+  auto it = std::lower_bound(ctx->dp_ids.begin(), ctx->dp_ids.end(), dp);
+  if (it == ctx->dp_ids.end() || *it != dp) return inval(ctx, "no such design point");
+  const size_t g = (size_t)(it - ctx->dp_ids.begin());
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  double nmv[3];
+  HIP_TRY(ctx, hipMemcpy(nmv, ctx->dp_stats.as<double>() + 3 * g, sizeof(nmv), hipMemcpyDeviceToHost));
+  mrip_status st = finish_stats(nmv, confidence, out);
+  if (st == MRIP_E_TOO_FEW) ctx->err = "fewer than two replications";
+  return st;
+}
+
+mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, void *hip_stream,
+                          uint32_t *best_rpw, uint32_t *best_wg, float *best_ms) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
+  if (ctx->mapping != MRIP_MAP_WAVE)
+    return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const uint32_t *order = ctx->it_order.as<uint32_t>();
+  uint64_t n = ctx->n_items;
+  DevBuf sub;
+  if (calib_items > 0 && calib_items < ctx->n_items) {
+    // an evenly strided slice of the longest-first order keeps its length mix
+    std::vector<uint32_t> full(ctx->n_items), pick;
+    HIP_TRY(ctx, hipMemcpy(full.data(), order, 4 * ctx->n_items, hipMemcpyDeviceToHost));
+    const double stride = (double)ctx->n_items / (double)calib_items;
+    for (uint64_t j = 0; j < calib_items; ++j) pick.push_back(full[(uint64_t)(j * stride)]);
+    HIP_TRY(ctx, sub.ensure(4 * pick.size()));
+    HIP_TRY(ctx, hipMemcpy(sub.p, pick.data(), 4 * pick.size(), hipMemcpyHostToDevice));
+    order = sub.as<uint32_t>();
+    n = pick.size();
+  }
+  const uint32_t rpws[3] = {1, 2, 4}, wgs[3] = {64, 256, 1024};
+  float best = 1e30f;
+  uint32_t br = ctx->rpw, bw = ctx->wg;
+  for (uint32_t r : rpws) {
+    for (uint32_t w : wgs) {
+      float t_min = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {  // first launch warms up
+        mrip_status st = run_plan_impl(ctx, seed, s, order, n, r, w, false);
+        if (st != MRIP_OK) return st;
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        if (rep > 0) t_min = std::min(t_min, ms);
+      }
+      if (t_min < best) {
+        best = t_min;
+        br = r;
+        bw = w;
+      }
+    }
+  }
+  ctx->rpw = br;
+  ctx->wg = bw;
+  ctx->last = RUN_NONE;  // outputs of the timing runs are partial
+  if (best_rpw) *best_rpw = br;
+  if (best_wg) *best_wg = bw;
+  if (best_ms) *best_ms = best;
+  return MRIP_OK;
+}
+
+// ------------------------------------------------------------- utilities
+
+mrip_status mrip_philox(uint64_t seed, const uint32_t *ctr_dev, uint64_t n, uint32_t *out_dev,
+                        void *hip_stream) {
+  if (n > 0 && (!ctr_dev || !out_dev)) return MRIP_E_INVAL;
+  hipError_t e = launch_philox_dump(seed, ctr_dev, n, out_dev, (hipStream_t)hip_stream);
+  return e == hipSuccess ? MRIP_OK : MRIP_E_HIP;
+}
+
+}  // extern "C"
+

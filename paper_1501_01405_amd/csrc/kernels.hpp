@@ -1,0 +1,76 @@
+// Host-side launchers of the MRIP kernels (one .hip file per model). Every
+// launcher only enqueues on `stream`; shapes are validated by the caller
+// (api.cpp) before any launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrip {
+
+// ------------------------------------------------------------ random walk
+struct RwArgs {
+  uint64_t seed;
+  uint32_t walkers, grid, steps;
+  uint64_t n_reps;
+  int32_t *ssd, *distinct;
+  uint32_t *scratch_bitmaps;  // SIMT only: n_reps * grid*grid/32 words
+};
+hipError_t launch_rw_wave(const RwArgs &a, uint32_t workgroup, hipStream_t s);
+hipError_t launch_rw_simt(const RwArgs &a, hipStream_t s);
+
+// ------------------------------------------------------------ M/M/1
+// Per-item parameters in structure-of-arrays form on the device.
+struct Mm1Items {
+  const uint32_t *dp, *rep;
+  const uint64_t *customers;
+  const float *lambda, *mu;
+  const uint32_t *order;  // queue order (longest first); index into the arrays
+};
+struct Mm1Args {
+  uint64_t seed;
+  uint64_t n_reps;              // uniform mode: replications 0..n_reps-1
+  float lambda, mu;             // uniform mode
+  uint64_t customers;           // uniform mode
+  uint64_t feature_prefix;      // K (0 = no features)
+  Mm1Items items;               // plan mode (items.dp != nullptr)
+  uint32_t *queue_head;         // plan mode: device counter, zero at launch
+  float *mean_w, *mean_t, *mean_i;
+  float *features;              // n x 10 when feature_prefix > 0
+};
+hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t reps_per_wave, uint32_t workgroup,
+                           hipStream_t s);
+hipError_t launch_mm1_simt(const Mm1Args &a, hipStream_t s);
+// Persistent plan kernel: grid sized to full residency, waves pop work.
+hipError_t launch_mm1_plan(const Mm1Args &a, uint64_t n_items, uint32_t reps_per_wave,
+                           uint32_t workgroup, hipStream_t s);
+// Zero the queue head with a one-thread kernel (no memset node in graphs).
+hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s);
+
+// ------------------------------------------------------------ forest fire
+struct FfArgs {
+  uint64_t seed;
+  uint32_t grid, steps;
+  uint32_t tp, tf;  // integer thresholds for growth and lightning
+  uint64_t n_reps;
+  int32_t *burnt;
+  uint32_t *state;  // SIMT only: 2 planes * grid rows * grid/32 words * n_reps
+};
+hipError_t launch_ff_wave(const FfArgs &a, uint32_t workgroup, hipStream_t s);
+hipError_t launch_ff_simt(const FfArgs &a, hipStream_t s);
+
+// ------------------------------------------------------------ reductions
+// out[3*g + {0,1,2}] = (n, mean, unbiased var) in fp64 over segment g of x;
+// segment g is x[offsets[g] .. offsets[g+1]) (offsets nullptr: one segment
+// of n values). dtype 0 = int32, 1 = fp32.
+hipError_t launch_reduce_f64(const void *x, int dtype, uint64_t n, const uint64_t *offsets,
+                             uint32_t n_segments, double *out, hipStream_t s);
+// Gathered variant: segment g reads x[index[offsets[g] .. offsets[g+1])].
+hipError_t launch_reduce_f64_gather(const void *x, int dtype, const uint32_t *index,
+                                    const uint64_t *offsets, uint32_t n_segments, double *out,
+                                    hipStream_t s);
+
+// ------------------------------------------------------------ utilities
+hipError_t launch_philox_dump(uint64_t seed, const uint32_t *ctr, uint64_t n, uint32_t *out,
+                              hipStream_t s);
+
+}  // namespace mrip

@@ -1,0 +1,152 @@
+// Lattice random-walk replication engines (paper section 5.1, third model).
+//
+// WAVE mapping: one replication per wavefront, lane w = walker w. The
+// replication's visited-site bitmap (grid^2 bits, 512 B at 64x64) lives in
+// LDS and every move sets its bit with an LDS atomic or; at the end the
+// lanes popcount the bitmap and sum squared displacements across the wave.
+//
+// SIMT mapping: one replication per lane; the lane walks its walkers one
+// after the other and keeps the replication's bitmap in global memory, the
+// per-thread state the paper's thread-per-replication form implies.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace mrip {
+
+namespace {
+
+__device__ __forceinline__ void step_delta(uint32_t d, int &dx, int &dy) {
+  dx = (d == 0u) - (d == 1u);
+  dy = (d == 2u) - (d == 3u);
+}
+
+template <int GRID>
+__global__ void rw_wave_kernel(RwArgs a) {
+  constexpr int WORDS = GRID * GRID / 32;
+  extern __shared__ uint32_t lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t r = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  uint32_t *bm = lds + wave * WORDS;
+  for (int i = lane; i < WORDS; i += 64) bm[i] = 0u;
+  __syncthreads();
+
+  const bool active = r < a.n_reps && (uint32_t)lane < a.walkers;
+  const uint32_t w = (uint32_t)lane;
+  int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
+  int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
+  int ux = 0, uy = 0;
+  if (active) atomicOr(&bm[(y * GRID + x) >> 5], 1u << (x & 31));
+
+  for (uint32_t g = 0; g < a.steps; g += 64) {
+    const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
+    const uint32_t words[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t word = words[j];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (g + 16u * j + i >= a.steps) break;
+        int dx, dy;
+        step_delta(word & 3u, dx, dy);
+        word >>= 2;
+        ux += dx;
+        uy += dy;
+        x = (x + dx) & (GRID - 1);
+        y = (y + dy) & (GRID - 1);
+        if (active) atomicOr(&bm[(y * GRID + x) >> 5], 1u << (x & 31));
+      }
+    }
+  }
+  __syncthreads();
+  int cnt = 0;
+  for (int i = lane; i < WORDS; i += 64) cnt += __popc(bm[i]);
+  cnt = group_sum_i(cnt, 64);
+  const int sd = active ? ux * ux + uy * uy : 0;
+  const int ssd = group_sum_i(sd, 64);
+  if (lane == 0 && r < a.n_reps) {
+    a.ssd[r] = ssd;
+    a.distinct[r] = cnt;
+  }
+}
+
+template <int GRID>
+__global__ void rw_simt_kernel(RwArgs a) {
+  constexpr int WORDS = GRID * GRID / 32;
+  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n_reps) return;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  uint32_t *bm = a.scratch_bitmaps + r * WORDS;
+  for (int i = 0; i < WORDS; ++i) bm[i] = 0u;
+  int ssd = 0;
+  for (uint32_t w = 0; w < a.walkers; ++w) {
+    int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
+    int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
+    int ux = 0, uy = 0;
+    bm[(y * GRID + x) >> 5] |= 1u << (x & 31);
+    for (uint32_t g = 0; g < a.steps; g += 64) {
+      const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
+      const uint32_t words[4] = {b.x, b.y, b.z, b.w};
+      for (int j = 0; j < 4; ++j) {
+        uint32_t word = words[j];
+        for (int i = 0; i < 16; ++i) {
+          if (g + 16u * j + i >= a.steps) break;
+          int dx, dy;
+          step_delta(word & 3u, dx, dy);
+          word >>= 2;
+          ux += dx;
+          uy += dy;
+          x = (x + dx) & (GRID - 1);
+          y = (y + dy) & (GRID - 1);
+          bm[(y * GRID + x) >> 5] |= 1u << (x & 31);
+        }
+      }
+    }
+    ssd += ux * ux + uy * uy;
+  }
+  int cnt = 0;
+  for (int i = 0; i < WORDS; ++i) cnt += __popc(bm[i]);
+  a.ssd[r] = ssd;
+  a.distinct[r] = cnt;
+}
+
+template <int GRID>
+hipError_t wave_launch(const RwArgs &a, uint32_t wg, hipStream_t s) {
+  const uint32_t wpb = wg / 64;
+  const uint64_t blocks = (a.n_reps + wpb - 1) / wpb;
+  const size_t lds = (size_t)wpb * (GRID * GRID / 32) * sizeof(uint32_t);
+  hipLaunchKernelGGL(rw_wave_kernel<GRID>, dim3((uint32_t)blocks), dim3(wg), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int GRID>
+hipError_t simt_launch(const RwArgs &a, hipStream_t s) {
+  const uint32_t wg = 64;
+  const uint64_t blocks = (a.n_reps + wg - 1) / wg;
+  hipLaunchKernelGGL(rw_simt_kernel<GRID>, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rw_wave(const RwArgs &a, uint32_t wg, hipStream_t s) {
+  switch (a.grid) {
+    case 16: return wave_launch<16>(a, wg, s);
+    case 32: return wave_launch<32>(a, wg, s);
+    case 64: return wave_launch<64>(a, wg, s);
+    case 128: return wave_launch<128>(a, wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rw_simt(const RwArgs &a, hipStream_t s) {
+  switch (a.grid) {
+    case 16: return simt_launch<16>(a, s);
+    case 32: return simt_launch<32>(a, s);
+    case 64: return simt_launch<64>(a, s);
+    case 128: return simt_launch<128>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mrip

@@ -1,0 +1,358 @@
+"""ctypes binding of libmrip.so (include/mrip.h), same names as the C ABI.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. Device buffers passed in or out are torch CUDA tensors (PyTorch
+provides device memory and streams, nothing else). There is no fallback:
+if the library is missing, `load()` raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmrip.so")
+
+MRIP_OK, MRIP_E_INVAL, MRIP_E_NOMEM, MRIP_E_HIP, MRIP_E_STATE, MRIP_E_TOO_FEW, \
+    MRIP_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MRIP_RW, MRIP_MM1, MRIP_FF = 1, 2, 3
+MRIP_MAP_AUTO, MRIP_MAP_SIMT, MRIP_MAP_WAVE = 0, 1, 2
+MRIP_MLP_PARAMS = 18049
+
+
+class mrip_rw_params(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("walkers", C.c_uint32), ("grid", C.c_uint32),
+                ("steps", C.c_uint32)]
+
+
+class mrip_mm1_params(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("lambda_", C.c_float), ("mu", C.c_float),
+                ("customers", C.c_uint64), ("feature_prefix", C.c_uint64)]
+
+
+class mrip_ff_params(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("grid", C.c_uint32), ("steps", C.c_uint32),
+                ("p_grow", C.c_double), ("f_light", C.c_double)]
+
+
+class mrip_stats_t(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("mean", C.c_double), ("var", C.c_double),
+                ("half_width", C.c_double), ("t_quantile", C.c_double),
+                ("confidence", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class mrip_plan_item(C.Structure):
+    _fields_ = [("dp", C.c_uint32), ("rep", C.c_uint32), ("customers", C.c_uint64),
+                ("lambda_", C.c_float), ("mu", C.c_float)]
+
+
+class mrip_cv_hparams(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("epochs", C.c_uint32), ("batch", C.c_uint32),
+                ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+PLAN_ITEM_DTYPE = np.dtype([("dp", "<u4"), ("rep", "<u4"), ("customers", "<u8"),
+                            ("lambda_", "<f4"), ("mu", "<f4")])
+assert PLAN_ITEM_DTYPE.itemsize == C.sizeof(mrip_plan_item)
+
+ctx_t = C.c_void_p
+vp = C.c_void_p
+u32, u64, f32, f64 = C.c_uint32, C.c_uint64, C.c_float, C.c_double
+st = C.c_int
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "mrip_create": (st, [C.POINTER(ctx_t), C.c_int, vp, C.c_int]),
+    "mrip_destroy": (None, [ctx_t]),
+    "mrip_set_shape": (st, [ctx_t, u32, u32]),
+    "mrip_run": (st, [ctx_t, u64, u64, vp]),
+    "mrip_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t)]),
+    "mrip_outputs": (st, [ctx_t, u32, vp, u64, C.c_int]),
+    "mrip_output_ptr": (st, [ctx_t, u32, C.POINTER(vp)]),
+    "mrip_last_run_ms": (st, [ctx_t, C.POINTER(f32)]),
+    "mrip_run_history_ms": (st, [ctx_t, C.POINTER(f32), u32, C.POINTER(u32)]),
+    "mrip_plan_set": (st, [ctx_t, vp, u64]),
+    "mrip_run_plan": (st, [ctx_t, u64, vp]),
+    "mrip_plan_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t)]),
+    "mrip_autotune": (st, [ctx_t, u64, u64, vp, C.POINTER(u32), C.POINTER(u32),
+                           C.POINTER(f32)]),
+    "mrip_mlp_forward": (st, [vp, vp, u64, vp, vp]),
+    "mrip_mlp_grad": (st, [vp, vp, vp, u64, vp, vp, vp]),
+    "mrip_adam_step": (st, [vp, vp, vp, vp, u64, u64, f32, f32, f32, f32, vp]),
+    "mrip_cv_train": (st, [ctx_t, vp, u64, vp, C.POINTER(mrip_cv_hparams), u64, vp]),
+    "mrip_cv_model": (st, [ctx_t, vp, vp, vp, vp]),
+    "mrip_cv_apply": (st, [ctx_t, vp, u64, vp, u64, u64, vp]),
+    "mrip_cv_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t),
+                           C.POINTER(mrip_stats_t)]),
+    "mrip_cv_times": (st, [ctx_t, C.POINTER(f32), C.POINTER(f32), C.POINTER(f32)]),
+    "mrip_philox": (st, [u64, vp, u64, vp, vp]),
+    "mrip_t_quantile": (f64, [f64, f64]),
+    "mrip_status_string": (C.c_char_p, [C.c_int]),
+    "mrip_last_error": (C.c_char_p, [ctx_t]),
+    "mrip_version": (C.c_char_p, []),
+}
+
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+class MripError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__("%s (%d)%s" % (_status_name(status), status, ": " + msg if msg else ""))
+
+
+def _status_name(s):
+    try:
+        return load().mrip_status_string(s).decode()
+    except Exception:  # noqa: BLE001 - only used to format an error
+        return "status"
+
+
+def load():
+    """Load libmrip.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmrip.so is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status, ctx=None):
+    if status != MRIP_OK:
+        msg = load().mrip_last_error(ctx).decode() if ctx else ""
+        raise MripError(status, msg)
+    return status
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor or numpy array, or None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+def current_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ----------------------------------------------------------- raw C-ABI calls
+def mrip_create(model, params, mapping=MRIP_MAP_AUTO):
+    ctx = ctx_t()
+    check(load().mrip_create(C.byref(ctx), model, C.byref(params), mapping))
+    return ctx
+
+
+def mrip_destroy(ctx):
+    load().mrip_destroy(ctx)
+
+
+def mrip_set_shape(ctx, reps_per_wave, workgroup):
+    check(load().mrip_set_shape(ctx, reps_per_wave, workgroup), ctx)
+
+
+def mrip_run(ctx, n_reps, seed, stream=None):
+    check(load().mrip_run(ctx, n_reps, seed, stream), ctx)
+
+
+def mrip_stats(ctx, output=0, confidence=0.95):
+    s = mrip_stats_t()
+    check(load().mrip_stats(ctx, output, confidence, C.byref(s)), ctx)
+    return s.as_dict()
+
+
+def mrip_outputs(ctx, output, dst, dst_is_device):
+    nbytes = dst.numel() * dst.element_size() if hasattr(dst, "numel") else dst.nbytes
+    check(load().mrip_outputs(ctx, output, _ptr(dst), nbytes, int(dst_is_device)), ctx)
+    return dst
+
+
+def mrip_last_run_ms(ctx):
+    ms = f32()
+    check(load().mrip_last_run_ms(ctx, C.byref(ms)), ctx)
+    return ms.value
+
+
+def mrip_run_history_ms(ctx, max_n=256):
+    buf = (f32 * max_n)()
+    n = u32()
+    check(load().mrip_run_history_ms(ctx, buf, max_n, C.byref(n)), ctx)
+    return [buf[i] for i in range(n.value)]
+
+
+def mrip_plan_set(ctx, items):
+    items = np.ascontiguousarray(items, dtype=PLAN_ITEM_DTYPE)
+    check(load().mrip_plan_set(ctx, items.ctypes.data, items.shape[0]), ctx)
+
+
+def mrip_run_plan(ctx, seed, stream=None):
+    check(load().mrip_run_plan(ctx, seed, stream), ctx)
+
+
+def mrip_plan_stats(ctx, dp, confidence=0.95):
+    s = mrip_stats_t()
+    check(load().mrip_plan_stats(ctx, dp, confidence, C.byref(s)), ctx)
+    return s.as_dict()
+
+
+def mrip_autotune(ctx, seed, calib_items=0, stream=None):
+    r, w, ms = u32(), u32(), f32()
+    check(load().mrip_autotune(ctx, seed, calib_items, stream, C.byref(r), C.byref(w),
+                               C.byref(ms)), ctx)
+    return r.value, w.value, ms.value
+
+
+def mrip_mlp_forward(theta, x, n, y, stream=None):
+    check(load().mrip_mlp_forward(_ptr(theta), _ptr(x), n, _ptr(y), stream))
+
+
+def mrip_mlp_grad(theta, x, y, n, grad, loss=None, stream=None):
+    check(load().mrip_mlp_grad(_ptr(theta), _ptr(x), _ptr(y), n, _ptr(grad), _ptr(loss),
+                               stream))
+
+
+def mrip_adam_step(theta, m, v, grad, n_params, step, lr=1e-3, beta1=0.9, beta2=0.999,
+                   eps=1e-8, stream=None):
+    check(load().mrip_adam_step(_ptr(theta), _ptr(m), _ptr(v), _ptr(grad), n_params, step, lr,
+                                beta1, beta2, eps, stream))
+
+
+def mrip_cv_train(ctx, items, theta0, hparams=None, seed=42, stream=None):
+    items = np.ascontiguousarray(items, dtype=PLAN_ITEM_DTYPE)
+    theta0 = np.ascontiguousarray(theta0, dtype=np.float32)
+    assert theta0.shape == (MRIP_MLP_PARAMS,)
+    hp = C.byref(hparams) if hparams is not None else None
+    check(load().mrip_cv_train(ctx, items.ctypes.data, items.shape[0], theta0.ctypes.data, hp,
+                               seed, stream), ctx)
+
+
+def mrip_cv_model(ctx):
+    theta = np.zeros(MRIP_MLP_PARAMS, np.float32)
+    mean = np.zeros(10, np.float32)
+    std = np.zeros(10, np.float32)
+    loss = f32()
+    check(load().mrip_cv_model(ctx, theta.ctypes.data, mean.ctypes.data, std.ctypes.data,
+                               C.byref(loss)), ctx)
+    return theta, mean, std, loss.value
+
+
+def mrip_cv_apply(ctx, full, prefix, seed=42, stream=None):
+    full = np.ascontiguousarray(full, dtype=PLAN_ITEM_DTYPE)
+    prefix = np.ascontiguousarray(prefix, dtype=PLAN_ITEM_DTYPE)
+    check(load().mrip_cv_apply(ctx, full.ctypes.data, full.shape[0], prefix.ctypes.data,
+                               prefix.shape[0], seed, stream), ctx)
+
+
+def mrip_cv_stats(ctx, dp, confidence=0.95):
+    a, b = mrip_stats_t(), mrip_stats_t()
+    check(load().mrip_cv_stats(ctx, dp, confidence, C.byref(a), C.byref(b)), ctx)
+    return a.as_dict(), b.as_dict()
+
+
+def mrip_cv_times(ctx):
+    a, b, c = f32(), f32(), f32()
+    check(load().mrip_cv_times(ctx, C.byref(a), C.byref(b), C.byref(c)), ctx)
+    return a.value, b.value, c.value
+
+
+def mrip_philox(seed, ctr, n, out, stream=None):
+    check(load().mrip_philox(seed, _ptr(ctr), n, _ptr(out), stream))
+
+
+def mrip_t_quantile(p, dof):
+    return load().mrip_t_quantile(p, dof)
+
+
+# ------------------------------------------------------------ convenience
+def rw_params(walkers=64, grid=64, steps=1000):
+    return mrip_rw_params(C.sizeof(mrip_rw_params), walkers, grid, steps)
+
+
+def mm1_params(lam=0.9, mu=1.0, customers=100000, feature_prefix=0):
+    return mrip_mm1_params(C.sizeof(mrip_mm1_params), lam, mu, customers, feature_prefix)
+
+
+def ff_params(grid=128, steps=2000, p_grow=0.01, f_light=1e-5):
+    return mrip_ff_params(C.sizeof(mrip_ff_params), grid, steps, p_grow, f_light)
+
+
+def cv_hparams(epochs=20, batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    return mrip_cv_hparams(C.sizeof(mrip_cv_hparams), epochs, batch, lr, beta1, beta2, eps)
+
+
+_OUT_DTYPES = {MRIP_RW: ("int32", "int32"), MRIP_MM1: ("float32",) * 3,
+               MRIP_FF: ("int32",)}
+
+
+class Context:
+    """An owned mrip_ctx; outputs come back as torch tensors on the device."""
+
+    def __init__(self, model, params, mapping=MRIP_MAP_AUTO):
+        self.model = model
+        self.params = params
+        self.ctx = mrip_create(model, params, mapping)
+        self.n = 0
+
+    def close(self):
+        if self.ctx:
+            mrip_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def set_shape(self, reps_per_wave, workgroup):
+        mrip_set_shape(self.ctx, reps_per_wave, workgroup)
+
+    def run(self, n_reps, seed=42, stream=None):
+        mrip_run(self.ctx, n_reps, seed, current_stream() if stream is None else stream)
+        self.n = n_reps
+
+    def stats(self, output=0, confidence=0.95):
+        return mrip_stats(self.ctx, output, confidence)
+
+    def output(self, output=0, n=None):
+        import torch
+        n = self.n if n is None else n
+        if self.model == MRIP_MM1 and output == 3:
+            t = torch.empty((n, 10), dtype=torch.float32, device="cuda")
+        else:
+            dt = getattr(torch, _OUT_DTYPES[self.model][output])
+            t = torch.empty(n, dtype=dt, device="cuda")
+        return mrip_outputs(self.ctx, output, t, True)
+
+    def last_ms(self):
+        return mrip_last_run_ms(self.ctx)
+
+    def history_ms(self, max_n=256):
+        return mrip_run_history_ms(self.ctx, max_n)
+
+    def plan_set(self, items):
+        mrip_plan_set(self.ctx, items)
+        self.n = len(items)
+
+    def run_plan(self, seed=42, stream=None):
+        mrip_run_plan(self.ctx, seed, current_stream() if stream is None else stream)
+
+    def plan_stats(self, dp, confidence=0.95):
+        return mrip_plan_stats(self.ctx, dp, confidence)
+
+    def autotune(self, seed=42, calib_items=0):
+        return mrip_autotune(self.ctx, seed, calib_items, current_stream())

@@ -1,0 +1,97 @@
+"""The C-ABI library loads, exports every symbol include/mrip.h declares,
+and its host-side logic (argument checks, Student-t quantile) behaves; no
+GPU needed (no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+import scipy.stats
+
+from paper_1501_01405_amd import mrip
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mrip.h")).read()
+    return sorted(set(re.findall(r"^MRIP_API [^;]*?\b(mrip_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = mrip.load()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(mrip.EXPORTED) == names
+
+
+def test_version_and_status_strings():
+    L = mrip.load()
+    assert b"gfx950" in L.mrip_version()
+    assert L.mrip_status_string(mrip.MRIP_E_TOO_FEW) == b"fewer than two replications"
+
+
+@pytest.mark.parametrize("dof", [1, 2, 5, 31, 1023, 2047, 100000])
+@pytest.mark.parametrize("p", [0.95, 0.975, 0.995])
+def test_t_quantile_matches_scipy(dof, p):
+    # scipy's own ppf is accurate to ~1e-10 relative (it is off by 2e-11 at
+    # dof 1, where the closed form is known); the closed forms are pinned below
+    q = mrip.mrip_t_quantile(p, dof)
+    assert abs(q - scipy.stats.t.ppf(p, dof)) <= 1e-9 * max(1.0, q)
+
+
+def test_t_quantile_closed_forms():
+    import math
+    for p in (0.8, 0.95, 0.975, 0.995):
+        assert abs(mrip.mrip_t_quantile(p, 1) - math.tan(math.pi * (p - 0.5))) < 1e-13 * 100
+        a = 4 * p * (1 - p)
+        assert abs(mrip.mrip_t_quantile(p, 2) - (2 * p - 1) * math.sqrt(2 / a)) < 1e-13 * 10
+    assert mrip.mrip_t_quantile(0.5, 7) == 0.0
+    assert math.isnan(mrip.mrip_t_quantile(0.4, 7))
+
+
+def _create(model, params, mapping=mrip.MRIP_MAP_AUTO):
+    ctx = mrip.ctx_t()
+    rc = mrip.load().mrip_create(C.byref(ctx), model, C.byref(params), mapping)
+    if rc == mrip.MRIP_OK:
+        mrip.load().mrip_destroy(ctx)
+    return rc
+
+
+def test_parameter_validation():
+    ok = mrip.MRIP_OK
+    bad = mrip.MRIP_E_INVAL
+    assert _create(mrip.MRIP_RW, mrip.rw_params()) == ok
+    assert _create(mrip.MRIP_RW, mrip.rw_params(walkers=65)) == bad
+    assert _create(mrip.MRIP_RW, mrip.rw_params(grid=48)) == bad
+    assert _create(mrip.MRIP_RW, mrip.rw_params(steps=10**5)) == bad
+    assert _create(mrip.MRIP_MM1, mrip.mm1_params()) == ok
+    assert _create(mrip.MRIP_MM1, mrip.mm1_params(lam=0.0)) == bad
+    assert _create(mrip.MRIP_MM1, mrip.mm1_params(customers=0)) == bad
+    assert _create(mrip.MRIP_MM1, mrip.mm1_params(customers=10, feature_prefix=11)) == bad
+    assert _create(mrip.MRIP_FF, mrip.ff_params()) == ok
+    assert _create(mrip.MRIP_FF, mrip.ff_params(grid=96), mrip.MRIP_MAP_WAVE) == bad
+    assert _create(mrip.MRIP_FF, mrip.ff_params(grid=96), mrip.MRIP_MAP_SIMT) == ok
+    assert _create(mrip.MRIP_FF, mrip.ff_params(p_grow=1.5)) == bad
+    p = mrip.rw_params()
+    p.size = 4
+    assert _create(mrip.MRIP_RW, p) == bad
+    assert _create(7, mrip.rw_params()) == bad
+
+
+def test_calls_out_of_order_and_bad_shapes():
+    L = mrip.load()
+    ctx = mrip.ctx_t()
+    assert L.mrip_create(C.byref(ctx), mrip.MRIP_MM1, C.byref(mrip.mm1_params()), 0) == 0
+    s = mrip.mrip_stats_t()
+    assert L.mrip_stats(ctx, 0, 0.95, C.byref(s)) == mrip.MRIP_E_STATE
+    assert L.mrip_run(ctx, 0, 42, None) == mrip.MRIP_E_INVAL
+    assert L.mrip_set_shape(ctx, 3, 256) == mrip.MRIP_E_INVAL
+    assert L.mrip_set_shape(ctx, 2, 128) == mrip.MRIP_E_INVAL
+    assert L.mrip_set_shape(ctx, 4, 1024) == mrip.MRIP_OK
+    assert L.mrip_run_plan(ctx, 42, None) == mrip.MRIP_E_STATE
+    assert L.mrip_plan_stats(ctx, 0, 0.95, C.byref(s)) == mrip.MRIP_E_STATE
+    assert b"no" in L.mrip_last_error(ctx)
+    L.mrip_destroy(ctx)

@@ -1,0 +1,96 @@
+"""GPU parity of the M/M/1 engines against the oracle: fp32 per-replication
+means within 1e-5 relative (abs floor 1e-6), both mappings and every WAVE
+launch shape, ragged run lengths, features, and the full 1024 x 1e5
+configuration on sampled replications."""
+import numpy as np
+import pytest
+
+from gpu_util import SIMT, WAVE, announce, rel_err
+from oracle import core
+from oracle import stats as ostats
+from paper_1501_01405_amd import mrip
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+SHAPES = [(SIMT, 1, 64), (WAVE, 1, 256), (WAVE, 2, 64), (WAVE, 4, 1024), (WAVE, 1, 1024)]
+RUNS = [(1, 3, 0.9), (2, 5, 0.9), (31, 7, 0.5), (33, 9, 0.9), (129, 5, 0.7), (1000, 40, 0.95),
+        (12345, 16, 0.9)]
+
+
+def _run(mapping, rpw, wg, lam, N, R, seed=42, K=0):
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(lam, 1.0, N, K), mapping)
+    if mapping == WAVE:
+        ctx.set_shape(rpw, wg)
+    ctx.run(R, seed=seed)
+    outs = np.stack([ctx.output(o).cpu().numpy() for o in range(3)], axis=1)
+    feat = ctx.output(3).cpu().numpy() if K else None
+    return ctx, outs, feat
+
+
+@pytest.mark.parametrize("mapping,rpw,wg", SHAPES)
+@pytest.mark.parametrize("N,R,lam", RUNS)
+def test_mm1_matches_oracle(gpu, mapping, rpw, wg, N, R, lam):
+    announce("mm1", mapping, rpw, wg, N, R, lam)
+    _, outs, _ = _run(mapping, rpw, wg, lam, N, R)
+    ref = core.mm1_many(42, R, N, lam, 1.0, threads=core.default_threads())
+    assert rel_err(outs, ref).max() <= TOL
+
+
+@pytest.mark.parametrize("mapping,rpw,wg", [(SIMT, 1, 64), (WAVE, 1, 256), (WAVE, 4, 256)])
+def test_mm1_features(gpu, mapping, rpw, wg):
+    announce("mm1 features", mapping, rpw)
+    K, N, R = 1000, 5000, 24
+    _, outs, feat = _run(mapping, rpw, wg, 0.9, N, R, K=K)
+    ref, rfeat = core.mm1_many(42, R, N, 0.9, 1.0, features=K, threads=core.default_threads())
+    assert rel_err(outs, ref).max() <= TOL
+    cont = [0, 1, 2, 3, 4, 5, 7, 8, 9]
+    assert rel_err(feat[:, cont], rfeat[:, cont]).max() <= TOL
+    # the fraction of zero waits counts exact zeros: a wait within rounding
+    # of zero may flip, one customer at most here
+    assert np.abs(feat[:, 6] - rfeat[:, 6]).max() <= 2.0 / K
+
+
+def test_mm1_full_config_sampled(gpu):
+    # 1024 replications x 1e5 customers, lambda 0.9, mu 1 (WAVE, default shape)
+    announce("mm1 full config")
+    ctx, outs, _ = _run(WAVE, 1, 256, 0.9, 100000, 1024)
+    rng = np.random.default_rng(5)
+    ids = sorted(set([0, 1, 511, 1023] + list(rng.integers(0, 1024, 28))))
+    ref = core.mm1_many(42, ids, 100000, 0.9, 1.0, threads=core.default_threads())
+    assert rel_err(outs[ids], ref).max() <= TOL
+    s = ctx.stats(0)
+    e = ostats.summarize(outs[:, 0])
+    assert abs(s["mean"] - e["mean"]) <= 1e-12 * e["mean"]
+    assert abs(s["var"] - e["var"]) <= 1e-10 * e["var"]
+    # the closed form Wq = 9 (start-empty transient ~ -0.01)
+    assert abs(s["mean"] - 9.0) < 4 * s["half_width"] / 1.96 + 0.03
+
+
+def test_mm1_simt_full_config_sampled(gpu):
+    announce("mm1 simt full config")
+    _, outs, _ = _run(SIMT, 1, 64, 0.9, 100000, 1024)
+    ids = [0, 63, 64, 700, 1023]
+    ref = core.mm1_many(42, ids, 100000, 0.9, 1.0, threads=core.default_threads())
+    assert rel_err(outs[ids], ref).max() <= TOL
+
+
+def test_mm1_shape_invariance(gpu):
+    announce("mm1 shape invariance")
+    base = _run(WAVE, 1, 64, 0.9, 4321, 37)[1]
+    for rpw, wg in ((1, 256), (1, 1024)):
+        assert np.array_equal(_run(WAVE, rpw, wg, 0.9, 4321, 37)[1], base)
+    for rpw in (2, 4):
+        for wg in (64, 256, 1024):
+            got = _run(WAVE, rpw, wg, 0.9, 4321, 37)[1]
+            # same per-customer values; only the summation order differs
+            assert rel_err(got, base).max() <= 1e-6
+
+
+def test_mm1_prefix_and_repeat(gpu):
+    announce("mm1 prefix/repeat")
+    a = _run(WAVE, 1, 256, 0.9, 3000, 100)[1]
+    b = _run(WAVE, 1, 256, 0.9, 3000, 100)[1]
+    c = _run(WAVE, 1, 256, 0.9, 3000, 13)[1]
+    assert np.array_equal(a, b)
+    assert np.array_equal(a[:13], c)

@@ -1,0 +1,84 @@
+"""The persistent plan kernel against the oracle: every item within 1e-5 of
+its standalone oracle run, per-design-point statistics, item == standalone
+GPU run, and invariance over the autotuner's shapes."""
+import numpy as np
+import pytest
+
+from gpu_util import WAVE, announce, rel_err
+from oracle import core
+from oracle import stats as ostats
+from paper_1501_01405_amd import inputs, mrip
+
+pytestmark = pytest.mark.gpu
+
+
+def _items_tuple(items):
+    return [(int(i["dp"]), int(i["rep"]), int(i["customers"]), float(i["lambda_"]),
+             float(i["mu"])) for i in items]
+
+
+def _plan_ctx(items, rpw=1, wg=256):
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), WAVE)
+    ctx.set_shape(rpw, wg)
+    ctx.plan_set(items)
+    return ctx
+
+
+def test_plan_matches_oracle(gpu):
+    items = inputs.plan_table(n_dp=16, reps=8, n_lo=100, n_hi=20000, seed=1)
+    announce("plan", len(items))
+    ctx = _plan_ctx(items)
+    ctx.run_plan(42)
+    got = ctx.output(0, n=len(items)).cpu().numpy()
+    ref = core.mm1_items(42, _items_tuple(items), threads=core.default_threads())[:, 0]
+    assert rel_err(got, ref).max() <= 1e-5
+    for dp in range(16):
+        s = ctx.plan_stats(dp)
+        e = ostats.summarize(got[items["dp"] == dp])
+        assert s["n"] == 8
+        assert abs(s["mean"] - e["mean"]) <= 1e-12 * e["mean"]
+        assert abs(s["var"] - e["var"]) <= 1e-10 * e["var"]
+
+
+def test_plan_full_config_sampled(gpu):
+    items = inputs.plan_table()  # 64 dp x 32 reps, N log-uniform in [1e4, 1e6]
+    announce("plan full", len(items))
+    ctx = _plan_ctx(items)
+    ctx.run_plan(42)
+    got = ctx.output(0, n=len(items)).cpu().numpy()
+    rng = np.random.default_rng(3)
+    longest = int(np.argmax(items["customers"]))
+    ids = sorted(set([0, len(items) - 1, longest] + list(rng.integers(0, len(items), 13))))
+    ref = core.mm1_items(42, _items_tuple(items[ids]), threads=core.default_threads())[:, 0]
+    assert rel_err(got[ids], ref).max() <= 1e-5
+
+
+def test_plan_item_equals_standalone_run(gpu):
+    announce("plan item == standalone")
+    items = inputs.uniform_items(1, 40, 5000, [0.9])
+    ctx = _plan_ctx(items)
+    ctx.run_plan(42)
+    got = ctx.output(0, n=40).cpu().numpy()
+    solo = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 5000), WAVE)
+    solo.run(40, seed=42)
+    assert np.array_equal(got, solo.output(0).cpu().numpy())
+
+
+def test_plan_shape_invariance_and_autotune(gpu):
+    items = inputs.plan_table(n_dp=8, reps=8, n_lo=50, n_hi=5000, seed=2)
+    announce("plan shapes")
+    base = None
+    for rpw in (1, 2, 4):
+        for wg in (64, 256, 1024):
+            ctx = _plan_ctx(items, rpw, wg)
+            ctx.run_plan(42)
+            got = ctx.output(0, n=len(items)).cpu().numpy()
+            if base is None:
+                base = got
+            tol = 0.0 if rpw == 1 else 1e-6
+            assert rel_err(got, base).max() <= tol
+    ctx = _plan_ctx(items)
+    rpw, wg, ms = ctx.autotune(42)
+    assert rpw in (1, 2, 4) and wg in (64, 256, 1024) and ms > 0
+    ctx.run_plan(42)
+    assert rel_err(ctx.output(0, n=len(items)).cpu().numpy(), base).max() <= 1e-6
