@@ -20,6 +20,9 @@ __device__ __forceinline__ void step_delta(uint32_t d, int &dx, int &dy) {
   dy = (d == 2u) - (d == 3u);
 }
 
+// Set the visited bit of lattice site c (row-major) in an LDS bitmap.
+__device__ __forceinline__ void mark(uint32_t *bm, int c) { atomicOr(&bm[c >> 5], 1u << (c & 31)); }
+
 template <int GRID>
 __global__ void rw_wave_kernel(RwArgs a) {
   constexpr int WORDS = GRID * GRID / 32;
@@ -36,7 +39,7 @@ __global__ void rw_wave_kernel(RwArgs a) {
   int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
   int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
   int ux = 0, uy = 0;
-  if (active) atomicOr(&bm[(y * GRID + x) >> 5], 1u << (x & 31));
+  if (active) mark(bm, y * GRID + x);
 
   for (uint32_t g = 0; g < a.steps; g += 64) {
     const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
@@ -54,7 +57,7 @@ __global__ void rw_wave_kernel(RwArgs a) {
         uy += dy;
         x = (x + dx) & (GRID - 1);
         y = (y + dy) & (GRID - 1);
-        if (active) atomicOr(&bm[(y * GRID + x) >> 5], 1u << (x & 31));
+        if (active) mark(bm, y * GRID + x);
       }
     }
   }
@@ -83,7 +86,7 @@ __global__ void rw_simt_kernel(RwArgs a) {
     int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
     int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
     int ux = 0, uy = 0;
-    bm[(y * GRID + x) >> 5] |= 1u << (x & 31);
+    bm[(y * GRID + x) >> 5] |= 1u << ((y * GRID + x) & 31);
     for (uint32_t g = 0; g < a.steps; g += 64) {
       const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
       const uint32_t words[4] = {b.x, b.y, b.z, b.w};
@@ -98,7 +101,7 @@ __global__ void rw_simt_kernel(RwArgs a) {
           uy += dy;
           x = (x + dx) & (GRID - 1);
           y = (y + dy) & (GRID - 1);
-          bm[(y * GRID + x) >> 5] |= 1u << (x & 31);
+          bm[(y * GRID + x) >> 5] |= 1u << ((y * GRID + x) & 31);
         }
       }
     }

@@ -4,7 +4,7 @@
 // times; the rate is lane-instructions per second, reported beside the
 // full-rate figure 256 CU x 4 SIMD x 16 lanes x clock.
 //
-// Usage: valu_rates [waves_per_simd]
+// Usage: valu_rates [waves_per_simd ...]   (default: 4 8 16)
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -111,14 +111,21 @@ int main(int argc, char **argv) {
   CHECK(hipGetDevice(&dev));
   CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   CHECK(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeClockRate, dev));
-  const int waves_per_simd = argc > 1 ? std::atoi(argv[1]) : 4;
+  int wps_list[8] = {4, 8, 16};
+  int n_wps = 3;
+  if (argc > 1) {
+    n_wps = 0;
+    for (int i = 1; i < argc && n_wps < 8; ++i) wps_list[n_wps++] = std::atoi(argv[i]);
+  }
   const int threads = 256;  // 4 waves per block, one per SIMD
+  const double full = (double)cus * 4 * 16 * clock_khz * 1e3;
+  for (int wi = 0; wi < n_wps; ++wi) {
+  const int waves_per_simd = wps_list[wi];
   const int blocks = cus * waves_per_simd;
   uint32_t *out;
   CHECK(hipMalloc(&out, (size_t)blocks * threads * sizeof(uint32_t)));
-  const double full = (double)cus * 4 * 16 * clock_khz * 1e3;
-  std::printf("cus %d clock_mhz %.0f waves_per_simd %d full_rate_lane_ops_per_s %.4e\n", cus,
-              clock_khz / 1e3, waves_per_simd, full);
+  std::printf("cus %d clock_mhz %.0f waves_per_simd %d (16 lanes/SIMD/clk = %.4e lane-ops/s)\n",
+              cus, clock_khz / 1e3, waves_per_simd, full);
   struct Row {
     const char *name;
     double (*fn)(uint32_t *, int, int, double *);
@@ -137,5 +144,6 @@ int main(int argc, char **argv) {
                 rate / full, ms);
   }
   CHECK(hipFree(out));
+  }
   return 0;
 }
