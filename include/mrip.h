@@ -199,6 +199,7 @@ MRIP_API mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_i
  * independent prefix-only replications stays unbiased for any g. */
 
 #define MRIP_MLP_PARAMS 18049 /* W1[128x10] b1[128] W2[128x128] b2[128] W3[1x128] b3[1] */
+#define MRIP_CV_BETA_BINS 16  /* control coefficients over equal bins of rho */
 
 /* Forward pass of the 10-128-128-1 ReLU network, bf16 operands with fp32
  * accumulation. theta_dev: MRIP_MLP_PARAMS fp32; x_dev: n x 10 fp32
@@ -223,26 +224,51 @@ typedef struct {
   float lr, beta1, beta2, eps; /* default 1e-3, 0.9, 0.999, 1e-8 */
 } mrip_cv_hparams;
 
-/* Generate the training set with the M/M/1 engine (one replication per item,
- * features over the context's feature_prefix customers, target = mean W),
- * normalise features, train from theta0 (host, MRIP_MLP_PARAMS fp32) with
- * Adam, and fix beta = 1. hparams nullable (defaults). Synchronises. */
+/* Generate the training set with the M/M/1 engine (items: design points
+ * with at least two replications each; features over the context's
+ * feature_prefix customers; response Y = mean W), and train the network
+ * from theta0 (host, MRIP_MLP_PARAMS fp32) with Adam on z-scored features
+ * and the target (Y - mean_dp Y) / sd_dp Y, the replication's standardised
+ * deviation within its design point, over the first four fifths of the
+ * design points. On the held-out fifth, fit the control coefficient of each
+ * of MRIP_CV_BETA_BINS equal bins of rho = lambda/mu: the pooled
+ * within-design-point slope of Y on g(X), clamped at 0 (an empty bin takes
+ * its nearest neighbour's). hparams nullable (defaults). Synchronises. */
 MRIP_API mrip_status mrip_cv_train(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n,
                           const float *theta0, const mrip_cv_hparams *hparams, uint64_t seed,
                           void *hip_stream);
 
-/* Copy the trained weights (MRIP_MLP_PARAMS) and the feature mean / std
- * (10 + 10 fp32) to host buffers (any may be NULL). */
+/* Copy the model to host buffers (any may be NULL): weights
+ * (MRIP_MLP_PARAMS), feature mean and std (10 + 10), the coefficient table
+ * (MRIP_CV_BETA_BINS), its rho range (2) and the last epoch's mean training
+ * loss (in units of the standardised target: 1 = no skill). */
 MRIP_API mrip_status mrip_cv_model(mrip_ctx ctx, float *theta, float *feat_mean, float *feat_std,
-                          float *final_loss);
+                                   float *beta_table, float *rho_range, float *final_loss);
+
+/* Install a model instead of training one: theta (MRIP_MLP_PARAMS fp32),
+ * feature mean / std (10 + 10 fp32, std > 0), the coefficient table
+ * (MRIP_CV_BETA_BINS values >= 0) over rho in [rho_lo, rho_hi]; the
+ * control is g(x) = net((x - mean) / std). Host pointers. */
+MRIP_API mrip_status mrip_cv_set_model(mrip_ctx ctx, const float *theta, const float *feat_mean,
+                                       const float *feat_std, const float *beta_table,
+                                       float rho_lo, float rho_hi);
 
 /* Apply the trained control variate: full items (features + mean W) and
- * prefix-only items (customers = feature prefix, stream ids disjoint from
- * the full ones) grouped by dp; per design point compute the CV and plain
- * estimates. Synchronises. */
+ * prefix-only items (customers >= feature prefix, stream ids disjoint from
+ * the full ones) grouped by dp. Per design point with n full and M prefix
+ * replications, beta_dp = beta[bin(rho)] * M / (M + n) (the
+ * variance-minimising coefficient when E[g] is itself estimated from M
+ * replications), and Y_cv = mean(Y) - beta_dp (mean g(X) - mean g(X')),
+ * unbiased for any fixed network and coefficients. Synchronises. */
 MRIP_API mrip_status mrip_cv_apply(mrip_ctx ctx, const mrip_plan_item *full, uint64_t n_full,
                           const mrip_plan_item *prefix, uint64_t n_prefix, uint64_t seed,
                           void *hip_stream);
+
+/* Per-replication values of the last apply, in item order: which = 0 mean W
+ * of the full items, 1 g(X) of the full items, 2 g(X') of the prefix items,
+ * 3 features of the full items (10 each), 4 features of the prefix items.
+ * Host destination, `bytes` at least the output size. Synchronises. */
+MRIP_API mrip_status mrip_cv_outputs(mrip_ctx ctx, uint32_t which, void *dst, uint64_t bytes);
 
 /* CV and plain estimates for design point `dp` of the last apply. */
 MRIP_API mrip_status mrip_cv_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_stats_t *cv,

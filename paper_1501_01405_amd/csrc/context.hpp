@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -39,22 +40,38 @@ struct DevBuf {
 
 enum RunKind { RUN_NONE = 0, RUN_UNIFORM = 1, RUN_PLAN = 2 };
 
+// An item table on the device (structure of arrays) with its queue order
+// (longest first) and its grouping by design point (index + offsets).
+struct ItemBufs {
+  DevBuf dp, rep, n, lambda, mu, order, index, offsets;
+  uint64_t count = 0;
+  std::vector<uint32_t> dp_ids;          // distinct design points, ascending
+  std::vector<uint64_t> group_offsets;   // host copy of offsets
+  std::vector<uint32_t> index_host;      // host copy of index
+};
+
 // State of the learned control variate.
 struct CvState {
   bool trained = false, applied = false;
-  DevBuf theta;             // fp32 master weights (MRIP_MLP_PARAMS)
-  DevBuf adam_m, adam_v;    // Adam moments
-  DevBuf grad, loss;        // gradient and loss of the last step
-  DevBuf partial;           // per-workgroup gradient partials
-  DevBuf xn, y;             // normalised training features and targets
-  DevBuf norm;              // feature mean[10], std[10]
-  DevBuf work;              // apply: features, predictions, per-dp sums
-  std::vector<float> mean, std_;
-  float final_loss = 0.f;
-  float beta = 1.0f;
-  // apply results, per design point (host)
+  DevBuf theta, adam_m, adam_v, partial, loss_hist;
+  DevBuf queue, norm, colstats;
+  std::vector<float> mean, std_;  // feature mean / std of the training set
+  std::vector<float> beta;        // MRIP_CV_BETA_BINS coefficients over [rho_lo, rho_hi]
+  float rho_lo = 0.f, rho_hi = 1.f;
+  float final_loss = 0.f, train_ms = 0.f;
+  int bin_of(float rho) const {
+    const float u = (rho - rho_lo) / (rho_hi - rho_lo) * (float)MRIP_CV_BETA_BINS;
+    const int k = (int)std::floor(u);
+    return k < 0 ? 0 : k >= MRIP_CV_BETA_BINS ? MRIP_CV_BETA_BINS - 1 : k;
+  }
+  // training and application buffers
+  ItemBufs train_items, full_items, pre_items;
+  DevBuf y_train, x_train, t_train, scratch_t, scratch_i, xn, yn;
+  DevBuf y_full, x_full, g_full, d_full, y_pre, x_pre, g_pre, red_d, red_g, red_y, red_f;
+  // per design point of the last apply: cv = (n, mean, var of the estimator,
+  // Welch dof, beta used), plain = (n, mean, var of Y)
   std::vector<uint32_t> dp_ids;
-  std::vector<double> cv_nmv, plain_nmv;  // n, mean, var-of-mean, dof
+  std::vector<double> cv, plain;
   float full_ms = 0.f, prefix_ms = 0.f, infer_ms = 0.f;
 };
 

@@ -18,6 +18,7 @@ MRIP_OK, MRIP_E_INVAL, MRIP_E_NOMEM, MRIP_E_HIP, MRIP_E_STATE, MRIP_E_TOO_FEW, \
 MRIP_RW, MRIP_MM1, MRIP_FF = 1, 2, 3
 MRIP_MAP_AUTO, MRIP_MAP_SIMT, MRIP_MAP_WAVE = 0, 1, 2
 MRIP_MLP_PARAMS = 18049
+MRIP_CV_BETA_BINS = 16
 
 
 class mrip_rw_params(C.Structure):
@@ -84,7 +85,9 @@ _SIGS = {
     "mrip_mlp_grad": (st, [vp, vp, vp, u64, vp, vp, vp]),
     "mrip_adam_step": (st, [vp, vp, vp, vp, u64, u64, f32, f32, f32, f32, vp]),
     "mrip_cv_train": (st, [ctx_t, vp, u64, vp, C.POINTER(mrip_cv_hparams), u64, vp]),
-    "mrip_cv_model": (st, [ctx_t, vp, vp, vp, vp]),
+    "mrip_cv_model": (st, [ctx_t, vp, vp, vp, vp, vp, vp]),
+    "mrip_cv_set_model": (st, [ctx_t, vp, vp, vp, vp, f32, f32]),
+    "mrip_cv_outputs": (st, [ctx_t, u32, vp, u64]),
     "mrip_cv_apply": (st, [ctx_t, vp, u64, vp, u64, u64, vp]),
     "mrip_cv_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t),
                            C.POINTER(mrip_stats_t)]),
@@ -115,9 +118,15 @@ def _status_name(s):
 
 
 def load():
-    """Load libmrip.so (built by __graft_entry__.build()); raises if absent."""
+    """Load libmrip.so (built by __graft_entry__.build()); raises if absent.
+
+    PyTorch is imported first so that the library binds to the HIP runtime
+    PyTorch already loaded (both carry the soname libamdhip64.so.7): one
+    runtime per process, so torch's streams and buffers are valid handles
+    for the library."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see docstring)
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libmrip.so is not built (run __graft_entry__.build())")
         L = C.CDLL(LIB_PATH)
@@ -241,13 +250,35 @@ def mrip_cv_train(ctx, items, theta0, hparams=None, seed=42, stream=None):
 
 
 def mrip_cv_model(ctx):
+    """dict(theta, feat_mean, feat_std, beta (table), rho_range, final_loss)."""
     theta = np.zeros(MRIP_MLP_PARAMS, np.float32)
     mean = np.zeros(10, np.float32)
     std = np.zeros(10, np.float32)
+    beta = np.zeros(MRIP_CV_BETA_BINS, np.float32)
+    rr = np.zeros(2, np.float32)
     loss = f32()
     check(load().mrip_cv_model(ctx, theta.ctypes.data, mean.ctypes.data, std.ctypes.data,
-                               C.byref(loss)), ctx)
-    return theta, mean, std, loss.value
+                               beta.ctypes.data, rr.ctypes.data, C.byref(loss)), ctx)
+    return dict(theta=theta, feat_mean=mean, feat_std=std, beta=beta,
+                rho_range=(float(rr[0]), float(rr[1])), final_loss=loss.value)
+
+
+def mrip_cv_set_model(ctx, theta, feat_mean, feat_std, beta_table, rho_lo, rho_hi):
+    theta = np.ascontiguousarray(theta, dtype=np.float32)
+    feat_mean = np.ascontiguousarray(feat_mean, dtype=np.float32)
+    feat_std = np.ascontiguousarray(feat_std, dtype=np.float32)
+    beta_table = np.ascontiguousarray(np.broadcast_to(beta_table, (MRIP_CV_BETA_BINS,)),
+                                      dtype=np.float32)
+    check(load().mrip_cv_set_model(ctx, theta.ctypes.data, feat_mean.ctypes.data,
+                                   feat_std.ctypes.data, beta_table.ctypes.data, rho_lo, rho_hi),
+          ctx)
+
+
+def mrip_cv_outputs(ctx, which, n):
+    cols = 10 if which in (3, 4) else 1
+    out = np.zeros((n, cols) if cols > 1 else n, np.float32)
+    check(load().mrip_cv_outputs(ctx, which, out.ctypes.data, out.nbytes), ctx)
+    return out
 
 
 def mrip_cv_apply(ctx, full, prefix, seed=42, stream=None):
