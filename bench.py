@@ -93,6 +93,45 @@ def cpu_baseline(seconds):
                       (reps, N, dt)}
 
 
+def cv_experiment(mrip, inputs, customers, K=1000):
+    """Learned control variate: train on 1e5 replications (3125 design points
+    x 32, rho ~ U[0.5, 0.95]), apply to 256 new design points x 64 full
+    replications + 256 prefix-only replications each; report the pooled
+    variance reduction, the interval half-widths at equal GPU time and the
+    bias z-score of CV - plain over design points."""
+    train, full, pref = inputs.cv_design(n_train=100000, train_reps=32, n_apply_dp=256, reps=64,
+                                         prefix_reps=256, customers=customers, prefix=K)
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, customers, K),
+                       mrip.MRIP_MAP_WAVE)
+    t0 = time.perf_counter()
+    mrip.mrip_cv_train(ctx.ctx, train, inputs.he_uniform_init(), mrip.cv_hparams(), seed=42,
+                       stream=mrip.current_stream())
+    train_s = time.perf_counter() - t0
+    model = mrip.mrip_cv_model(ctx.ctx)
+    mrip.mrip_cv_apply(ctx.ctx, full, pref, seed=43, stream=mrip.current_stream())
+    full_ms, pre_ms, inf_ms = mrip.mrip_cv_times(ctx.ctx)
+    v_cv = v_pl = 0.0
+    diffs = []
+    for dp in sorted(set(int(d) for d in full["dp"])):
+        c, p = mrip.mrip_cv_stats(ctx.ctx, dp)
+        v_cv += c["var"] / c["n"]
+        v_pl += p["var"] / p["n"]
+        diffs.append(c["mean"] - p["mean"])
+    n_dp = len(diffs)
+    mean_d = sum(diffs) / n_dp
+    sd_d = math.sqrt(sum((d - mean_d) ** 2 for d in diffs) / (n_dp - 1))
+    t_plain = full_ms * 1e-3
+    t_cv = (full_ms + pre_ms + inf_ms) * 1e-3
+    vrf = v_pl / v_cv
+    return {"customers_per_rep": customers, "prefix": K, "train_s_wall": train_s,
+            "train_final_loss": model["final_loss"],
+            "beta_table": [round(float(b), 4) for b in model["beta"]],
+            "variance_reduction": vrf, "half_width_ratio_plain_over_cv": math.sqrt(vrf),
+            "gpu_ms": {"full": full_ms, "prefix": pre_ms, "inference": inf_ms},
+            "equal_time_gain": math.sqrt(vrf * t_plain / t_cv),
+            "bias_z": mean_d / (sd_d / math.sqrt(n_dp)) if sd_d > 0 else 0.0}
+
+
 def extras(torch, mrip, inputs):
     """Secondary configurations, each timed by the library's kernel events."""
     out = {}
@@ -124,6 +163,9 @@ def extras(torch, mrip, inputs):
     ff["simt"] = {"cell_updates_per_s": v, "kernel_ms": ms}
     ff["wave_over_simt"] = ff["wave"]["cell_updates_per_s"] / ff["simt"]["cell_updates_per_s"]
     out["ff_4096x128x128x2000"] = ff
+
+    out["cv_1e5"] = cv_experiment(mrip, inputs, 100000)
+    out["cv_1e4"] = cv_experiment(mrip, inputs, 10000)
 
     # uneven plan: 64 dp x 32 reps, N log-uniform in [1e4, 1e6], one launch
     items = inputs.plan_table()

@@ -44,7 +44,7 @@ enum RunKind { RUN_NONE = 0, RUN_UNIFORM = 1, RUN_PLAN = 2 };
 // (longest first) and its grouping by design point (index + offsets).
 struct ItemBufs {
   DevBuf dp, rep, n, lambda, mu, order, index, offsets;
-  uint64_t count = 0;
+  uint64_t count = 0, max_customers = 0;
   std::vector<uint32_t> dp_ids;          // distinct design points, ascending
   std::vector<uint64_t> group_offsets;   // host copy of offsets
   std::vector<uint32_t> index_host;      // host copy of index

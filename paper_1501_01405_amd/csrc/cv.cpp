@@ -83,6 +83,7 @@ mrip_status upload_items(mrip_ctx c, const mrip_plan_item *items, uint64_t n, ui
   }
   b.group_offsets.push_back(n);
   b.index_host = index;
+  b.max_customers = *std::max_element(cust.begin(), cust.end());
   CV_TRY(c, b.dp.ensure(4 * n));
   CV_TRY(c, b.rep.ensure(4 * n));
   CV_TRY(c, b.n.ensure(8 * n));
@@ -133,7 +134,9 @@ mrip_status run_items(mrip_ctx c, ItemBufs &b, uint64_t seed, uint64_t K, float 
   }
   CV_TRY(c, launch_zero_u32(a.queue_head, 1, s));
   if (ms) CV_TRY(c, hipEventRecord(e0, s));
-  CV_TRY(c, launch_mm1_plan(a, b.count, c->rpw, c->wg, s));
+  // short replications (prefix-only runs) share a wavefront four at a time
+  const uint32_t rpw = b.max_customers <= 4096 ? 4u : c->rpw;
+  CV_TRY(c, launch_mm1_plan(a, b.count, rpw, c->wg, s));
   if (ms) {
     CV_TRY(c, hipEventRecord(e1, s));
     CV_TRY(c, hipEventSynchronize(e1));

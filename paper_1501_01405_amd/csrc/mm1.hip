@@ -8,14 +8,14 @@
 // sequential Lindley recursion into a prefix scan.
 //
 // WAVE mapping (one replication per wavefront): a segment of 16 lanes takes
-// 32 consecutive customers, two per lane from one Philox block, composes
-// the lane's pair, runs a 4-step DPP inclusive scan (row_shr 1, 2, 4, 8;
+// 16 P consecutive customers, P per lane from P/2 Philox blocks, composes
+// the lane's maps, runs a 4-step DPP inclusive scan (row_shr 1, 2, 4, 8;
 // a DPP row is exactly the segment) and applies the exclusive prefix to the
 // carried T. A replication spans 4 / RPW segments; the carry passes through
 // them in order as T <- max(a_tot, T + b_tot). Because every replication is
-// always cut into the same 32-customer segments and the carry visits them
-// in the same order, the per-customer values do not depend on RPW or on the
-// workgroup size; only the summation order of the means does.
+// always cut into the same segments and the carry visits them in the same
+// order, the per-customer values do not depend on RPW or on the workgroup
+// size; only the summation order of the means does.
 //
 // SIMT mapping (one replication per lane): the sequential recursion, one
 // customer after the other, as the paper's thread-per-replication form.
@@ -49,23 +49,62 @@ __device__ __forceinline__ float pick4(int q, float v0, float v1, float v2, floa
   return q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3;
 }
 
-// One chunk: every segment of the replication handles 32 customers.
-template <int RPW, bool FEAT>
-__device__ __forceinline__ void wave_chunk(uint64_t base, const Rep &d, uint32_t k0, uint32_t k1,
+// Customers per lane per chunk (P / 2 Philox blocks). A segment of 16 lanes
+// takes 16 P consecutive customers; this fixes the association of the scan,
+// so it is the same for every launch shape.
+constexpr int MM1_P = 8;
+
+// The variates of one chunk for this lane: P customers from P/2 blocks.
+template <int P>
+struct Draw {
+  float A[P], S[P];
+};
+
+template <int RPW, int P>
+__device__ __forceinline__ Draw<P> draw_chunk(uint64_t base, const Rep &d, uint32_t k0,
+                                              uint32_t k1) {
+  constexpr int S = 4 / RPW;
+  constexpr int NB = P / 2;
+  const int lane = threadIdx.x & 63;
+  const int s = (lane >> 4) % S, l = lane & 15;
+  const uint64_t kb = (base >> 1) + (uint64_t)(16 * s + l) * NB;
+  Draw<P> r;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const Block4 b = philox((uint32_t)(kb + j), d.dp, d.rep, TAG_MM1, k0, k1);
+    r.A[2 * j] = exp_variate(b.x, d.ca);
+    r.S[2 * j] = exp_variate(b.y, d.cs);
+    r.A[2 * j + 1] = exp_variate(b.z, d.ca);
+    r.S[2 * j + 1] = exp_variate(b.w, d.cs);
+  }
+  return r;
+}
+
+// One chunk: every segment of the replication takes 16 P customers, whose
+// variates are `dr`. FEAT accumulates the prefix features; TAIL masks
+// customers >= n (only chunks that reach past some replication's end need
+// it).
+template <int RPW, int P, bool FEAT, bool TAIL>
+__device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, const Rep &d,
                                            uint64_t K, float &carry, Sums &acc, Feat &ft) {
   constexpr int S = 4 / RPW;  // segments per replication
+  constexpr int NB = P / 2;   // Philox blocks per lane
   const int lane = threadIdx.x & 63;
   const int row = lane >> 4, l = lane & 15;
   const int q = row / S, s = row % S;
+  const uint64_t kb = (base >> 1) + (uint64_t)(16 * s + l) * NB;
+  const float *A = dr.A;
+  const float *Sv = dr.S;
 
-  const uint64_t kblk = (base >> 1) + 16u * (uint32_t)s + (uint32_t)l;
-  const Block4 b = philox((uint32_t)kblk, d.dp, d.rep, TAG_MM1, k0, k1);
-  const float A0 = exp_variate(b.x, d.ca), S0 = exp_variate(b.y, d.cs);
-  const float A1 = exp_variate(b.z, d.ca), S1 = exp_variate(b.w, d.cs);
-
-  // lane-local composition of customer 2k then 2k+1
-  float a = fmaxf(S1, S0 + (S1 - A1));
-  float bb = (S0 - A0) + (S1 - A1);
+  // lane-local composition of the lane's P customers, in order
+  float a = Sv[0];
+  float bb = Sv[0] - A[0];
+#pragma unroll
+  for (int j = 1; j < P; ++j) {
+    const float bj = Sv[j] - A[j];
+    a = fmaxf(Sv[j], a + bj);
+    bb = bb + bj;
+  }
 
   // inclusive scan over the 16-lane segment
 #define MRIP_SCAN_STEP(N)                              \
@@ -104,27 +143,40 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Rep &d, uint32_t
   }
   carry = cur;
 
-  // the two customers of this lane
-  const float tp = fmaxf(ea, tin + eb);
-  const float W0 = fmaxf(0.0f, tp - A0), I0 = fmaxf(0.0f, A0 - tp), T0 = W0 + S0;
-  const float W1 = fmaxf(0.0f, T0 - A1), I1 = fmaxf(0.0f, A1 - T0), T1 = W1 + S1;
-  const uint64_t n0 = 2 * kblk;
-  const bool v0 = n0 < d.n, v1 = n0 + 1 < d.n;
-  acc.w.add((v0 ? W0 : 0.f) + (v1 ? W1 : 0.f));
-  acc.t.add((v0 ? T0 : 0.f) + (v1 ? T1 : 0.f));
-  acc.i.add((v0 ? I0 : 0.f) + (v1 ? I1 : 0.f));
-  if (FEAT) {
-    const bool f0 = n0 < K, f1 = n0 + 1 < K;
-    ft.sa += (f0 ? A0 : 0.f) + (f1 ? A1 : 0.f);
-    ft.ss += (f0 ? S0 : 0.f) + (f1 ? S1 : 0.f);
-    ft.sw += (f0 ? W0 : 0.f) + (f1 ? W1 : 0.f);
-    ft.st += (f0 ? T0 : 0.f) + (f1 ? T1 : 0.f);
-    ft.si += (f0 ? I0 : 0.f) + (f1 ? I1 : 0.f);
-    ft.zeros += (f0 && W0 == 0.f) + (f1 && W1 == 0.f);
-    ft.wmax = fmaxf(ft.wmax, fmaxf(f0 ? W0 : 0.f, f1 ? W1 : 0.f));
-    if (f0 && n0 + 1 == K) ft.tlast = T0;
-    if (f1 && n0 + 2 == K) ft.tlast = T1;
+  // the lane's customers, in order, from the system time before the first
+  float T = fmaxf(ea, tin + eb);
+  float sw = 0.0f, st = 0.0f, si = 0.0f;
+  const uint64_t n0 = 2 * kb;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const float W = fmaxf(0.0f, T - A[j]);
+    const float I = fmaxf(0.0f, A[j] - T);
+    T = W + Sv[j];
+    if (TAIL) {
+      const bool v = n0 + j < d.n;
+      sw += v ? W : 0.0f;
+      st += v ? T : 0.0f;
+      si += v ? I : 0.0f;
+    } else {
+      sw += W;
+      st += T;
+      si += I;
+    }
+    if (FEAT) {
+      const bool f = n0 + j < K;
+      ft.sa += f ? A[j] : 0.0f;
+      ft.ss += f ? Sv[j] : 0.0f;
+      ft.sw += f ? W : 0.0f;
+      ft.st += f ? T : 0.0f;
+      ft.si += f ? I : 0.0f;
+      ft.zeros += (f && W == 0.0f);
+      ft.wmax = fmaxf(ft.wmax, f ? W : 0.0f);
+      if (n0 + j + 1 == K) ft.tlast = T;
+    }
   }
+  acc.w.add(sw);
+  acc.t.add(st);
+  acc.i.add(si);
 }
 
 // Runs the replications of one wavefront (RPW of them, one per lane group)
@@ -132,23 +184,37 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Rep &d, uint32_t
 template <int RPW>
 __device__ void wave_group(const Rep &d, uint32_t k0, uint32_t k1, uint64_t K,
                            const Mm1Args &a) {
+  constexpr int P = MM1_P;
   constexpr int S = 4 / RPW;
   constexpr int WIDTH = 16 * S;  // lanes per replication
-  constexpr uint64_t CHUNK = 32u * S;
+  constexpr uint64_t CHUNK = 16u * P * S;
   const int lane = threadIdx.x & 63;
 
-  // wave-uniform trip counts: the longest replication of the wave
-  uint32_t my_chunks = (uint32_t)((d.n + CHUNK - 1) / CHUNK);
-  for (int off = WIDTH; off < 64; off <<= 1) my_chunks = max(my_chunks, (uint32_t)__shfl_xor((int)my_chunks, off, 64));
-  const uint32_t chunks = (uint32_t)__builtin_amdgcn_readfirstlane((int)my_chunks);
-  const uint32_t fchunks = (uint32_t)((K + CHUNK - 1) / CHUNK);
+  // wave-uniform trip counts: chunks of the longest replication, and chunks
+  // that are full for every non-empty replication of the wave
+  uint32_t hi = (uint32_t)((d.n + CHUNK - 1) / CHUNK);
+  uint32_t lo = d.n > 0 ? (uint32_t)(d.n / CHUNK) : 0xFFFFFFFFu;
+  for (int off = WIDTH; off < 64; off <<= 1) {
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+  }
+  const uint32_t chunks = (uint32_t)__builtin_amdgcn_readfirstlane((int)hi);
+  const uint32_t full = min(chunks, (uint32_t)__builtin_amdgcn_readfirstlane((int)lo));
+  const uint32_t fchunks = min(chunks, (uint32_t)((K + CHUNK - 1) / CHUNK));
 
   float carry = 0.0f;
   Sums acc;
   Feat ft;
   uint32_t c = 0;
-  for (; c < fchunks && c < chunks; ++c) wave_chunk<RPW, true>(c * CHUNK, d, k0, k1, K, carry, acc, ft);
-  for (; c < chunks; ++c) wave_chunk<RPW, false>(c * CHUNK, d, k0, k1, K, carry, acc, ft);
+#define MRIP_CHUNK(F, TL)                                                            \
+  {                                                                                  \
+    const Draw<P> cur = draw_chunk<RPW, P>((uint64_t)c * CHUNK, d, k0, k1);         \
+    wave_chunk<RPW, P, F, TL>(c * CHUNK, cur, d, K, carry, acc, ft);                 \
+  }
+  for (; c < fchunks; ++c) MRIP_CHUNK(true, true)
+  for (; c < full; ++c) MRIP_CHUNK(false, false)
+  for (; c < chunks; ++c) MRIP_CHUNK(false, true)
+#undef MRIP_CHUNK
 
   const float sw = group_sum_compensated(acc.w.value(), WIDTH);
   const float st = group_sum_compensated(acc.t.value(), WIDTH);
