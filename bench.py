@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 R, N, LAM, MU = 1024, 100000, 0.9, 1.0
+SPLIT = 2  # wavefronts per replication (two per SIMD at 1024 replications)
 # Peak vector issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, the rate
 # behind the published fp32 vector figure (157.3 TFLOP/s counts an FMA as 2).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
@@ -143,13 +144,28 @@ def extras(torch, mrip, inputs):
             ms.append(ctx.last_ms())
         return events / (min(ms) * 1e-3), min(ms)
 
+    maps = (("wave", mrip.MRIP_MAP_WAVE), ("simt", mrip.MRIP_MAP_SIMT),
+            ("lane0", mrip.MRIP_MAP_LANE0))
     # random walk: 32 reps x 64 walkers x 1000 steps on a 64x64 torus
-    for name, mp in (("wave", mrip.MRIP_MAP_WAVE), ("simt", mrip.MRIP_MAP_SIMT)):
+    for name, mp in maps:
         ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), mp)
         v, ms = rate(ctx, 32, 32 * 64 * 1000)
         out.setdefault("rw_32x64x1000", {})[name] = {"walker_steps_per_s": v, "kernel_ms": ms}
     rw = out["rw_32x64x1000"]
     rw["wave_over_simt"] = rw["wave"]["walker_steps_per_s"] / rw["simt"]["walker_steps_per_s"]
+    rw["lane0_over_simt"] = rw["lane0"]["walker_steps_per_s"] / rw["simt"]["walker_steps_per_s"]
+    # the paper's replication sweep (its random-walk figure): kernel ms per mapping
+    sweep = {}
+    for name, mp in maps:
+        ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), mp)
+        for n in (1, 8, 32, 64, 256, 1024, 4096, 16384):
+            sweep.setdefault(str(n), {})[name] = rate(ctx, n, n * 64 * 1000, runs=2)[1]
+    rw["sweep_kernel_ms"] = sweep
+
+    # M/M/1 with the paper's one-working-lane WLP form
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_LANE0)
+    v, ms = rate(ctx, R, R * N, runs=2)
+    out["mm1_lane0"] = {"customers_per_s": v, "kernel_ms": ms}
 
     # forest fire: 4096 reps x 128^2 x 2000 steps
     ev = 4096 * 128 * 128 * 2000
@@ -200,6 +216,7 @@ def main():
     mrip.load()
 
     ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_WAVE)
+    ctx.set_split(SPLIT)
     elapsed, kernel_ms, ci = timed_steps(ctx, args.steps, args.warmup, torch, mrip)
     customers = R * N
     value = customers * args.steps / elapsed
@@ -232,12 +249,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic (Philox4x32-10 streams generated on the device, seed 42+step)",
         "config": {"workload": "M/M/1 MRIP, 1024 replications x 100000 customers, "
-                               "lambda=0.9, mu=1, one replication per wavefront",
-                   "replications": R, "customers": N, "mapping": "WAVE"},
+                               "lambda=0.9, mu=1, one replication per wavefront pair",
+                   "replications": R, "customers": N, "mapping": "WAVE",
+                   "waves_per_replication": SPLIT},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                     "kernel": "mm1_wave_kernel<1>", "avg_kernel_ms": avg_kernel_ms,
+                     "kernel": "mm1_split_kernel<2>", "avg_kernel_ms": avg_kernel_ms,
                      "slots_per_customer": slots},
         "ci": {"mean_wq": ci["mean"], "half_width_95": ci["half_width"],
                "gpu_seconds_per_step": ms_step * 1e-3,

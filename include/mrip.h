@@ -58,10 +58,18 @@ typedef enum {
 
 typedef enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3 } mrip_model;
 
-/* SIMT: one replication per lane. WAVE: one replication per 64-lane
- * wavefront (or 2 / 4 replications per wavefront on 32 / 16 lanes each, see
- * mrip_set_shape). AUTO picks WAVE. */
-typedef enum { MRIP_MAP_AUTO = 0, MRIP_MAP_SIMT = 1, MRIP_MAP_WAVE = 2 } mrip_mapping;
+/* SIMT: one replication per lane (the paper's thread-level form, section
+ * 3). WAVE: one replication per 64-lane wavefront with every lane working on
+ * it (or 2 / 4 replications per wavefront on 32 / 16 lanes each, see
+ * mrip_set_shape). LANE0: one replication per wavefront with only its first
+ * lane working, the paper's own warp-level form (sections 3 and 4: every
+ * thread but the first of its warp disabled). AUTO picks WAVE. */
+typedef enum {
+  MRIP_MAP_AUTO = 0,
+  MRIP_MAP_SIMT = 1,
+  MRIP_MAP_WAVE = 2,
+  MRIP_MAP_LANE0 = 3
+} mrip_mapping;
 
 /* Parameter structs: `size` must equal sizeof(the struct); they are copied
  * by mrip_create. */
@@ -136,6 +144,16 @@ MRIP_API void mrip_destroy(mrip_ctx ctx);
 /* WAVE launch shape: replications per wavefront (1, 2 or 4) and workgroup
  * size (64, 256 or 1024). Outputs do not depend on it. Defaults 1 and 256. */
 MRIP_API mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t reps_per_wave, uint32_t workgroup);
+
+/* Wavefronts per replication for mrip_run on an M/M/1 WAVE context: 1, 2
+ * or 4 (default 1; needs reps_per_wave = 1). With 2 or 4, the wavefronts of
+ * a 256-thread workgroup each take an equal run of the replication's
+ * customers, start from an empty system, and then in order re-run their
+ * leading chunks from the carry the previous part left until the two
+ * trajectories meet (Lindley's recursion forgets its start once the queue
+ * empties). Per-customer values are those of the unsplit run; the means
+ * differ only by fp32 summation order. */
+MRIP_API mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep);
 
 /* --------------------------------------------------------------- the path */
 

@@ -45,7 +45,9 @@ uint32_t scalar_outputs(mrip_model m) { return m == MRIP_RW ? 2 : m == MRIP_MM1 
 
 bool is_pow2_grid(uint32_t g) { return g == 16 || g == 32 || g == 64 || g == 128; }
 
-mrip_mapping effective(mrip_mapping m) { return m == MRIP_MAP_SIMT ? MRIP_MAP_SIMT : MRIP_MAP_WAVE; }
+mrip_mapping effective(mrip_mapping m) {
+  return (m == MRIP_MAP_SIMT || m == MRIP_MAP_LANE0) ? m : MRIP_MAP_WAVE;
+}
 
 uint32_t ff_threshold(double prob) {
   double v = std::floor(prob * 4294967296.0);
@@ -93,7 +95,8 @@ mrip_status finish_stats(const double *nmv, double confidence, mrip_stats_t *out
 
 mrip_status validate(mrip_model model, const void *params, mrip_mapping map, std::string &why) {
   if (!params) return why = "params is NULL", MRIP_E_INVAL;
-  if (map != MRIP_MAP_AUTO && map != MRIP_MAP_SIMT && map != MRIP_MAP_WAVE)
+  if (map != MRIP_MAP_AUTO && map != MRIP_MAP_SIMT && map != MRIP_MAP_WAVE &&
+      map != MRIP_MAP_LANE0)
     return why = "unknown mapping", MRIP_E_INVAL;
   if (model == MRIP_RW) {
     const mrip_rw_params *p = (const mrip_rw_params *)params;
@@ -183,8 +186,20 @@ mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t rpw, uint32_t wg) {
   if (wg != 64 && wg != 256 && wg != 1024) return inval(ctx, "workgroup must be 64, 256 or 1024");
   if (rpw != 1 && ctx->model != MRIP_MM1)
     return inval(ctx, "reps_per_wave > 1 is only defined for the M/M/1 engine");
+  if (rpw != 1 && ctx->split != 1) return inval(ctx, "a split replication needs reps_per_wave = 1");
   ctx->rpw = rpw;
   ctx->wg = wg;
+  return MRIP_OK;
+}
+
+mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (waves_per_rep != 1 && waves_per_rep != 2 && waves_per_rep != 4)
+    return inval(ctx, "waves_per_rep must be 1, 2 or 4");
+  if (waves_per_rep > 1 && (ctx->model != MRIP_MM1 || ctx->mapping != MRIP_MAP_WAVE))
+    return inval(ctx, "splitting a replication is defined for the M/M/1 WAVE engine");
+  if (waves_per_rep > 1 && ctx->rpw != 1) return inval(ctx, "splitting needs reps_per_wave = 1");
+  ctx->split = waves_per_rep;
   return MRIP_OK;
 }
 
@@ -216,7 +231,7 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     } else {
       HIP_TRY(ctx, ctx->scratch.ensure(n_reps * (uint64_t)a.grid * a.grid / 8));
       a.scratch_bitmaps = ctx->scratch.as<uint32_t>();
-      HIP_TRY(ctx, launch_rw_simt(a, s));
+      HIP_TRY(ctx, launch_rw_simt(a, ctx->mapping == MRIP_MAP_LANE0, s));
     }
   } else if (ctx->model == MRIP_MM1) {
     Mm1Args a{};
@@ -233,8 +248,9 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
       HIP_TRY(ctx, ctx->out[3].ensure(n_reps * 40));
       a.features = ctx->out[3].as<float>();
     }
-    if (wave) HIP_TRY(ctx, launch_mm1_wave(a, ctx->rpw, ctx->wg, s));
-    else HIP_TRY(ctx, launch_mm1_simt(a, s));
+    if (wave && ctx->split > 1) HIP_TRY(ctx, launch_mm1_split(a, ctx->split, s));
+    else if (wave) HIP_TRY(ctx, launch_mm1_wave(a, ctx->rpw, ctx->wg, s));
+    else HIP_TRY(ctx, launch_mm1_simt(a, ctx->mapping == MRIP_MAP_LANE0, s));
   } else {
     FfArgs a{};
     a.seed = seed;
@@ -249,7 +265,7 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     } else {
       HIP_TRY(ctx, ctx->scratch.ensure(n_reps * 2ull * a.grid * (a.grid / 32) * 4));
       a.state = ctx->scratch.as<uint32_t>();
-      HIP_TRY(ctx, launch_ff_simt(a, s));
+      HIP_TRY(ctx, launch_ff_simt(a, ctx->mapping == MRIP_MAP_LANE0, s));
     }
   }
   st = record_end(ctx, s);

@@ -84,6 +84,7 @@ struct mrip_ctx_s {
   mrip_mm1_params mm1;
   mrip_ff_params ff;
   uint32_t rpw = 1, wg = 256;
+  uint32_t split = 1;  // wavefronts per M/M/1 replication in mrip_run
 
   mrip::DevBuf out[4];
   mrip::DevBuf scratch;

@@ -51,9 +51,13 @@ __device__ __forceinline__ uint32_t word_of(const Block4 &b, uint32_t j) {
 }
 
 // Exponential variate: scale * log2(u) with scale = -(1/rate) * ln 2
-// (computed on the host), u = ((x >> 8) + 1) * 2^-24 in (0, 1].
+// (computed on the host), u = ((x >> 8) + 1) * 2^-24 in (0, 1]. u is formed
+// as fma(x & ~0xff, 2^-32, 2^-24): the masked word converts exactly (24
+// significant bits), and the fused multiply-add is exact because its result
+// k * 2^-24, k <= 2^24, is representable; one instruction fewer than shift,
+// add, convert, scale.
 __device__ __forceinline__ float exp_variate(uint32_t x, float neg_mean_ln2) {
-  const float u = (float)((x >> 8) + 1u) * 0x1p-24f;
+  const float u = __builtin_fmaf((float)(x & 0xFFFFFF00u), 0x1p-32f, 0x1p-24f);
   return neg_mean_ln2 * __builtin_amdgcn_logf(u);
 }
 

@@ -115,10 +115,13 @@ __global__ void ff_wave_kernel(FfArgs a) {
   if (lane == 0) a.burnt[r] = burnt;
 }
 
-template <int GRID>
+// STRIDE = 1: one replication per lane; 64: one working lane per wavefront
+// (the paper's WLP form).
+template <int GRID, int STRIDE>
 __global__ void ff_simt_kernel(FfArgs a) {
   constexpr int DW = GRID / 32;
-  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x % STRIDE) return;
+  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
   if (r >= a.n_reps) return;
   const uint64_t R = a.n_reps;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -172,10 +175,12 @@ hipError_t wave_launch(const FfArgs &a, uint32_t wg, hipStream_t s) {
 }
 
 template <int GRID>
-hipError_t simt_launch(const FfArgs &a, hipStream_t s) {
+hipError_t simt_launch(const FfArgs &a, bool one_lane, hipStream_t s) {
   const uint32_t wg = 64;
-  const uint64_t blocks = (a.n_reps + wg - 1) / wg;
-  hipLaunchKernelGGL(ff_simt_kernel<GRID>, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
+  const uint64_t blocks = (threads + wg - 1) / wg;
+  if (one_lane) hipLaunchKernelGGL((ff_simt_kernel<GRID, 64>), dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  else hipLaunchKernelGGL((ff_simt_kernel<GRID, 1>), dim3((uint32_t)blocks), dim3(wg), 0, s, a);
   return hipGetLastError();
 }
 
@@ -189,16 +194,16 @@ hipError_t launch_ff_wave(const FfArgs &a, uint32_t wg, hipStream_t s) {
   }
 }
 
-hipError_t launch_ff_simt(const FfArgs &a, hipStream_t s) {
+hipError_t launch_ff_simt(const FfArgs &a, bool one_lane, hipStream_t s) {
   switch (a.grid) {
-    case 32: return simt_launch<32>(a, s);
-    case 64: return simt_launch<64>(a, s);
-    case 96: return simt_launch<96>(a, s);
-    case 128: return simt_launch<128>(a, s);
-    case 160: return simt_launch<160>(a, s);
-    case 192: return simt_launch<192>(a, s);
-    case 224: return simt_launch<224>(a, s);
-    case 256: return simt_launch<256>(a, s);
+    case 32: return simt_launch<32>(a, one_lane, s);
+    case 64: return simt_launch<64>(a, one_lane, s);
+    case 96: return simt_launch<96>(a, one_lane, s);
+    case 128: return simt_launch<128>(a, one_lane, s);
+    case 160: return simt_launch<160>(a, one_lane, s);
+    case 192: return simt_launch<192>(a, one_lane, s);
+    case 224: return simt_launch<224>(a, one_lane, s);
+    case 256: return simt_launch<256>(a, one_lane, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -16,7 +16,8 @@ struct RwArgs {
   uint32_t *scratch_bitmaps;  // SIMT only: n_reps * grid*grid/32 words
 };
 hipError_t launch_rw_wave(const RwArgs &a, uint32_t workgroup, hipStream_t s);
-hipError_t launch_rw_simt(const RwArgs &a, hipStream_t s);
+// one_lane: one working lane per wavefront (the paper's WLP form)
+hipError_t launch_rw_simt(const RwArgs &a, bool one_lane, hipStream_t s);
 
 // ------------------------------------------------------------ M/M/1
 // Per-item parameters in structure-of-arrays form on the device.
@@ -39,7 +40,10 @@ struct Mm1Args {
 };
 hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t reps_per_wave, uint32_t workgroup,
                            hipStream_t s);
-hipError_t launch_mm1_simt(const Mm1Args &a, hipStream_t s);
+hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s);
+// WAVE mapping with each replication split over 2 or 4 wavefronts of a
+// 256-thread workgroup (speculate from carry 0, then correct in order).
+hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s);
 // Persistent plan kernel: grid sized to full residency, waves pop work.
 hipError_t launch_mm1_plan(const Mm1Args &a, uint64_t n_items, uint32_t reps_per_wave,
                            uint32_t workgroup, hipStream_t s);
@@ -56,7 +60,7 @@ struct FfArgs {
   uint32_t *state;  // SIMT only: 2 planes * grid rows * grid/32 words * n_reps
 };
 hipError_t launch_ff_wave(const FfArgs &a, uint32_t workgroup, hipStream_t s);
-hipError_t launch_ff_simt(const FfArgs &a, hipStream_t s);
+hipError_t launch_ff_simt(const FfArgs &a, bool one_lane, hipStream_t s);
 
 // ------------------------------------------------------------ reductions
 // out[3*g + {0,1,2}] = (n, mean, unbiased var) in fp64 over segment g of x;

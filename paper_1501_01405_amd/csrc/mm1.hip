@@ -80,33 +80,24 @@ __device__ __forceinline__ Draw<P> draw_chunk(uint64_t base, const Rep &d, uint3
   return r;
 }
 
-// One chunk: every segment of the replication takes 16 P customers, whose
-// variates are `dr`. FEAT accumulates the prefix features; TAIL masks
-// customers >= n (only chunks that reach past some replication's end need
-// it).
-template <int RPW, int P, bool FEAT, bool TAIL>
-__device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, const Rep &d,
-                                           uint64_t K, float &carry, Sums &acc, Feat &ft) {
-  constexpr int S = 4 / RPW;  // segments per replication
-  constexpr int NB = P / 2;   // Philox blocks per lane
-  const int lane = threadIdx.x & 63;
-  const int row = lane >> 4, l = lane & 15;
-  const int q = row / S, s = row % S;
-  const uint64_t kb = (base >> 1) + (uint64_t)(16 * s + l) * NB;
-  const float *A = dr.A;
-  const float *Sv = dr.S;
+// The scanned maps of one chunk: this lane's exclusive prefix (ea, eb) and
+// the four segment totals.
+struct ChunkScan {
+  float ea, eb;
+  float ta[4], tb[4];
+};
 
-  // lane-local composition of the lane's P customers, in order
-  float a = Sv[0];
-  float bb = Sv[0] - A[0];
+// Compose this lane's P customers in order, then scan the 16-lane segment.
+template <int P>
+__device__ __forceinline__ ChunkScan compose_scan(const Draw<P> &dr) {
+  float a = dr.S[0];
+  float bb = dr.S[0] - dr.A[0];
 #pragma unroll
   for (int j = 1; j < P; ++j) {
-    const float bj = Sv[j] - A[j];
-    a = fmaxf(Sv[j], a + bj);
+    const float bj = dr.S[j] - dr.A[j];
+    a = fmaxf(dr.S[j], a + bj);
     bb = bb + bj;
   }
-
-  // inclusive scan over the 16-lane segment
 #define MRIP_SCAN_STEP(N)                              \
   {                                                    \
     const float as = row_shr<N>(a, kNegInf);           \
@@ -119,41 +110,59 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, con
   MRIP_SCAN_STEP(4)
   MRIP_SCAN_STEP(8)
 #undef MRIP_SCAN_STEP
-  const float ea = row_shr<1>(a, kNegInf);
-  const float eb = row_shr<1>(bb, 0.0f);
+  ChunkScan r;
+  r.ea = row_shr<1>(a, kNegInf);
+  r.eb = row_shr<1>(bb, 0.0f);
+  r.ta[0] = readlane_f(a, 15);
+  r.ta[1] = readlane_f(a, 31);
+  r.ta[2] = readlane_f(a, 47);
+  r.ta[3] = readlane_f(a, 63);
+  r.tb[0] = readlane_f(bb, 15);
+  r.tb[1] = readlane_f(bb, 31);
+  r.tb[2] = readlane_f(bb, 47);
+  r.tb[3] = readlane_f(bb, 63);
+  return r;
+}
 
-  // segment totals (lane 15 of every row) and the carry through the segments
-  const float ta0 = readlane_f(a, 15), ta1 = readlane_f(a, 31);
-  const float ta2 = readlane_f(a, 47), ta3 = readlane_f(a, 63);
-  const float tb0 = readlane_f(bb, 15), tb1 = readlane_f(bb, 31);
-  const float tb2 = readlane_f(bb, 47), tb3 = readlane_f(bb, 63);
-  float tin = carry, cur = carry;
+// Pass the carry through the replication's segments in order: returns the
+// carry after the chunk and sets `tin`, the carry into this lane's segment.
+template <int RPW>
+__device__ __forceinline__ float carry_through(const ChunkScan &cs, float carry, float &tin) {
+  constexpr int S = 4 / RPW;
+  const int row = (threadIdx.x & 63) >> 4;
+  const int q = row / S, s = row % S;
+  float cur = carry;
+  tin = carry;
 #pragma unroll
   for (int j = 0; j < S; ++j) {
     float ta, tb;
     if (RPW == 1) {
-      ta = j == 0 ? ta0 : j == 1 ? ta1 : j == 2 ? ta2 : ta3;
-      tb = j == 0 ? tb0 : j == 1 ? tb1 : j == 2 ? tb2 : tb3;
+      ta = cs.ta[j];
+      tb = cs.tb[j];
     } else {
-      ta = pick4(q * S + j, ta0, ta1, ta2, ta3);
-      tb = pick4(q * S + j, tb0, tb1, tb2, tb3);
+      ta = pick4(q * S + j, cs.ta[0], cs.ta[1], cs.ta[2], cs.ta[3]);
+      tb = pick4(q * S + j, cs.tb[0], cs.tb[1], cs.tb[2], cs.tb[3]);
     }
     tin = (j == s) ? cur : tin;
     cur = fmaxf(ta, cur + tb);
   }
-  carry = cur;
+  return cur;
+}
 
-  // the lane's customers, in order, from the system time before the first
-  float T = fmaxf(ea, tin + eb);
-  float sw = 0.0f, st = 0.0f, si = 0.0f;
-  const uint64_t n0 = 2 * kb;
+// The lane's P customers in order, from the system time T before the first;
+// sums of W, T and I (TAIL: only customers < n) and the prefix features.
+template <int P, bool FEAT, bool TAIL>
+__device__ __forceinline__ void apply_lane(float T, const Draw<P> &dr, uint64_t n0, uint64_t n,
+                                           uint64_t K, float &sw, float &st, float &si,
+                                           Feat &ft) {
+  sw = st = si = 0.0f;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const float W = fmaxf(0.0f, T - A[j]);
-    const float I = fmaxf(0.0f, A[j] - T);
-    T = W + Sv[j];
+    const float W = fmaxf(0.0f, T - dr.A[j]);
+    const float I = fmaxf(0.0f, dr.A[j] - T);
+    T = W + dr.S[j];
     if (TAIL) {
-      const bool v = n0 + j < d.n;
+      const bool v = n0 + j < n;
       sw += v ? W : 0.0f;
       st += v ? T : 0.0f;
       si += v ? I : 0.0f;
@@ -164,8 +173,8 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, con
     }
     if (FEAT) {
       const bool f = n0 + j < K;
-      ft.sa += f ? A[j] : 0.0f;
-      ft.ss += f ? Sv[j] : 0.0f;
+      ft.sa += f ? dr.A[j] : 0.0f;
+      ft.ss += f ? dr.S[j] : 0.0f;
       ft.sw += f ? W : 0.0f;
       ft.st += f ? T : 0.0f;
       ft.si += f ? I : 0.0f;
@@ -174,9 +183,52 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, con
       if (n0 + j + 1 == K) ft.tlast = T;
     }
   }
+}
+
+template <int RPW, int P>
+__device__ __forceinline__ uint64_t lane_first_customer(uint64_t base) {
+  constexpr int S = 4 / RPW;
+  const int lane = threadIdx.x & 63;
+  const int s = (lane >> 4) % S, l = lane & 15;
+  return base + (uint64_t)(16 * s + l) * P;
+}
+
+// One chunk: every segment of the replication takes 16 P customers, whose
+// variates are `dr`. FEAT accumulates the prefix features; TAIL masks
+// customers >= n (only chunks that reach past some replication's end need
+// it).
+template <int RPW, int P, bool FEAT, bool TAIL>
+__device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, const Rep &d,
+                                           uint64_t K, float &carry, Sums &acc, Feat &ft) {
+  const ChunkScan cs = compose_scan<P>(dr);
+  float tin;
+  carry = carry_through<RPW>(cs, carry, tin);
+  float sw, st, si;
+  apply_lane<P, FEAT, TAIL>(fmaxf(cs.ea, tin + cs.eb), dr, lane_first_customer<RPW, P>(base),
+                            d.n, K, sw, st, si, ft);
   acc.w.add(sw);
   acc.t.add(st);
   acc.i.add(si);
+}
+
+// Fix-up chunk of a split replication: the same customers from two carries
+// (the true one and the speculative one the part started from); adds the
+// difference of their sums.
+template <int P, bool TAIL>
+__device__ __forceinline__ void fixup_chunk(uint64_t base, const Draw<P> &dr, const Rep &d,
+                                            float &c_true, float &c_spec, Sums &acc) {
+  const ChunkScan cs = compose_scan<P>(dr);
+  float tin_t, tin_s;
+  c_true = carry_through<1>(cs, c_true, tin_t);
+  c_spec = carry_through<1>(cs, c_spec, tin_s);
+  const uint64_t n0 = lane_first_customer<1, P>(base);
+  Feat none;
+  float wt, tt, it, ws, ts, is;
+  apply_lane<P, false, TAIL>(fmaxf(cs.ea, tin_t + cs.eb), dr, n0, d.n, 0, wt, tt, it, none);
+  apply_lane<P, false, TAIL>(fmaxf(cs.ea, tin_s + cs.eb), dr, n0, d.n, 0, ws, ts, is, none);
+  acc.w.add(wt - ws);
+  acc.t.add(tt - ts);
+  acc.i.add(it - is);
 }
 
 // Runs the replications of one wavefront (RPW of them, one per lane group)
@@ -315,8 +367,126 @@ __global__ void mm1_plan_kernel(Mm1Args a, uint64_t n_items) {
   }
 }
 
+// Split replication: X wavefronts of one workgroup share each replication,
+// part h taking an equal run of its chunks. Every part first runs its chunks
+// from carry 0 (speculation; exact for part 0). Then, in order, each part h
+// re-runs its leading chunks from the true carry left by part h-1 alongside
+// the speculative one and adds the difference of their sums, until the two
+// carries are bit-identical: from there on the trajectories coincide (once a
+// chunk's composite map takes its constant branch for the larger carry it
+// takes it for the smaller one too), so the rest of the speculative pass is
+// already exact. Per-customer values equal the unsplit engine's; only the
+// summation order of the means differs. Part 0 keeps the feature chunks.
+template <int X>
+__global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, float cs) {
+  constexpr int P = MM1_P;
+  constexpr uint64_t CHUNK = 16u * P * 4;
+  constexpr int SLOTS = 4 / X;  // replications per 256-thread workgroup
+  __shared__ float sh_spec[SLOTS][X], sh_true[SLOTS][X];
+  __shared__ float sh_sum[SLOTS][X][3];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = wave / X, h = wave % X;
+  const uint64_t r = (uint64_t)blockIdx.x * SLOTS + slot;
+  const Rep d = uniform_rep(a, r, ca, cs);
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  const uint64_t K = a.feature_prefix;
+  const uint32_t chunks = (uint32_t)((d.n + CHUNK - 1) / CHUNK);
+  const uint32_t full = (uint32_t)(d.n / CHUNK);
+  const uint32_t fchunks = min(chunks, (uint32_t)((K + CHUNK - 1) / CHUNK));
+  const bool split = chunks / X >= 2 && chunks / X >= fchunks;
+  const uint32_t cb = split ? (uint32_t)((uint64_t)h * chunks / X) : (h == 0 ? 0u : chunks);
+  const uint32_t ce = split ? (uint32_t)((uint64_t)(h + 1) * chunks / X) : chunks;
+
+  // phase 1: every part from carry 0
+  float carry = 0.0f;
+  Sums acc;
+  Feat ft;
+  uint32_t c = cb;
+#define MRIP_CHUNK(F, TL)                                                          \
+  {                                                                                \
+    const Draw<P> dr = draw_chunk<1, P>((uint64_t)c * CHUNK, d, k0, k1);          \
+    wave_chunk<1, P, F, TL>((uint64_t)c * CHUNK, dr, d, K, carry, acc, ft);        \
+  }
+  for (; c < min(ce, fchunks); ++c) MRIP_CHUNK(true, true)
+  for (; c < min(ce, full); ++c) MRIP_CHUNK(false, false)
+  for (; c < ce; ++c) MRIP_CHUNK(false, true)
+#undef MRIP_CHUNK
+  if (lane == 0) sh_spec[slot][h] = carry;
+  __syncthreads();
+
+  // phase 2: parts 1..X-1 in order correct their leading chunks
+#pragma unroll
+  for (int j = 1; j < X; ++j) {
+    if (h == j && cb < ce) {
+      float ct = j == 1 ? sh_spec[slot][0] : sh_true[slot][j - 1];
+      float cspec = 0.0f;
+      bool coupled = false;
+      for (c = cb; c < ce && !coupled; ++c) {
+        const Draw<P> dr = draw_chunk<1, P>((uint64_t)c * CHUNK, d, k0, k1);
+        if (c < full) fixup_chunk<P, false>((uint64_t)c * CHUNK, dr, d, ct, cspec, acc);
+        else fixup_chunk<P, true>((uint64_t)c * CHUNK, dr, d, ct, cspec, acc);
+        coupled = __builtin_amdgcn_readfirstlane((int)(__float_as_uint(ct) == __float_as_uint(cspec))) != 0;
+      }
+      if (lane == 0) sh_true[slot][j] = coupled ? sh_spec[slot][j] : ct;
+    }
+    __syncthreads();
+  }
+
+  // phase 3: part sums, then the replication's means in part order
+  const float sw = group_sum_compensated(acc.w.value(), 64);
+  const float st = group_sum_compensated(acc.t.value(), 64);
+  const float si = group_sum_compensated(acc.i.value(), 64);
+  float f[10];
+  if (h == 0 && K > 0) {
+    const float kf = (float)K;
+    f[0] = d.lambda / d.mu;
+    f[1] = d.mu;
+    f[2] = group_sum_compensated(ft.sa, 64) / kf;
+    f[3] = group_sum_compensated(ft.ss, 64) / kf;
+    f[4] = group_sum_compensated(ft.sw, 64) / kf;
+    f[5] = group_sum_compensated(ft.st, 64) / kf;
+    f[6] = (float)group_sum_i(ft.zeros, 64) / kf;
+    f[7] = group_max(ft.wmax, 64);
+    f[8] = group_sum_compensated(ft.si, 64) / kf;
+    f[9] = group_sum_compensated(ft.tlast, 64);
+  }
+  if (lane == 0) {
+    sh_sum[slot][h][0] = sw;
+    sh_sum[slot][h][1] = st;
+    sh_sum[slot][h][2] = si;
+  }
+  __syncthreads();
+  if (h == 0 && lane == 0 && d.n > 0) {
+    float tot[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float hi = sh_sum[slot][0][k], lo = 0.0f;
+#pragma unroll
+      for (int j = 1; j < X; ++j) {
+        float s2, e;
+        two_sum(hi, sh_sum[slot][j][k], s2, e);
+        hi = s2;
+        lo += e;
+      }
+      tot[k] = hi + lo;
+    }
+    const float nf = (float)d.n;
+    a.mean_w[d.out] = tot[0] / nf;
+    a.mean_t[d.out] = tot[1] / nf;
+    a.mean_i[d.out] = tot[2] / nf;
+    if (K > 0) {
+#pragma unroll
+      for (int j = 0; j < 10; ++j) a.features[d.out * 10 + j] = f[j];
+    }
+  }
+}
+
+// STRIDE = 1: one replication per lane; 64: one working lane per wavefront
+// (the paper's WLP form).
+template <int STRIDE>
 __global__ void mm1_simt_kernel(Mm1Args a, float ca, float cs) {
-  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x % STRIDE) return;
+  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
   if (r >= a.n_reps) return;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   const uint64_t N = a.customers, K = a.feature_prefix;
@@ -391,11 +561,23 @@ hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t rpw, uint32_t wg, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_mm1_simt(const Mm1Args &a, hipStream_t s) {
-  const uint32_t wg = 64;
-  const uint64_t blocks = (a.n_reps + wg - 1) / wg;
+hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s) {
   const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
-  hipLaunchKernelGGL(mm1_simt_kernel, dim3((uint32_t)blocks), dim3(wg), 0, s, a, ca, cs);
+  const uint32_t slots = 4 / waves_per_rep;
+  const uint64_t blocks = (a.n_reps + slots - 1) / slots;
+  if (waves_per_rep == 2) hipLaunchKernelGGL(mm1_split_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, s, a, ca, cs);
+  else if (waves_per_rep == 4) hipLaunchKernelGGL(mm1_split_kernel<4>, dim3((uint32_t)blocks), dim3(256), 0, s, a, ca, cs);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s) {
+  const uint32_t wg = 64;
+  const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
+  const uint64_t blocks = (threads + wg - 1) / wg;
+  const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
+  if (one_lane) hipLaunchKernelGGL(mm1_simt_kernel<64>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, ca, cs);
+  else hipLaunchKernelGGL(mm1_simt_kernel<1>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, ca, cs);
   return hipGetLastError();
 }
 

@@ -7,7 +7,8 @@
 //
 // SIMT mapping: one replication per lane; the lane walks its walkers one
 // after the other and keeps the replication's bitmap in global memory, the
-// per-thread state the paper's thread-per-replication form implies.
+// per-thread state the paper's thread-per-replication form implies. The
+// same kernel with one working lane per wavefront is the paper's own WLP.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -73,10 +74,14 @@ __global__ void rw_wave_kernel(RwArgs a) {
   }
 }
 
-template <int GRID>
+// STRIDE = 1: one replication per lane. STRIDE = 64: one replication per
+// wavefront with only its first lane working (the paper's WLP form, 63 of
+// 64 lanes idle).
+template <int GRID, int STRIDE>
 __global__ void rw_simt_kernel(RwArgs a) {
   constexpr int WORDS = GRID * GRID / 32;
-  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x % STRIDE) return;
+  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
   if (r >= a.n_reps) return;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   uint32_t *bm = a.scratch_bitmaps + r * WORDS;
@@ -123,10 +128,12 @@ hipError_t wave_launch(const RwArgs &a, uint32_t wg, hipStream_t s) {
 }
 
 template <int GRID>
-hipError_t simt_launch(const RwArgs &a, hipStream_t s) {
+hipError_t simt_launch(const RwArgs &a, bool one_lane, hipStream_t s) {
   const uint32_t wg = 64;
-  const uint64_t blocks = (a.n_reps + wg - 1) / wg;
-  hipLaunchKernelGGL(rw_simt_kernel<GRID>, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
+  const uint64_t blocks = (threads + wg - 1) / wg;
+  if (one_lane) hipLaunchKernelGGL((rw_simt_kernel<GRID, 64>), dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  else hipLaunchKernelGGL((rw_simt_kernel<GRID, 1>), dim3((uint32_t)blocks), dim3(wg), 0, s, a);
   return hipGetLastError();
 }
 
@@ -142,12 +149,12 @@ hipError_t launch_rw_wave(const RwArgs &a, uint32_t wg, hipStream_t s) {
   }
 }
 
-hipError_t launch_rw_simt(const RwArgs &a, hipStream_t s) {
+hipError_t launch_rw_simt(const RwArgs &a, bool one_lane, hipStream_t s) {
   switch (a.grid) {
-    case 16: return simt_launch<16>(a, s);
-    case 32: return simt_launch<32>(a, s);
-    case 64: return simt_launch<64>(a, s);
-    case 128: return simt_launch<128>(a, s);
+    case 16: return simt_launch<16>(a, one_lane, s);
+    case 32: return simt_launch<32>(a, one_lane, s);
+    case 64: return simt_launch<64>(a, one_lane, s);
+    case 128: return simt_launch<128>(a, one_lane, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmrip.so")
 MRIP_OK, MRIP_E_INVAL, MRIP_E_NOMEM, MRIP_E_HIP, MRIP_E_STATE, MRIP_E_TOO_FEW, \
     MRIP_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MRIP_RW, MRIP_MM1, MRIP_FF = 1, 2, 3
-MRIP_MAP_AUTO, MRIP_MAP_SIMT, MRIP_MAP_WAVE = 0, 1, 2
+MRIP_MAP_AUTO, MRIP_MAP_SIMT, MRIP_MAP_WAVE, MRIP_MAP_LANE0 = 0, 1, 2, 3
 MRIP_MLP_PARAMS = 18049
 MRIP_CV_BETA_BINS = 16
 
@@ -70,6 +70,7 @@ _SIGS = {
     "mrip_create": (st, [C.POINTER(ctx_t), C.c_int, vp, C.c_int]),
     "mrip_destroy": (None, [ctx_t]),
     "mrip_set_shape": (st, [ctx_t, u32, u32]),
+    "mrip_set_split": (st, [ctx_t, u32]),
     "mrip_run": (st, [ctx_t, u64, u64, vp]),
     "mrip_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t)]),
     "mrip_outputs": (st, [ctx_t, u32, vp, u64, C.c_int]),
@@ -172,6 +173,10 @@ def mrip_destroy(ctx):
 
 def mrip_set_shape(ctx, reps_per_wave, workgroup):
     check(load().mrip_set_shape(ctx, reps_per_wave, workgroup), ctx)
+
+
+def mrip_set_split(ctx, waves_per_rep):
+    check(load().mrip_set_split(ctx, waves_per_rep), ctx)
 
 
 def mrip_run(ctx, n_reps, seed, stream=None):
@@ -351,6 +356,9 @@ class Context:
 
     def set_shape(self, reps_per_wave, workgroup):
         mrip_set_shape(self.ctx, reps_per_wave, workgroup)
+
+    def set_split(self, waves_per_rep):
+        mrip_set_split(self.ctx, waves_per_rep)
 
     def run(self, n_reps, seed=42, stream=None):
         mrip_run(self.ctx, n_reps, seed, current_stream() if stream is None else stream)

@@ -3,7 +3,7 @@ import numpy as np
 
 from paper_1501_01405_amd import mrip
 
-SIMT, WAVE = mrip.MRIP_MAP_SIMT, mrip.MRIP_MAP_WAVE
+SIMT, WAVE, LANE0 = mrip.MRIP_MAP_SIMT, mrip.MRIP_MAP_WAVE, mrip.MRIP_MAP_LANE0
 
 
 def rel_err(got, ref, floor=1e-6):

@@ -79,6 +79,8 @@ def test_parameter_validation():
     p.size = 4
     assert _create(mrip.MRIP_RW, p) == bad
     assert _create(7, mrip.rw_params()) == bad
+    assert _create(mrip.MRIP_RW, mrip.rw_params(), mrip.MRIP_MAP_LANE0) == ok
+    assert _create(mrip.MRIP_RW, mrip.rw_params(), 9) == bad
 
 
 def test_calls_out_of_order_and_bad_shapes():
@@ -91,6 +93,11 @@ def test_calls_out_of_order_and_bad_shapes():
     assert L.mrip_set_shape(ctx, 3, 256) == mrip.MRIP_E_INVAL
     assert L.mrip_set_shape(ctx, 2, 128) == mrip.MRIP_E_INVAL
     assert L.mrip_set_shape(ctx, 4, 1024) == mrip.MRIP_OK
+    assert L.mrip_set_split(ctx, 2) == mrip.MRIP_E_INVAL  # needs reps_per_wave = 1
+    assert L.mrip_set_shape(ctx, 1, 256) == mrip.MRIP_OK
+    assert L.mrip_set_split(ctx, 3) == mrip.MRIP_E_INVAL
+    assert L.mrip_set_split(ctx, 4) == mrip.MRIP_OK
+    assert L.mrip_set_shape(ctx, 2, 256) == mrip.MRIP_E_INVAL
     assert L.mrip_run_plan(ctx, 42, None) == mrip.MRIP_E_STATE
     assert L.mrip_plan_stats(ctx, 0, 0.95, C.byref(s)) == mrip.MRIP_E_STATE
     assert b"no" in L.mrip_last_error(ctx)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import SIMT, WAVE, announce
+from gpu_util import LANE0, SIMT, WAVE, announce
 from oracle import core
 from oracle import stats as ostats
 from paper_1501_01405_amd import mrip
@@ -33,7 +33,7 @@ RW_CASES = [(64, 64, 1000, 32), (1, 16, 7, 5), (37, 128, 130, 9), (64, 32, 64, 7
             (8, 64, 1, 3)]
 
 
-@pytest.mark.parametrize("mapping", [SIMT, WAVE])
+@pytest.mark.parametrize("mapping", [SIMT, WAVE, LANE0])
 @pytest.mark.parametrize("walkers,grid,steps,reps", RW_CASES)
 def test_rw_bit_exact(gpu, mapping, walkers, grid, steps, reps):
     announce("rw", mapping, walkers, grid, steps, reps)

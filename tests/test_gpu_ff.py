@@ -4,7 +4,7 @@ bit-exact, both mappings, several grid sizes, and the full 4096-replication
 import numpy as np
 import pytest
 
-from gpu_util import SIMT, WAVE, announce
+from gpu_util import LANE0, SIMT, WAVE, announce
 from oracle import core
 from paper_1501_01405_amd import mrip
 
@@ -20,7 +20,7 @@ def _run(mapping, grid, steps, R, p, f, seed=42, wg=256):
 
 
 @pytest.mark.parametrize("mapping,grid", [(WAVE, 128), (WAVE, 64), (SIMT, 128), (SIMT, 96),
-                                          (SIMT, 32)])
+                                          (SIMT, 32), (LANE0, 128)])
 def test_ff_bit_exact_busy_fire(gpu, mapping, grid):
     # high growth and lightning so that every rule fires within a few steps
     announce("ff", mapping, grid)

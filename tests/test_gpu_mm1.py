@@ -5,7 +5,7 @@ configuration on sampled replications."""
 import numpy as np
 import pytest
 
-from gpu_util import SIMT, WAVE, announce, rel_err
+from gpu_util import LANE0, SIMT, WAVE, announce, rel_err
 from oracle import core
 from oracle import stats as ostats
 from paper_1501_01405_amd import mrip
@@ -13,7 +13,8 @@ from paper_1501_01405_amd import mrip
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-SHAPES = [(SIMT, 1, 64), (WAVE, 1, 256), (WAVE, 2, 64), (WAVE, 4, 1024), (WAVE, 1, 1024)]
+SHAPES = [(SIMT, 1, 64), (WAVE, 1, 256), (WAVE, 2, 64), (WAVE, 4, 1024), (WAVE, 1, 1024),
+          (LANE0, 1, 64)]
 RUNS = [(1, 3, 0.9), (2, 5, 0.9), (31, 7, 0.5), (33, 9, 0.9), (129, 5, 0.7), (1000, 40, 0.95),
         (12345, 16, 0.9)]
 
@@ -87,6 +88,14 @@ def test_mm1_shape_invariance(gpu):
             assert rel_err(got, base).max() <= 1e-6
 
 
+def test_mm1_lane0_equals_simt(gpu):
+    # the paper's one-working-lane form runs the SIMT code on one lane per wave
+    announce("mm1 lane0 vs simt")
+    a = _run(SIMT, 1, 64, 0.9, 2345, 70)[1]
+    b = _run(LANE0, 1, 64, 0.9, 2345, 70)[1]
+    assert np.array_equal(a, b)
+
+
 def test_mm1_prefix_and_repeat(gpu):
     announce("mm1 prefix/repeat")
     a = _run(WAVE, 1, 256, 0.9, 3000, 100)[1]
@@ -94,3 +103,31 @@ def test_mm1_prefix_and_repeat(gpu):
     c = _run(WAVE, 1, 256, 0.9, 3000, 13)[1]
     assert np.array_equal(a, b)
     assert np.array_equal(a[:13], c)
+
+
+@pytest.mark.parametrize("split", [2, 4])
+@pytest.mark.parametrize("N,R,lam", [(100000, 40, 0.9), (20000, 33, 0.95), (3000, 9, 0.5),
+                                     (1500, 5, 0.9), (50000, 6, 1.3)])
+def test_mm1_split_matches_unsplit_and_oracle(gpu, split, N, R, lam):
+    # lambda = 1.3: an unstable queue never empties, so the correction
+    # re-runs whole parts; short runs fall back to one part
+    announce("mm1 split", split, N, R, lam)
+    base = _run(WAVE, 1, 256, lam, N, R)[1]
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(lam, 1.0, N), WAVE)
+    ctx.set_split(split)
+    ctx.run(R, seed=42)
+    got = np.stack([ctx.output(o).cpu().numpy() for o in range(3)], axis=1)
+    assert rel_err(got, base).max() <= 1e-6
+    ref = core.mm1_many(42, R, N, lam, 1.0, threads=core.default_threads())
+    assert rel_err(got, ref).max() <= TOL
+
+
+def test_mm1_split_features(gpu):
+    announce("mm1 split features")
+    K, N, R = 1000, 40000, 12
+    base = _run(WAVE, 1, 256, 0.9, N, R, K=K)
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, N, K), WAVE)
+    ctx.set_split(2)
+    ctx.run(R, seed=42)
+    assert np.array_equal(ctx.output(3).cpu().numpy(), base[2])
+    assert rel_err(ctx.output(0).cpu().numpy(), base[1][:, 0]).max() <= 1e-6
