@@ -204,9 +204,25 @@ MRIP_API mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream
  * last plan run. Synchronises. */
 MRIP_API mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_stats_t *out);
 
-/* Time every (reps_per_wave, workgroup) in {1,2,4} x {64,256,1024} on the
- * uploaded plan (or on its first `calib_items` items, 0 = all), keep the
- * fastest as the context's shape and report it. Synchronises. */
+/* Plans: items of at least long_min customers (0 = 65536) are each split
+ * over waves_per_item (1, 2 or 4) wavefronts of a workgroup, served first
+ * (longest first) at raised wavefront priority, since the longest items set
+ * the plan's makespan; the rest go reps_per_wave per wavefront. Default 4. */
+MRIP_API mrip_status mrip_set_plan_split(mrip_ctx ctx, uint32_t waves_per_item,
+                                         uint64_t long_min);
+
+/* Current launch shape: reps_per_wave, workgroup, wavefronts per
+ * replication of mrip_run, wavefronts per long plan item (any may be NULL). */
+MRIP_API mrip_status mrip_get_shape(mrip_ctx ctx, uint32_t *reps_per_wave, uint32_t *workgroup,
+                                    uint32_t *split, uint32_t *plan_split);
+
+/* Time every (reps_per_wave, workgroup) in {1,2,4} x {64,256,1024}, and,
+ * when the plan has long items, every reps_per_wave with long items split
+ * over 2 or 4 wavefronts (workgroup 256), on the uploaded plan (or on an
+ * evenly strided slice of `calib_items` items of its longest-first order,
+ * 0 = all); keep the fastest as the context's plan shape and report its
+ * reps_per_wave, workgroup and time (mrip_get_shape gives the split).
+ * Synchronises. */
 MRIP_API mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, void *hip_stream,
                           uint32_t *best_rpw, uint32_t *best_workgroup, float *best_ms);
 

@@ -203,6 +203,26 @@ mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep) {
   return MRIP_OK;
 }
 
+mrip_status mrip_set_plan_split(mrip_ctx ctx, uint32_t waves_per_item, uint64_t long_min) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (waves_per_item != 1 && waves_per_item != 2 && waves_per_item != 4)
+    return inval(ctx, "waves_per_item must be 1, 2 or 4");
+  if (ctx->model != MRIP_MM1) return inval(ctx, "plans are defined for the M/M/1 engine");
+  ctx->plan_split = waves_per_item;
+  ctx->long_min = long_min > 0 ? long_min : 65536;
+  return MRIP_OK;
+}
+
+mrip_status mrip_get_shape(mrip_ctx ctx, uint32_t *rpw, uint32_t *wg, uint32_t *split,
+                           uint32_t *plan_split) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (rpw) *rpw = ctx->rpw;
+  if (wg) *wg = ctx->wg;
+  if (split) *split = ctx->split;
+  if (plan_split) *plan_split = ctx->plan_split;
+  return MRIP_OK;
+}
+
 mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_stream) {
   if (!ctx) return MRIP_E_INVAL;
   if (n_reps == 0) return inval(ctx, "n_reps must be >= 1");
@@ -397,11 +417,21 @@ mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n)
   HIP_TRY(ctx, hipMemcpy(ctx->dp_offsets.p, offsets.data(), 8 * offsets.size(), hipMemcpyHostToDevice));
   ctx->n_items = n;
   ctx->dp_ids = ids;
+  ctx->lpt_customers.resize(n);
+  for (uint64_t j = 0; j < n; ++j) ctx->lpt_customers[j] = cust[order[j]];
   return MRIP_OK;
 }
 
+// Items of a longest-first order that count as long (a prefix of it).
+static uint64_t count_long(const std::vector<uint64_t> &lpt, uint64_t n, uint64_t long_min) {
+  uint64_t k = 0;
+  while (k < n && lpt[k] >= long_min) ++k;
+  return k;
+}
+
 static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, const uint32_t *order,
-                                 uint64_t n, uint32_t rpw, uint32_t wg, bool reduce) {
+                                 uint64_t n, uint64_t n_long, uint32_t rpw, uint32_t wg,
+                                 uint32_t split, bool reduce) {
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
   for (uint32_t o = 0; o < 3; ++o) HIP_TRY(ctx, ctx->out[o].ensure(ctx->n_items * 4));
@@ -423,10 +453,11 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
   a.mean_w = ctx->out[0].as<float>();
   a.mean_t = ctx->out[1].as<float>();
   a.mean_i = ctx->out[2].as<float>();
-  HIP_TRY(ctx, launch_zero_u32(a.queue_head, 1, s));
+  HIP_TRY(ctx, launch_zero_u32(a.queue_head, 2, s));
   st = record_begin(ctx, s);
   if (st != MRIP_OK) return st;
-  HIP_TRY(ctx, launch_mm1_plan(a, n, rpw, wg, s));
+  if (split > 1 && n_long > 0) HIP_TRY(ctx, launch_mm1_plan_split(a, n, n_long, split, rpw, s));
+  else HIP_TRY(ctx, launch_mm1_plan(a, n, rpw, wg, s));
   st = record_end(ctx, s);
   if (st != MRIP_OK) return st;
   if (reduce) {
@@ -446,8 +477,9 @@ mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
   if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
   if (ctx->mapping != MRIP_MAP_WAVE)
     return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
+  const uint64_t n_long = count_long(ctx->lpt_customers, ctx->n_items, ctx->long_min);
   mrip_status st = run_plan_impl(ctx, seed, (hipStream_t)hip_stream, ctx->it_order.as<uint32_t>(),
-                                 ctx->n_items, ctx->rpw, ctx->wg, true);
+                                 ctx->n_items, n_long, ctx->rpw, ctx->wg, ctx->plan_split, true);
   if (st != MRIP_OK) return st;
   ctx->last = RUN_PLAN;
   ctx->last_n = ctx->n_items;
@@ -490,27 +522,42 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
     order = sub.as<uint32_t>();
     n = pick.size();
   }
-  const uint32_t rpws[3] = {1, 2, 4}, wgs[3] = {64, 256, 1024};
+  // the slice's lengths in longest-first order decide which items are long
+  std::vector<uint64_t> lpt(n);
+  if (n == ctx->n_items) {
+    lpt = ctx->lpt_customers;
+  } else {
+    const double stride = (double)ctx->n_items / (double)n;
+    for (uint64_t j = 0; j < n; ++j) lpt[j] = ctx->lpt_customers[(uint64_t)(j * stride)];
+  }
+  const uint64_t n_long = count_long(lpt, n, ctx->long_min);
+  struct Shape { uint32_t rpw, wg, split; };
+  std::vector<Shape> shapes;
+  for (uint32_t r : {1u, 2u, 4u})
+    for (uint32_t w : {64u, 256u, 1024u}) shapes.push_back({r, w, 1});
+  if (n_long > 0)
+    for (uint32_t r : {1u, 2u, 4u})
+      for (uint32_t x : {2u, 4u}) shapes.push_back({r, 256u, x});
   float best = 1e30f;
-  uint32_t br = ctx->rpw, bw = ctx->wg;
-  for (uint32_t r : rpws) {
-    for (uint32_t w : wgs) {
-      float t_min = 1e30f;
-      for (int rep = 0; rep < 3; ++rep) {  // first launch warms up
-        mrip_status st = run_plan_impl(ctx, seed, s, order, n, r, w, false);
-        if (st != MRIP_OK) return st;
-        HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
-        float ms = 0.f;
-        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        if (rep > 0) t_min = std::min(t_min, ms);
-      }
-      if (t_min < best) {
-        best = t_min;
-        br = r;
-        bw = w;
-      }
+  uint32_t br = ctx->rpw, bw = ctx->wg, bx = ctx->plan_split;
+  for (const Shape &sh : shapes) {
+    float t_min = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {  // the first launch warms up
+      mrip_status st = run_plan_impl(ctx, seed, s, order, n, n_long, sh.rpw, sh.wg, sh.split, false);
+      if (st != MRIP_OK) return st;
+      HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      if (rep > 0) t_min = std::min(t_min, ms);
+    }
+    if (t_min < best) {
+      best = t_min;
+      br = sh.rpw;
+      bw = sh.wg;
+      bx = sh.split;
     }
   }
+  ctx->plan_split = bx;
   ctx->rpw = br;
   ctx->wg = bw;
   ctx->last = RUN_NONE;  // outputs of the timing runs are partial

@@ -85,6 +85,9 @@ struct mrip_ctx_s {
   mrip_ff_params ff;
   uint32_t rpw = 1, wg = 256;
   uint32_t split = 1;  // wavefronts per M/M/1 replication in mrip_run
+  // plans: wavefronts per long item (1 = none) and what counts as long
+  uint32_t plan_split = 4;
+  uint64_t long_min = 65536;
 
   mrip::DevBuf out[4];
   mrip::DevBuf scratch;
@@ -100,7 +103,8 @@ struct mrip_ctx_s {
   std::string err;
 
   // plan
-  uint64_t n_items = 0;
+  uint64_t n_items = 0, n_long = 0;
+  std::vector<uint64_t> lpt_customers;  // customers in longest-first order
   mrip::DevBuf it_dp, it_rep, it_n, it_lambda, it_mu, it_order, queue, dp_index, dp_offsets,
       dp_stats;
   std::vector<uint32_t> dp_ids;

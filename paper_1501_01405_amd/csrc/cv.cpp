@@ -132,7 +132,7 @@ mrip_status run_items(mrip_ctx c, ItemBufs &b, uint64_t seed, uint64_t K, float 
     CV_TRY(c, hipEventCreate(&e0));
     CV_TRY(c, hipEventCreate(&e1));
   }
-  CV_TRY(c, launch_zero_u32(a.queue_head, 1, s));
+  CV_TRY(c, launch_zero_u32(a.queue_head, 2, s));
   if (ms) CV_TRY(c, hipEventRecord(e0, s));
   // short replications (prefix-only runs) share a wavefront four at a time
   const uint32_t rpw = b.max_customers <= 4096 ? 4u : c->rpw;

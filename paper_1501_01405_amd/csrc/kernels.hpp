@@ -47,6 +47,11 @@ hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_
 // Persistent plan kernel: grid sized to full residency, waves pop work.
 hipError_t launch_mm1_plan(const Mm1Args &a, uint64_t n_items, uint32_t reps_per_wave,
                            uint32_t workgroup, hipStream_t s);
+// Plan kernel whose first n_long items (longest first) are each split over
+// waves_per_rep (2 or 4) wavefronts of a 256-thread workgroup; the rest go
+// rpw per wavefront. queue_head[0..1] must be zero at launch.
+hipError_t launch_mm1_plan_split(const Mm1Args &a, uint64_t n_items, uint64_t n_long,
+                                 uint32_t waves_per_rep, uint32_t rpw, hipStream_t s);
 // Zero the queue head with a one-thread kernel (no memset node in graphs).
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s);
 

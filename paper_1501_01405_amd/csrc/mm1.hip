@@ -378,18 +378,19 @@ __global__ void mm1_plan_kernel(Mm1Args a, uint64_t n_items) {
 // already exact. Per-customer values equal the unsplit engine's; only the
 // summation order of the means differs. Part 0 keeps the feature chunks.
 template <int X>
-__global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, float cs) {
+struct SplitShared {
+  float spec[4 / X][X], truth[4 / X][X];
+  float sum[4 / X][X][3];
+};
+
+// Part h of replication d (slot `slot` of the workgroup); every thread of
+// the 256-thread workgroup must call it (it holds X + 1 barriers).
+template <int X>
+__device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, uint32_t k1,
+                                  uint64_t K, const Mm1Args &a, SplitShared<X> &sh) {
   constexpr int P = MM1_P;
   constexpr uint64_t CHUNK = 16u * P * 4;
-  constexpr int SLOTS = 4 / X;  // replications per 256-thread workgroup
-  __shared__ float sh_spec[SLOTS][X], sh_true[SLOTS][X];
-  __shared__ float sh_sum[SLOTS][X][3];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int slot = wave / X, h = wave % X;
-  const uint64_t r = (uint64_t)blockIdx.x * SLOTS + slot;
-  const Rep d = uniform_rep(a, r, ca, cs);
-  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-  const uint64_t K = a.feature_prefix;
+  const int lane = threadIdx.x & 63;
   const uint32_t chunks = (uint32_t)((d.n + CHUNK - 1) / CHUNK);
   const uint32_t full = (uint32_t)(d.n / CHUNK);
   const uint32_t fchunks = min(chunks, (uint32_t)((K + CHUNK - 1) / CHUNK));
@@ -411,14 +412,14 @@ __global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, flo
   for (; c < min(ce, full); ++c) MRIP_CHUNK(false, false)
   for (; c < ce; ++c) MRIP_CHUNK(false, true)
 #undef MRIP_CHUNK
-  if (lane == 0) sh_spec[slot][h] = carry;
+  if (lane == 0) sh.spec[slot][h] = carry;
   __syncthreads();
 
   // phase 2: parts 1..X-1 in order correct their leading chunks
 #pragma unroll
   for (int j = 1; j < X; ++j) {
     if (h == j && cb < ce) {
-      float ct = j == 1 ? sh_spec[slot][0] : sh_true[slot][j - 1];
+      float ct = j == 1 ? sh.spec[slot][0] : sh.truth[slot][j - 1];
       float cspec = 0.0f;
       bool coupled = false;
       for (c = cb; c < ce && !coupled; ++c) {
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, flo
         else fixup_chunk<P, true>((uint64_t)c * CHUNK, dr, d, ct, cspec, acc);
         coupled = __builtin_amdgcn_readfirstlane((int)(__float_as_uint(ct) == __float_as_uint(cspec))) != 0;
       }
-      if (lane == 0) sh_true[slot][j] = coupled ? sh_spec[slot][j] : ct;
+      if (lane == 0) sh.truth[slot][j] = coupled ? sh.spec[slot][j] : ct;
     }
     __syncthreads();
   }
@@ -451,20 +452,20 @@ __global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, flo
     f[9] = group_sum_compensated(ft.tlast, 64);
   }
   if (lane == 0) {
-    sh_sum[slot][h][0] = sw;
-    sh_sum[slot][h][1] = st;
-    sh_sum[slot][h][2] = si;
+    sh.sum[slot][h][0] = sw;
+    sh.sum[slot][h][1] = st;
+    sh.sum[slot][h][2] = si;
   }
   __syncthreads();
   if (h == 0 && lane == 0 && d.n > 0) {
     float tot[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float hi = sh_sum[slot][0][k], lo = 0.0f;
+      float hi = sh.sum[slot][0][k], lo = 0.0f;
 #pragma unroll
       for (int j = 1; j < X; ++j) {
         float s2, e;
-        two_sum(hi, sh_sum[slot][j][k], s2, e);
+        two_sum(hi, sh.sum[slot][j][k], s2, e);
         hi = s2;
         lo += e;
       }
@@ -478,6 +479,59 @@ __global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, flo
 #pragma unroll
       for (int j = 0; j < 10; ++j) a.features[d.out * 10 + j] = f[j];
     }
+  }
+}
+
+template <int X>
+__global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, float cs) {
+  constexpr int SLOTS = 4 / X;  // replications per 256-thread workgroup
+  __shared__ SplitShared<X> sh;
+  const int wave = threadIdx.x >> 6;
+  const int slot = wave / X, h = wave % X;
+  const uint64_t r = (uint64_t)blockIdx.x * SLOTS + slot;
+  split_replication<X>(uniform_rep(a, r, ca, cs), slot, h, (uint32_t)a.seed,
+                       (uint32_t)(a.seed >> 32), a.feature_prefix, a, sh);
+}
+
+// Persistent plan kernel with the long items split: the first n_long items
+// of the longest-first order are served one per X wavefronts of a workgroup
+// (queue_head[0]), at raised wave priority so that the critical path keeps
+// its issue slots when it shares a SIMD; then every wavefront serves the
+// rest RPW items at a time (queue_head[1]). Both exits are uniform (the
+// first per workgroup, the second per wavefront), so the grid drains.
+template <int X, int RPW>
+__global__ __launch_bounds__(256) void mm1_plan_split_kernel(Mm1Args a, uint64_t n_items,
+                                                             uint64_t n_long) {
+  constexpr int SLOTS = 4 / X;
+  constexpr int S = 4 / RPW;
+  __shared__ SplitShared<X> sh;
+  __shared__ uint32_t sh_pop;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = wave / X, h = wave % X;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  __builtin_amdgcn_s_setprio(2);
+  for (;;) {
+    if (threadIdx.x == 0) sh_pop = atomicAdd(&a.queue_head[0], (uint32_t)SLOTS);
+    __syncthreads();
+    const uint64_t first = sh_pop;
+    __syncthreads();
+    if (first >= n_long) break;
+    const uint64_t idx = first + slot;
+    const Rep d = item_rep(a, idx, idx < n_long ? n_long : 0);
+    split_replication<X>(d, slot, h, k0, k1, a.feature_prefix, a, sh);
+  }
+  __builtin_amdgcn_s_setprio(0);
+  const int q = (lane >> 4) / S;
+  const uint64_t n_short = n_items - n_long;
+  const uint64_t n_units = (n_short + RPW - 1) / RPW;
+  for (;;) {
+    uint32_t unit = 0;
+    if (lane == 0) unit = atomicAdd(&a.queue_head[1], 1u);
+    unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)unit, 0, 64));
+    if (unit >= n_units) break;
+    const uint64_t j = (uint64_t)unit * RPW + q;
+    wave_group<RPW>(item_rep(a, n_long + j, j < n_short ? n_items : 0), k0, k1,
+                    a.feature_prefix, a);
   }
 }
 
@@ -603,6 +657,27 @@ hipError_t launch_mm1_plan(const Mm1Args &a, uint64_t n_items, uint32_t rpw, uin
   if (rpw == 1) hipLaunchKernelGGL(mm1_plan_kernel<1>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, n_items);
   else if (rpw == 2) hipLaunchKernelGGL(mm1_plan_kernel<2>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, n_items);
   else hipLaunchKernelGGL(mm1_plan_kernel<4>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_mm1_plan_split(const Mm1Args &a, uint64_t n_items, uint64_t n_long,
+                                 uint32_t waves_per_rep, uint32_t rpw, hipStream_t s) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+#define MRIP_PICK(X, R) (const void *)mm1_plan_split_kernel<X, R>
+  const void *fn = waves_per_rep == 2 ? (rpw == 1 ? MRIP_PICK(2, 1) : rpw == 2 ? MRIP_PICK(2, 2) : MRIP_PICK(2, 4))
+                                      : (rpw == 1 ? MRIP_PICK(4, 1) : rpw == 2 ? MRIP_PICK(4, 2) : MRIP_PICK(4, 4));
+#undef MRIP_PICK
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  const uint64_t blocks = (uint64_t)cus * (uint64_t)per_cu;
+  void *args[] = {(void *)&a, (void *)&n_items, (void *)&n_long};
+  e = hipLaunchKernel(fn, dim3((uint32_t)blocks), dim3(256), args, 0, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

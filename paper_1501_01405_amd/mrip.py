@@ -71,6 +71,9 @@ _SIGS = {
     "mrip_destroy": (None, [ctx_t]),
     "mrip_set_shape": (st, [ctx_t, u32, u32]),
     "mrip_set_split": (st, [ctx_t, u32]),
+    "mrip_set_plan_split": (st, [ctx_t, u32, u64]),
+    "mrip_get_shape": (st, [ctx_t, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32),
+                            C.POINTER(u32)]),
     "mrip_run": (st, [ctx_t, u64, u64, vp]),
     "mrip_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t)]),
     "mrip_outputs": (st, [ctx_t, u32, vp, u64, C.c_int]),
@@ -177,6 +180,18 @@ def mrip_set_shape(ctx, reps_per_wave, workgroup):
 
 def mrip_set_split(ctx, waves_per_rep):
     check(load().mrip_set_split(ctx, waves_per_rep), ctx)
+
+
+def mrip_set_plan_split(ctx, waves_per_item, long_min=0):
+    check(load().mrip_set_plan_split(ctx, waves_per_item, long_min), ctx)
+
+
+def mrip_get_shape(ctx):
+    """dict(reps_per_wave, workgroup, split, plan_split)."""
+    v = [u32() for _ in range(4)]
+    check(load().mrip_get_shape(ctx, *[C.byref(x) for x in v]), ctx)
+    return dict(zip(("reps_per_wave", "workgroup", "split", "plan_split"),
+                    (x.value for x in v)))
 
 
 def mrip_run(ctx, n_reps, seed, stream=None):
@@ -359,6 +374,12 @@ class Context:
 
     def set_split(self, waves_per_rep):
         mrip_set_split(self.ctx, waves_per_rep)
+
+    def set_plan_split(self, waves_per_item, long_min=0):
+        mrip_set_plan_split(self.ctx, waves_per_item, long_min)
+
+    def shape(self):
+        return mrip_get_shape(self.ctx)
 
     def run(self, n_reps, seed=42, stream=None):
         mrip_run(self.ctx, n_reps, seed, current_stream() if stream is None else stream)

@@ -17,9 +17,10 @@ def _items_tuple(items):
              float(i["mu"])) for i in items]
 
 
-def _plan_ctx(items, rpw=1, wg=256):
+def _plan_ctx(items, rpw=1, wg=256, split=1, long_min=0):
     ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), WAVE)
     ctx.set_shape(rpw, wg)
+    ctx.set_plan_split(split, long_min)
     ctx.plan_set(items)
     return ctx
 
@@ -40,10 +41,11 @@ def test_plan_matches_oracle(gpu):
         assert abs(s["var"] - e["var"]) <= 1e-10 * e["var"]
 
 
-def test_plan_full_config_sampled(gpu):
+@pytest.mark.parametrize("split", [1, 4])
+def test_plan_full_config_sampled(gpu, split):
     items = inputs.plan_table()  # 64 dp x 32 reps, N log-uniform in [1e4, 1e6]
-    announce("plan full", len(items))
-    ctx = _plan_ctx(items)
+    announce("plan full", len(items), split)
+    ctx = _plan_ctx(items, split=split)
     ctx.run_plan(42)
     got = ctx.output(0, n=len(items)).cpu().numpy()
     rng = np.random.default_rng(3)
@@ -51,6 +53,18 @@ def test_plan_full_config_sampled(gpu):
     ids = sorted(set([0, len(items) - 1, longest] + list(rng.integers(0, len(items), 13))))
     ref = core.mm1_items(42, _items_tuple(items[ids]), threads=core.default_threads())[:, 0]
     assert rel_err(got[ids], ref).max() <= 1e-5
+
+
+def test_plan_split_long_items_match_oracle(gpu):
+    # unstable and near-critical factor levels: long correction runs
+    items = inputs.plan_table(n_dp=6, reps=4, rho_lo=0.9, rho_hi=1.2, n_lo=4000, n_hi=40000,
+                              seed=9)
+    announce("plan split oracle", len(items))
+    ctx = _plan_ctx(items, rpw=2, wg=256, split=4, long_min=8000)
+    ctx.run_plan(42)
+    got = ctx.output(0, n=len(items)).cpu().numpy()
+    ref = core.mm1_items(42, _items_tuple(items), threads=core.default_threads())[:, 0]
+    assert rel_err(got, ref).max() <= 1e-5
 
 
 def test_plan_item_equals_standalone_run(gpu):
@@ -77,8 +91,16 @@ def test_plan_shape_invariance_and_autotune(gpu):
                 base = got
             tol = 0.0 if rpw == 1 else 1e-6
             assert rel_err(got, base).max() <= tol
-    ctx = _plan_ctx(items)
+    for rpw in (1, 2, 4):
+        for split in (2, 4):
+            # long_min 1000: most items take the split path here
+            ctx = _plan_ctx(items, rpw, 256, split, long_min=1000)
+            ctx.run_plan(42)
+            got = ctx.output(0, n=len(items)).cpu().numpy()
+            assert rel_err(got, base).max() <= 1e-6, (rpw, split)
+    ctx = _plan_ctx(items, long_min=1000)
     rpw, wg, ms = ctx.autotune(42)
     assert rpw in (1, 2, 4) and wg in (64, 256, 1024) and ms > 0
+    assert ctx.shape()["plan_split"] in (1, 2, 4)
     ctx.run_plan(42)
     assert rel_err(ctx.output(0, n=len(items)).cpu().numpy(), base).max() <= 1e-6
