@@ -22,6 +22,11 @@ sys.path.insert(0, ROOT)
 
 R, N, LAM, MU = 1024, 100000, 0.9, 1.0
 SPLIT = 2  # wavefronts per replication (two per SIMD at 1024 replications)
+# HBM bytes per launch of mm1_split_kernel<2> from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by the same counter on a 256 MiB copy
+# (profiles/mm1_split_hbm_counters.md); to be re-measured when the kernel
+# changes.
+TRAFFIC_BYTES = 292454
 # Peak vector issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, the rate
 # behind the published fp32 vector figure (157.3 TFLOP/s counts an FMA as 2).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
@@ -56,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle sample")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="end with a 256 MiB device-to-device copy (calibrates HBM counters)")
     return ap.parse_args()
 
 
@@ -254,7 +261,7 @@ def main():
                    "waves_per_replication": SPLIT},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "frac": achieved / PEAK_LANE_OPS, "traffic": TRAFFIC_BYTES,
                      "kernel": "mm1_split_kernel<2>", "avg_kernel_ms": avg_kernel_ms,
                      "slots_per_customer": slots},
         "ci": {"mean_wq": ci["mean"], "half_width_95": ci["half_width"],
@@ -269,6 +276,11 @@ def main():
     }
     if not args.no_extras:
         line["extras"] = extras(torch, mrip, inputs)
+    if args.copy_calib:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)
