@@ -169,6 +169,27 @@ def extras(torch, mrip, inputs):
             sweep.setdefault(str(n), {})[name] = rate(ctx, n, n * 64 * 1000, runs=2)[1]
     rw["sweep_kernel_ms"] = sweep
 
+    # Monte Carlo pi, 1e7 draws per replication (the paper's first model):
+    # kernel ms against replications per mapping, and the oracle's single-core
+    # time per replication (the paper's CPU-vs-GPU crossover)
+    from oracle import core as ocore
+    t0 = time.perf_counter()
+    ocore.pi_hits(7, 0, 10_000_000)
+    cpu_rep_s = time.perf_counter() - t0
+    psweep = {}
+    for name, mp in maps:
+        ctx = mrip.Context(mrip.MRIP_PI, mrip.pi_params(10_000_000), mp)
+        for n in (1, 8, 32, 64, 256, 1024):
+            if name != "wave" and n > 256:
+                continue
+            psweep.setdefault(str(n), {})[name] = rate(ctx, n, n * 10_000_000, runs=2)[1]
+    ctx = mrip.Context(mrip.MRIP_PI, mrip.pi_params(10_000_000), mrip.MRIP_MAP_WAVE)
+    v, ms = rate(ctx, 1024, 1024 * 10_000_000, runs=2)
+    s_pi = ctx.stats(1)
+    out["pi_1e7"] = {"wave_points_per_s_1024reps": v, "sweep_kernel_ms": psweep,
+                     "cpu_oracle_s_per_rep_one_core": cpu_rep_s,
+                     "pi_estimate_1024reps": s_pi["mean"], "half_width": s_pi["half_width"]}
+
     # M/M/1 with the paper's one-working-lane WLP form
     ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_LANE0)
     v, ms = rate(ctx, R, R * N, runs=2)

@@ -56,7 +56,7 @@ typedef enum {
   MRIP_E_UNSUPPORTED = -6  /* valid request this build does not implement     */
 } mrip_status;
 
-typedef enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3 } mrip_model;
+typedef enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3, MRIP_PI = 4 } mrip_model;
 
 /* SIMT: one replication per lane (the paper's thread-level form, section
  * 3). WAVE: one replication per 64-lane wavefront with every lane working on
@@ -118,6 +118,16 @@ typedef struct {
   double p_grow, f_light;
 } mrip_ff_params;
 
+/* Monte Carlo pi (paper section 5.1, first model): `points` points per
+ * replication (1 <= points < 2^31); point i takes words 2(i&1), 2(i&1)+1 of
+ * block (i>>1, 0, r, 4), a word's top 24 bits X give u = (X + 1/2) 2^-24, and
+ * the point counts when u^2 + v^2 <= 1 (decided exactly in integers).
+ * Outputs: 0 = int32 hits, 1 = fp32 estimate 4 hits / points. */
+typedef struct {
+  uint32_t size;
+  uint64_t points;
+} mrip_pi_params;
+
 typedef struct {
   uint64_t n;
   double mean, var;        /* var: unbiased, over replications          */
@@ -135,8 +145,9 @@ typedef struct {
 
 /* ---------------------------------------------------------------- context */
 
-/* Validate `params` (a struct matching `model`) and create a context; no
- * kernel runs. */
+/* Validate `params` (a struct matching `model`: mrip_rw_params,
+ * mrip_mm1_params, mrip_ff_params or mrip_pi_params) and create a context;
+ * no kernel runs. */
 MRIP_API mrip_status mrip_create(mrip_ctx *out, mrip_model model, const void *params,
                         mrip_mapping mapping);
 MRIP_API void mrip_destroy(mrip_ctx ctx);

@@ -41,6 +41,10 @@ def lib():
                                  C.c_float, C.c_uint64, f32p, C.c_void_p]
         L.oracle_mm1_injected.argtypes = [f32p, f32p, C.c_uint64, C.c_void_p, C.c_void_p,
                                           C.c_void_p, f32p]
+        L.oracle_pi_inside.argtypes = [C.c_uint32, C.c_uint32]
+        L.oracle_pi_inside.restype = C.c_int
+        L.oracle_pi.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64]
+        L.oracle_pi.restype = C.c_int64
         L.oracle_ff_threshold.argtypes = [C.c_double]
         L.oracle_ff_threshold.restype = C.c_uint32
         L.oracle_ff.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double,
@@ -194,6 +198,20 @@ def ff_injected(u, p, f, init=None):
 def ff_many(seed, reps, grid=128, steps=2000, p=0.01, f=1e-5, threads=1):
     ids = list(range(reps)) if isinstance(reps, int) else list(reps)
     return np.array(_map(lambda r: ff(seed, r, grid, steps, p, f), ids, threads), np.int64)
+
+
+# ---------------------------------------------------------------- Monte Carlo pi
+def pi_inside(wx, wy):
+    return bool(lib().oracle_pi_inside(int(wx), int(wy)))
+
+
+def pi_hits(seed, rep, points):
+    return int(lib().oracle_pi(seed, rep, points))
+
+
+def pi_many(seed, reps, points, threads=1):
+    ids = list(range(reps)) if isinstance(reps, int) else list(reps)
+    return np.array(_map(lambda r: pi_hits(seed, r, points), ids, threads), np.int64)
 
 
 # ---------------------------------------------------------------- helpers

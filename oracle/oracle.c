@@ -22,6 +22,8 @@
  *               inputs (S == 0, A == 0).
  *   ff       -- injected-uniform cases with closed-form burnt counts and an
  *               independent array-rolling implementation on tiny grids.
+ *   pi       -- hand-checked inside/outside points on and near the circle,
+ *               E[hits/N] = pi/4 and the binomial variance N p (1 - p).
  */
 #include <math.h>
 #include <stdint.h>
@@ -77,7 +79,7 @@ static void philox_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, u
 }
 
 /* Model tags: the fourth counter word separates the streams of each model. */
-enum { TAG_RW = 1, TAG_MM1 = 2, TAG_FF = 3 };
+enum { TAG_RW = 1, TAG_MM1 = 2, TAG_FF = 3, TAG_PI = 4 };
 
 /* ------------------------------------------------------------------------ */
 /* Variates.                                                                */
@@ -345,4 +347,29 @@ EXPORT int oracle_ff_state(uint64_t seed, uint32_t rep, uint32_t L, uint32_t T, 
   if (L == 0 || (L % 4u) != 0) return -1;
   return ff_core(seed, rep, L, T, oracle_ff_threshold(p), oracle_ff_threshold(f), NULL, NULL,
                  final, burnt);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Monte Carlo pi (paper section 5.1, first model): draw points uniformly in */
+/* the unit square and count those inside the quarter disc. Point i of      */
+/* replication r takes words 2(i&1), 2(i&1)+1 of block (i>>1, 0, r, TAG_PI); */
+/* each word's top 24 bits X give the coordinate u = (X + 1/2) 2^-24, so    */
+/* the point is inside iff u^2 + v^2 <= 1, i.e. (2X+1)^2 + (2Y+1)^2 <= 2^50, */
+/* decided exactly in 64-bit integers. The estimate is 4 hits / N.          */
+/* ------------------------------------------------------------------------ */
+EXPORT int oracle_pi_inside(uint32_t wx, uint32_t wy) {
+  uint64_t a = 2ull * (uint64_t)(wx >> 8) + 1ull;
+  uint64_t b = 2ull * (uint64_t)(wy >> 8) + 1ull;
+  return a * a + b * b <= (1ull << 50);
+}
+
+EXPORT int64_t oracle_pi(uint64_t seed, uint32_t rep, uint64_t points) {
+  int64_t hits = 0;
+  uint32_t blk[4];
+  for (uint64_t i = 0; i < points; ++i) {
+    if ((i & 1u) == 0) philox_block(seed, (uint32_t)(i >> 1), 0, rep, TAG_PI, blk);
+    uint32_t j = 2u * (uint32_t)(i & 1u);
+    hits += oracle_pi_inside(blk[j], blk[j + 1]);
+  }
+  return hits;
 }

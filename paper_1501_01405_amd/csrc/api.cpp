@@ -41,7 +41,14 @@ mrip_status inval(mrip_ctx c, const char *why) {
     if (_e != hipSuccess) return hip_fail((ctx), _e, #expr); \
   } while (0)
 
-uint32_t scalar_outputs(mrip_model m) { return m == MRIP_RW ? 2 : m == MRIP_MM1 ? 3 : 1; }
+uint32_t scalar_outputs(mrip_model m) {
+  return m == MRIP_RW ? 2 : m == MRIP_MM1 ? 3 : m == MRIP_PI ? 2 : 1;
+}
+
+// dtype of scalar output o for the reduction kernel: 0 = int32, 1 = fp32
+int output_dtype(mrip_model m, uint32_t o) {
+  return m == MRIP_MM1 ? 1 : (m == MRIP_PI && o == 1) ? 1 : 0;
+}
 
 bool is_pow2_grid(uint32_t g) { return g == 16 || g == 32 || g == 64 || g == 128; }
 
@@ -130,6 +137,12 @@ mrip_status validate(mrip_model model, const void *params, mrip_mapping map, std
       return why = "grid^2 * steps must be < 2^31", MRIP_E_INVAL;
     return MRIP_OK;
   }
+  if (model == MRIP_PI) {
+    const mrip_pi_params *p = (const mrip_pi_params *)params;
+    if (p->size != sizeof(mrip_pi_params)) return why = "mrip_pi_params.size mismatch", MRIP_E_INVAL;
+    if (p->points < 1 || p->points >= (1ull << 31)) return why = "points must be in [1, 2^31)", MRIP_E_INVAL;
+    return MRIP_OK;
+  }
   return why = "unknown model", MRIP_E_INVAL;
 }
 
@@ -170,6 +183,7 @@ mrip_status mrip_create(mrip_ctx *out, mrip_model model, const void *params,
   if (model == MRIP_RW) c->rw = *(const mrip_rw_params *)params;
   if (model == MRIP_MM1) c->mm1 = *(const mrip_mm1_params *)params;
   if (model == MRIP_FF) c->ff = *(const mrip_ff_params *)params;
+  if (model == MRIP_PI) c->pi = *(const mrip_pi_params *)params;
   *out = c;
   return MRIP_OK;
 }
@@ -271,6 +285,15 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     if (wave && ctx->split > 1) HIP_TRY(ctx, launch_mm1_split(a, ctx->split, s));
     else if (wave) HIP_TRY(ctx, launch_mm1_wave(a, ctx->rpw, ctx->wg, s));
     else HIP_TRY(ctx, launch_mm1_simt(a, ctx->mapping == MRIP_MAP_LANE0, s));
+  } else if (ctx->model == MRIP_PI) {
+    PiArgs a{};
+    a.seed = seed;
+    a.points = ctx->pi.points;
+    a.n_reps = n_reps;
+    a.hits = ctx->out[0].as<int32_t>();
+    a.estimate = ctx->out[1].as<float>();
+    if (wave) HIP_TRY(ctx, launch_pi_wave(a, ctx->wg, s));
+    else HIP_TRY(ctx, launch_pi_simt(a, ctx->mapping == MRIP_MAP_LANE0, s));
   } else {
     FfArgs a{};
     a.seed = seed;
@@ -290,10 +313,9 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   }
   st = record_end(ctx, s);
   if (st != MRIP_OK) return st;
-  const int dtype = ctx->model == MRIP_MM1 ? 1 : 0;
   for (uint32_t o = 0; o < nout; ++o)
-    HIP_TRY(ctx, launch_reduce_f64(ctx->out[o].p, dtype, n_reps, nullptr, 1,
-                                   ctx->stats.as<double>() + 3 * o, s));
+    HIP_TRY(ctx, launch_reduce_f64(ctx->out[o].p, output_dtype(ctx->model, o), n_reps, nullptr,
+                                   1, ctx->stats.as<double>() + 3 * o, s));
   ctx->last = RUN_UNIFORM;
   ctx->last_n = n_reps;
   ctx->last_stream = s;

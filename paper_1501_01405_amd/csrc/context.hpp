@@ -83,6 +83,7 @@ struct mrip_ctx_s {
   mrip_rw_params rw;
   mrip_mm1_params mm1;
   mrip_ff_params ff;
+  mrip_pi_params pi;
   uint32_t rpw = 1, wg = 256;
   uint32_t split = 1;  // wavefronts per M/M/1 replication in mrip_run
   // plans: wavefronts per long item (1 = none) and what counts as long

@@ -67,6 +67,17 @@ struct FfArgs {
 hipError_t launch_ff_wave(const FfArgs &a, uint32_t workgroup, hipStream_t s);
 hipError_t launch_ff_simt(const FfArgs &a, bool one_lane, hipStream_t s);
 
+// ------------------------------------------------------------ Monte Carlo pi
+struct PiArgs {
+  uint64_t seed;
+  uint64_t points;  // per replication, < 2^31
+  uint64_t n_reps;
+  int32_t *hits;
+  float *estimate;  // 4 hits / points
+};
+hipError_t launch_pi_wave(const PiArgs &a, uint32_t workgroup, hipStream_t s);
+hipError_t launch_pi_simt(const PiArgs &a, bool one_lane, hipStream_t s);
+
 // ------------------------------------------------------------ reductions
 // out[3*g + {0,1,2}] = (n, mean, unbiased var) in fp64 over segment g of x;
 // segment g is x[offsets[g] .. offsets[g+1]) (offsets nullptr: one segment

@@ -1,0 +1,87 @@
+// Monte Carlo pi replication engines (paper section 5.1, first model).
+//
+// Point i of replication r is the pair of words 2(i&1), 2(i&1)+1 of Philox
+// block (i>>1, 0, r, TAG_PI); a word's top 24 bits X give u = (X + 1/2)
+// 2^-24 and the point is inside the quarter disc iff
+// (2X+1)^2 + (2Y+1)^2 <= 2^50, an exact test on two v_mad_u64_u32.
+//
+// WAVE: one replication per wavefront, the lanes take interleaved blocks
+// (four per lane per iteration) and sum their counts at the end. SIMT: one
+// replication per lane (STRIDE 1) or per wavefront's first lane (STRIDE 64,
+// the paper's WLP form).
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace mrip {
+
+namespace {
+
+constexpr uint32_t TAG_PI = 4;
+
+__device__ __forceinline__ uint32_t inside(uint32_t wx, uint32_t wy) {
+  const uint64_t a = 2u * (wx >> 8) + 1u, b = 2u * (wy >> 8) + 1u;
+  return a * a + b * b <= (1ull << 50) ? 1u : 0u;
+}
+
+// hits of the two points of block k (the second only if it exists)
+__device__ __forceinline__ uint32_t block_hits(uint64_t k, uint64_t points, uint32_t rep,
+                                               uint32_t k0, uint32_t k1) {
+  const Block4 b = philox((uint32_t)k, 0u, rep, TAG_PI, k0, k1);
+  return inside(b.x, b.y) + ((2 * k + 1 < points) ? inside(b.z, b.w) : 0u);
+}
+
+__global__ void pi_wave_kernel(PiArgs a) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t r = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= a.n_reps) return;  // wave-uniform
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  const uint64_t blocks = (a.points + 1) / 2;
+  uint32_t hits = 0;
+  uint64_t k = lane;
+  // four blocks per lane per iteration while all of them exist
+  for (; k + 192 < blocks; k += 256) {
+    hits += block_hits(k, a.points, (uint32_t)r, k0, k1);
+    hits += block_hits(k + 64, a.points, (uint32_t)r, k0, k1);
+    hits += block_hits(k + 128, a.points, (uint32_t)r, k0, k1);
+    hits += block_hits(k + 192, a.points, (uint32_t)r, k0, k1);
+  }
+  for (; k < blocks; k += 64) hits += block_hits(k, a.points, (uint32_t)r, k0, k1);
+  const int total = group_sum_i((int)hits, 64);
+  if (lane == 0) {
+    a.hits[r] = total;
+    a.estimate[r] = (float)(4.0 * (double)total / (double)a.points);
+  }
+}
+
+template <int STRIDE>
+__global__ void pi_simt_kernel(PiArgs a) {
+  if (threadIdx.x % STRIDE) return;
+  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
+  if (r >= a.n_reps) return;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  const uint64_t blocks = (a.points + 1) / 2;
+  uint32_t hits = 0;
+  for (uint64_t k = 0; k < blocks; ++k) hits += block_hits(k, a.points, (uint32_t)r, k0, k1);
+  a.hits[r] = (int32_t)hits;
+  a.estimate[r] = (float)(4.0 * (double)hits / (double)a.points);
+}
+
+}  // namespace
+
+hipError_t launch_pi_wave(const PiArgs &a, uint32_t wg, hipStream_t s) {
+  const uint32_t wpb = wg / 64;
+  const uint64_t blocks = (a.n_reps + wpb - 1) / wpb;
+  hipLaunchKernelGGL(pi_wave_kernel, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pi_simt(const PiArgs &a, bool one_lane, hipStream_t s) {
+  const uint32_t wg = 64;
+  const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
+  const uint64_t blocks = (threads + wg - 1) / wg;
+  if (one_lane) hipLaunchKernelGGL(pi_simt_kernel<64>, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  else hipLaunchKernelGGL(pi_simt_kernel<1>, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace mrip

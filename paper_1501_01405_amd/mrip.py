@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmrip.so")
 
 MRIP_OK, MRIP_E_INVAL, MRIP_E_NOMEM, MRIP_E_HIP, MRIP_E_STATE, MRIP_E_TOO_FEW, \
     MRIP_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-MRIP_RW, MRIP_MM1, MRIP_FF = 1, 2, 3
+MRIP_RW, MRIP_MM1, MRIP_FF, MRIP_PI = 1, 2, 3, 4
 MRIP_MAP_AUTO, MRIP_MAP_SIMT, MRIP_MAP_WAVE, MRIP_MAP_LANE0 = 0, 1, 2, 3
 MRIP_MLP_PARAMS = 18049
 MRIP_CV_BETA_BINS = 16
@@ -34,6 +34,10 @@ class mrip_mm1_params(C.Structure):
 class mrip_ff_params(C.Structure):
     _fields_ = [("size", C.c_uint32), ("grid", C.c_uint32), ("steps", C.c_uint32),
                 ("p_grow", C.c_double), ("f_light", C.c_double)]
+
+
+class mrip_pi_params(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("points", C.c_uint64)]
 
 
 class mrip_stats_t(C.Structure):
@@ -341,12 +345,16 @@ def ff_params(grid=128, steps=2000, p_grow=0.01, f_light=1e-5):
     return mrip_ff_params(C.sizeof(mrip_ff_params), grid, steps, p_grow, f_light)
 
 
+def pi_params(points=10_000_000):
+    return mrip_pi_params(C.sizeof(mrip_pi_params), points)
+
+
 def cv_hparams(epochs=20, batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return mrip_cv_hparams(C.sizeof(mrip_cv_hparams), epochs, batch, lr, beta1, beta2, eps)
 
 
 _OUT_DTYPES = {MRIP_RW: ("int32", "int32"), MRIP_MM1: ("float32",) * 3,
-               MRIP_FF: ("int32",)}
+               MRIP_FF: ("int32",), MRIP_PI: ("int32", "float32")}
 
 
 class Context:

@@ -81,6 +81,9 @@ def test_parameter_validation():
     assert _create(7, mrip.rw_params()) == bad
     assert _create(mrip.MRIP_RW, mrip.rw_params(), mrip.MRIP_MAP_LANE0) == ok
     assert _create(mrip.MRIP_RW, mrip.rw_params(), 9) == bad
+    assert _create(mrip.MRIP_PI, mrip.pi_params(1000)) == ok
+    assert _create(mrip.MRIP_PI, mrip.pi_params(0)) == bad
+    assert _create(mrip.MRIP_PI, mrip.pi_params(2**31)) == bad
 
 
 def test_calls_out_of_order_and_bad_shapes():
