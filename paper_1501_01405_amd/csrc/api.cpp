@@ -66,6 +66,9 @@ uint32_t ff_threshold(double prob) {
 mrip_status ensure_events(mrip_ctx c) {
   if (!c->ev0) HIP_TRY(c, hipEventCreate(&c->ev0));
   if (!c->ev1) HIP_TRY(c, hipEventCreate(&c->ev1));
+  if (!c->ev_stats) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_stats, hipEventDisableTiming));
+  if (!c->stats_host) HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, sizeof(double) * 3 * 4,
+                                               hipHostMallocDefault));
   return MRIP_OK;
 }
 
@@ -313,9 +316,17 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   }
   st = record_end(ctx, s);
   if (st != MRIP_OK) return st;
-  for (uint32_t o = 0; o < nout; ++o)
-    HIP_TRY(ctx, launch_reduce_f64(ctx->out[o].p, output_dtype(ctx->model, o), n_reps, nullptr,
-                                   1, ctx->stats.as<double>() + 3 * o, s));
+  // all scalar outputs in one reduction launch; the triples go to pinned
+  // host memory on the same stream so mrip_stats only waits for an event
+  ReduceSet set{};
+  for (uint32_t o = 0; o < nout; ++o) {
+    set.x[o] = ctx->out[o].p;
+    set.dtype[o] = output_dtype(ctx->model, o);
+  }
+  HIP_TRY(ctx, launch_reduce_f64_multi(set, nout, n_reps, ctx->stats.as<double>(), s));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->stats_host, ctx->stats.p, sizeof(double) * 3 * nout,
+                              hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev_stats, s));
   ctx->last = RUN_UNIFORM;
   ctx->last_n = n_reps;
   ctx->last_stream = s;
@@ -327,10 +338,9 @@ mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence, mrip_st
   if (!(confidence > 0.0 && confidence < 1.0)) return inval(ctx, "confidence must be in (0, 1)");
   if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
   if (output >= scalar_outputs(ctx->model)) return inval(ctx, "no such scalar output");
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev_stats));
   double nmv[3];
-  HIP_TRY(ctx, hipMemcpy(nmv, ctx->stats.as<double>() + 3 * output, sizeof(nmv),
-                         hipMemcpyDeviceToHost));
+  std::memcpy(nmv, ctx->stats_host + 3 * output, sizeof(nmv));
   mrip_status st = finish_stats(nmv, confidence, out);
   if (st == MRIP_E_TOO_FEW) ctx->err = "fewer than two replications";
   return st;
@@ -486,9 +496,15 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
     HIP_TRY(ctx, launch_reduce_f64_gather(ctx->out[0].p, 1, ctx->dp_index.as<uint32_t>(),
                                           ctx->dp_offsets.as<uint64_t>(), (uint32_t)ctx->dp_ids.size(),
                                           ctx->dp_stats.as<double>(), s));
-    for (uint32_t o = 0; o < 3; ++o)
-      HIP_TRY(ctx, launch_reduce_f64(ctx->out[o].p, 1, ctx->n_items, nullptr, 1,
-                                     ctx->stats.as<double>() + 3 * o, s));
+    ReduceSet set{};
+    for (uint32_t o = 0; o < 3; ++o) {
+      set.x[o] = ctx->out[o].p;
+      set.dtype[o] = 1;
+    }
+    HIP_TRY(ctx, launch_reduce_f64_multi(set, 3, ctx->n_items, ctx->stats.as<double>(), s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->stats_host, ctx->stats.p, sizeof(double) * 9,
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_stats, s));
   }
   ctx->last_stream = s;
   return MRIP_OK;

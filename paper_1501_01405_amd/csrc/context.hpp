@@ -93,6 +93,8 @@ struct mrip_ctx_s {
   mrip::DevBuf out[4];
   mrip::DevBuf scratch;
   mrip::DevBuf stats;  // 3 doubles per scalar output
+  double *stats_host = nullptr;     // pinned copy of `stats`, filled on the run's stream
+  hipEvent_t ev_stats = nullptr;    // recorded after that copy
   mrip::RunKind last = mrip::RUN_NONE;
   uint64_t last_n = 0;
   hipStream_t last_stream = nullptr;
@@ -114,6 +116,8 @@ struct mrip_ctx_s {
   mrip::CvState cv;
 
   ~mrip_ctx_s() {
+    if (stats_host) (void)hipHostFree(stats_host);
+    if (ev_stats) (void)hipEventDestroy(ev_stats);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     for (uint32_t i = 0; i < RING; ++i) {

@@ -84,6 +84,14 @@ hipError_t launch_pi_simt(const PiArgs &a, bool one_lane, hipStream_t s);
 // of n values). dtype 0 = int32, 1 = fp32.
 hipError_t launch_reduce_f64(const void *x, int dtype, uint64_t n, const uint64_t *offsets,
                              uint32_t n_segments, double *out, hipStream_t s);
+// Several outputs of n values each in one launch (one workgroup each):
+// out[3*o + {0,1,2}] for output o.
+struct ReduceSet {
+  const void *x[4];
+  int dtype[4];
+};
+hipError_t launch_reduce_f64_multi(const ReduceSet &set, uint32_t n_outputs, uint64_t n,
+                                   double *out, hipStream_t s);
 // Gathered variant: segment g reads x[index[offsets[g] .. offsets[g+1])].
 hipError_t launch_reduce_f64_gather(const void *x, int dtype, const uint32_t *index,
                                     const uint64_t *offsets, uint32_t n_segments, double *out,

@@ -158,8 +158,11 @@ __device__ __forceinline__ void apply_lane(float T, const Draw<P> &dr, uint64_t 
   sw = st = si = 0.0f;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const float W = fmaxf(0.0f, T - dr.A[j]);
-    const float I = fmaxf(0.0f, dr.A[j] - T);
+    // I = max(0, A - T) = W - (T - A) exactly: A - T = -(T - A) in IEEE
+    // arithmetic, and W is either 0 or T - A
+    const float dlt = T - dr.A[j];
+    const float W = fmaxf(0.0f, dlt);
+    const float I = W - dlt;
     T = W + dr.S[j];
     if (TAIL) {
       const bool v = n0 + j < n;

@@ -74,6 +74,36 @@ __global__ void reduce_kernel(const void *x, int dtype, const uint32_t *index,
   }
 }
 
+// One workgroup per output: the same fixed-order two-pass reduction.
+__global__ void reduce_multi_kernel(ReduceSet set, uint64_t n, double *out) {
+  __shared__ double shd[RB];
+  __shared__ long long shl[RB];
+  const uint32_t o = blockIdx.x;
+  const void *x = set.x[o];
+  const int dtype = set.dtype[o];
+  double mean;
+  if (dtype == 0) {
+    long long s = 0;
+    for (uint64_t j = threadIdx.x; j < n; j += RB) s += ((const int32_t *)x)[j];
+    mean = (double)block_sum_ll(s, shl) / (double)n;
+  } else {
+    double s = 0.0;
+    for (uint64_t j = threadIdx.x; j < n; j += RB) s += load_x(x, dtype, j);
+    mean = block_sum(s, shd) / (double)n;
+  }
+  double ss = 0.0;
+  for (uint64_t j = threadIdx.x; j < n; j += RB) {
+    const double d = load_x(x, dtype, j) - mean;
+    ss += d * d;
+  }
+  ss = block_sum(ss, shd);
+  if (threadIdx.x == 0) {
+    out[3 * o + 0] = (double)n;
+    out[3 * o + 1] = n > 0 ? mean : 0.0;
+    out[3 * o + 2] = n > 1 ? ss / (double)(n - 1) : 0.0;
+  }
+}
+
 __global__ void philox_dump_kernel(uint64_t seed, const uint32_t *ctr, uint64_t n,
                                    uint32_t *out) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,6 +130,12 @@ hipError_t launch_reduce_f64_gather(const void *x, int dtype, const uint32_t *in
                                     hipStream_t s) {
   hipLaunchKernelGGL(reduce_kernel, dim3(n_segments), dim3(RB), 0, s, x, dtype, index, offsets,
                      (uint64_t)0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_f64_multi(const ReduceSet &set, uint32_t n_outputs, uint64_t n,
+                                   double *out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_multi_kernel, dim3(n_outputs), dim3(RB), 0, s, set, n, out);
   return hipGetLastError();
 }
 
