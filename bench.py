@@ -24,9 +24,9 @@ R, N, LAM, MU = 1024, 100000, 0.9, 1.0
 SPLIT = 2  # wavefronts per replication (two per SIMD at 1024 replications)
 # HBM bytes per launch of mm1_split_kernel<2> from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by the same counter on a 256 MiB copy
-# (profiles/mm1_split_hbm_counters.md); to be re-measured when the kernel
-# changes.
-TRAFFIC_BYTES = None  # re-measured below after kernel changes
+# (profiles/mm1_split_hbm_counters.md); to be re-measured (or set to None)
+# whenever the kernel changes.
+TRAFFIC_BYTES = (116.0 * 2.00 + 48.0 * 1.00) * 1024
 # Peak vector issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, the rate
 # behind the published fp32 vector figure (157.3 TFLOP/s counts an FMA as 2).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
@@ -96,9 +96,19 @@ def cpu_baseline(seconds):
     t0 = time.perf_counter()
     core.mm1_many(7, reps, N, LAM, MU, threads=threads)
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": reps * N / dt, "unit": "customers/s", "cores": threads, "kind": "oracle",
             "sample": "%d replications x %d customers (of 1024 x 1e5), %.1f s wall" %
-                      (reps, N, dt)}
+                      (reps, N, dt),
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def cv_experiment(mrip, inputs, customers, K=1000):

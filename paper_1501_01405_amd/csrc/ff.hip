@@ -26,6 +26,19 @@ namespace mrip {
 
 namespace {
 
+// mask = 2 mask + [u < t]: the borrow of u - t shifts straight into the mask
+// (v_sub_co_u32 then v_addc_co_u32), two instructions per bit where a
+// compare, a select and a shift-or would take three.
+__device__ __forceinline__ uint32_t shift_in_less(uint32_t mask, uint32_t u, uint32_t t) {
+  uint32_t tmp;
+  asm("v_sub_co_u32 %0, vcc, %2, %3\n\t"
+      "v_addc_co_u32 %1, vcc, %1, %1, vcc"
+      : "=&v"(tmp), "+v"(mask)
+      : "v"(u), "v"(t)
+      : "vcc");
+  return mask;
+}
+
 // Bits [u < TP] and [u < TF] for the 32 cells of one word: cells
 // 32k..32k+31 of row y use blocks q0..q0+7, word (cell & 3).
 __device__ __forceinline__ void draw_masks(uint32_t t, uint32_t q0, uint32_t rep, uint32_t k0,
@@ -37,14 +50,14 @@ __device__ __forceinline__ void draw_masks(uint32_t t, uint32_t q0, uint32_t rep
 #pragma unroll 2
   for (int m = 7; m >= 0; --m) {
     const Block4 b = philox(t, q0 + (uint32_t)m, rep, TAG_FF, k0, k1);
-    mp = (mp << 1) | (uint32_t)(b.w < tp);
-    mf = (mf << 1) | (uint32_t)(b.w < tf);
-    mp = (mp << 1) | (uint32_t)(b.z < tp);
-    mf = (mf << 1) | (uint32_t)(b.z < tf);
-    mp = (mp << 1) | (uint32_t)(b.y < tp);
-    mf = (mf << 1) | (uint32_t)(b.y < tf);
-    mp = (mp << 1) | (uint32_t)(b.x < tp);
-    mf = (mf << 1) | (uint32_t)(b.x < tf);
+    mp = shift_in_less(mp, b.w, tp);
+    mf = shift_in_less(mf, b.w, tf);
+    mp = shift_in_less(mp, b.z, tp);
+    mf = shift_in_less(mf, b.z, tf);
+    mp = shift_in_less(mp, b.y, tp);
+    mf = shift_in_less(mf, b.y, tf);
+    mp = shift_in_less(mp, b.x, tp);
+    mf = shift_in_less(mf, b.x, tf);
   }
   ltp = mp;
   ltf = mf;

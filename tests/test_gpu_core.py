@@ -75,3 +75,16 @@ def test_stats_too_few(gpu):
     with pytest.raises(mrip.MripError) as e:
         ctx.stats(0)
     assert e.value.status == mrip.MRIP_E_TOO_FEW
+
+
+def test_rw_many_replications_sampled(gpu):
+    # 16384 replications (the top of the replication sweep), sampled ids
+    announce("rw 16384")
+    for mapping in (WAVE, SIMT):
+        ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), mapping)
+        ctx.run(16384, seed=5)
+        ssd = ctx.output(0).cpu().numpy()
+        dist = ctx.output(1).cpu().numpy()
+        ids = [0, 1, 8191, 16383]
+        essd, edist = core.rw_many(5, ids, 64, 64, 1000)
+        assert np.array_equal(ssd[ids], essd) and np.array_equal(dist[ids], edist)

@@ -131,3 +131,17 @@ def test_mm1_split_features(gpu):
     ctx.run(R, seed=42)
     assert np.array_equal(ctx.output(3).cpu().numpy(), base[2])
     assert rel_err(ctx.output(0).cpu().numpy(), base[1][:, 0]).max() <= 1e-6
+
+
+@pytest.mark.parametrize("mapping,rpw", [(WAVE, 1), (WAVE, 4), (SIMT, 1)])
+@pytest.mark.parametrize("N,K", [(1, 1), (5000, 5000), (777, 512), (2048, 1)])
+def test_mm1_feature_edges(gpu, mapping, rpw, N, K):
+    # prefix = whole run, a one-customer run, prefixes ending inside a chunk
+    announce("mm1 feature edges", mapping, rpw, N, K)
+    R = 9
+    _, outs, feat = _run(mapping, rpw, 256, 0.8, N, R, K=K)
+    ref, rfeat = core.mm1_many(42, R, N, 0.8, 1.0, features=K, threads=core.default_threads())
+    assert rel_err(outs, ref).max() <= TOL
+    cont = [0, 1, 2, 3, 4, 5, 7, 8, 9]
+    assert rel_err(feat[:, cont], rfeat[:, cont]).max() <= TOL
+    assert np.abs(feat[:, 6] - rfeat[:, 6]).max() <= 2.0 / K
