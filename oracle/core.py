@@ -53,7 +53,17 @@ def lib():
                                          C.c_void_p, u8p, C.POINTER(C.c_int64)]
         L.oracle_ff_state.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                       C.c_double, C.c_double, u8p, C.POINTER(C.c_int64)]
-        for name in ("oracle_rw", "oracle_mm1", "oracle_mm1_injected", "oracle_ff",
+        L.oracle_taus88_next.argtypes = [u32p]
+        L.oracle_taus88_next.restype = C.c_uint32
+        L.oracle_taus88_seed.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, u32p]
+        L.oracle_taus88_seed.restype = None
+        L.oracle_taus88_outputs.argtypes = [u32p, C.c_uint64, u32p]
+        L.oracle_taus88_outputs.restype = None
+        L.oracle_pi_taus.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64]
+        L.oracle_pi_taus.restype = C.c_int64
+        L.oracle_rw_taus.argtypes = L.oracle_rw.argtypes
+        L.oracle_mm1_taus.argtypes = L.oracle_mm1.argtypes
+        for name in ("oracle_rw_taus", "oracle_mm1_taus", "oracle_rw", "oracle_mm1", "oracle_mm1_injected", "oracle_ff",
                      "oracle_ff_injected", "oracle_ff_state", "oracle_rw_injected"):
             getattr(L, name).restype = C.c_int
         L.oracle_philox4x32_10.restype = None
@@ -113,10 +123,19 @@ def rw_injected(dirs):
     return s.value, d.value
 
 
-def rw_many(seed, reps, walkers=64, grid=64, steps=1000, threads=1):
+def rw_taus(seed, rep, walkers=64, grid=64, steps=1000):
+    """(ssd, distinct) of one replication on its taus88 stream."""
+    s, d = C.c_int64(), C.c_int64()
+    _check(lib().oracle_rw_taus(seed, rep, walkers, grid, steps, C.byref(s), C.byref(d)),
+           "rw_taus")
+    return s.value, d.value
+
+
+def rw_many(seed, reps, walkers=64, grid=64, steps=1000, threads=1, rng="philox"):
     """Outputs (ssd[R], distinct[R]) for replications 0..reps-1 (or an id list)."""
     ids = list(range(reps)) if isinstance(reps, int) else list(reps)
-    res = _map(lambda r: rw(seed, r, walkers, grid, steps), ids, threads)
+    one = rw if rng == "philox" else rw_taus
+    res = _map(lambda r: one(seed, r, walkers, grid, steps), ids, threads)
     return (np.array([a for a, _ in res], dtype=np.int64),
             np.array([b for _, b in res], dtype=np.int64))
 
@@ -144,10 +163,20 @@ def mm1_injected(A, S):
     return W, I, T, out
 
 
-def mm1_many(seed, reps, customers, lam, mu, dp=0, features=0, threads=1):
+def mm1_taus(seed, rep, customers, lam, mu, dp=0, features=0):
+    """mm1() on the replication's taus88 stream."""
+    out = np.zeros(3, dtype=np.float32)
+    feat = np.zeros(10, dtype=np.float32)
+    _check(lib().oracle_mm1_taus(seed, dp, rep, customers, lam, mu, features, out,
+                                 feat.ctypes.data if features else None), "mm1_taus")
+    return (out, feat) if features else out
+
+
+def mm1_many(seed, reps, customers, lam, mu, dp=0, features=0, threads=1, rng="philox"):
     """Outputs (R,3) float32, and (R,10) features when requested."""
     ids = list(range(reps)) if isinstance(reps, int) else list(reps)
-    res = _map(lambda r: mm1(seed, r, customers, lam, mu, dp, features), ids, threads)
+    one = mm1 if rng == "philox" else mm1_taus
+    res = _map(lambda r: one(seed, r, customers, lam, mu, dp, features), ids, threads)
     if features:
         return (np.stack([a for a, _ in res]), np.stack([b for _, b in res]))
     return np.stack(res)
@@ -209,9 +238,33 @@ def pi_hits(seed, rep, points):
     return int(lib().oracle_pi(seed, rep, points))
 
 
-def pi_many(seed, reps, points, threads=1):
+def pi_taus(seed, rep, points):
+    return int(lib().oracle_pi_taus(seed, rep, points))
+
+
+def pi_many(seed, reps, points, threads=1, rng="philox"):
     ids = list(range(reps)) if isinstance(reps, int) else list(reps)
-    return np.array(_map(lambda r: pi_hits(seed, r, points), ids, threads), np.int64)
+    one = pi_hits if rng == "philox" else pi_taus
+    return np.array(_map(lambda r: one(seed, r, points), ids, threads), np.int64)
+
+
+# ---------------------------------------------------------------- taus88
+MODEL_TAG = {"rw": 1, "mm1": 2, "ff": 3, "pi": 4}
+
+
+def taus88_seed(seed, model, rep, dp=0):
+    """Random Spacing start state (3 words) of the stream of (model, dp, rep)."""
+    st = np.zeros(3, np.uint32)
+    lib().oracle_taus88_seed(seed, MODEL_TAG.get(model, model), dp, rep, st)
+    return st
+
+
+def taus88_outputs(state, n):
+    """n outputs from a start state; returns (outputs, state after)."""
+    st = np.ascontiguousarray(state, dtype=np.uint32).copy()
+    out = np.zeros(max(n, 1), np.uint32)
+    lib().oracle_taus88_outputs(st, n, out)
+    return out[:n], st
 
 
 # ---------------------------------------------------------------- helpers

@@ -24,6 +24,10 @@
  *               independent array-rolling implementation on tiny grids.
  *   pi       -- hand-checked inside/outside points on and near the circle,
  *               E[hits/N] = pi/4 and the binomial variance N p (1 - p).
+ *   taus88   -- each component against the bit-serial linear recurrence of
+ *               its trinomial, primitivity of the three trinomials, Random
+ *               Spacing seeds against an independent Philox, and the three
+ *               models on streams built from the bit-serial definition.
  */
 #include <math.h>
 #include <stdint.h>
@@ -78,8 +82,9 @@ static void philox_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, u
   oracle_philox4x32_10(ctr, key, out);
 }
 
-/* Model tags: the fourth counter word separates the streams of each model. */
-enum { TAG_RW = 1, TAG_MM1 = 2, TAG_FF = 3, TAG_PI = 4 };
+/* Model tags: the fourth counter word separates the streams of each model;
+ * TAG_TAUS_SEED marks the blocks that seed the second generator's streams. */
+enum { TAG_RW = 1, TAG_MM1 = 2, TAG_FF = 3, TAG_PI = 4, TAG_TAUS_SEED = 5 };
 
 /* ------------------------------------------------------------------------ */
 /* Variates.                                                                */
@@ -372,4 +377,96 @@ EXPORT int64_t oracle_pi(uint64_t seed, uint32_t rep, uint64_t points) {
     hits += oracle_pi_inside(blk[j], blk[j + 1]);
   }
   return hits;
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Second generator (paper section 5: the models draw from L'Ecuyer's       */
+/* three-component Tausworthe generator, streams split by Random Spacing).  */
+/* taus88 (L'Ecuyer, Math. Comp. 65, 1996): component j keeps a k_j-bit     */
+/* state in the top bits of a 32-bit word and advances it s_j steps of the  */
+/* recurrence of the trinomial z^k + z^q + 1 at a time; the output is the   */
+/* xor of the three words after the step. (k, q, s) = (31, 13, 12),         */
+/* (29, 2, 4), (28, 3, 17).                                                  */
+/* Random Spacing: the stream of (model, dp, replication) starts from a     */
+/* random state, here the words x, y, z of Philox block (model, dp, rep,    */
+/* TAG_TAUS_SEED) under the run's seed, each raised by 2, 8 or 16 when its  */
+/* k-bit part would be zero. Draw d of a replication is output d of its     */
+/* stream. Models: point i of pi uses outputs 2i, 2i+1; customer n of the   */
+/* M/M/1 queue uses 2n (interarrival) and 2n+1 (service); move t of walker  */
+/* w uses bits 2(t&15) of output w*ceil(T/16) + (t>>4).                      */
+/* ------------------------------------------------------------------------ */
+static uint32_t taus_component(uint32_t z, int k, int q, int s) {
+  uint32_t keep = 0xFFFFFFFFu << (32 - k);
+  uint32_t feedback = ((z << q) ^ z) >> (k - s);
+  return ((z & keep) << s) ^ feedback;
+}
+
+EXPORT uint32_t oracle_taus88_next(uint32_t st[3]) {
+  st[0] = taus_component(st[0], 31, 13, 12);
+  st[1] = taus_component(st[1], 29, 2, 4);
+  st[2] = taus_component(st[2], 28, 3, 17);
+  return st[0] ^ st[1] ^ st[2];
+}
+
+EXPORT void oracle_taus88_seed(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep,
+                               uint32_t st[3]) {
+  uint32_t blk[4];
+  philox_block(seed, model, dp, rep, TAG_TAUS_SEED, blk);
+  st[0] = blk[0] < 2u ? blk[0] + 2u : blk[0];
+  st[1] = blk[1] < 8u ? blk[1] + 8u : blk[1];
+  st[2] = blk[2] < 16u ? blk[2] + 16u : blk[2];
+}
+
+/* n consecutive outputs from state st (st is advanced). */
+EXPORT void oracle_taus88_outputs(uint32_t st[3], uint64_t n, uint32_t *out) {
+  for (uint64_t i = 0; i < n; ++i) out[i] = oracle_taus88_next(st);
+}
+
+EXPORT int64_t oracle_pi_taus(uint64_t seed, uint32_t rep, uint64_t points) {
+  uint32_t st[3];
+  oracle_taus88_seed(seed, TAG_PI, 0, rep, st);
+  int64_t hits = 0;
+  for (uint64_t i = 0; i < points; ++i) {
+    uint32_t wx = oracle_taus88_next(st);
+    uint32_t wy = oracle_taus88_next(st);
+    hits += oracle_pi_inside(wx, wy);
+  }
+  return hits;
+}
+
+EXPORT int oracle_rw_taus(uint64_t seed, uint32_t rep, uint32_t walkers, uint32_t grid,
+                          uint32_t steps, int64_t *ssd, int64_t *distinct) {
+  uint8_t *dirs = (uint8_t *)malloc((size_t)walkers * steps + 1);
+  if (!dirs) return -1;
+  uint32_t st[3];
+  oracle_taus88_seed(seed, TAG_RW, 0, rep, st);
+  uint32_t per_walker = (steps + 15u) / 16u;
+  for (uint32_t w = 0; w < walkers; ++w) {
+    for (uint32_t j = 0; j < per_walker; ++j) {
+      uint32_t word = oracle_taus88_next(st);
+      for (uint32_t t = 16u * j; t < steps && t < 16u * j + 16u; ++t)
+        dirs[(size_t)w * steps + t] = (uint8_t)((word >> (2u * (t & 15u))) & 3u);
+    }
+  }
+  int rc = rw_core(0, 0, walkers, grid, steps, dirs, ssd, distinct);
+  free(dirs);
+  return rc;
+}
+
+EXPORT int oracle_mm1_taus(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, float lambda,
+                           float mu, uint64_t K, float out[3], float *feat) {
+  if (N == 0 || K > N) return -1;
+  mm1_acc acc;
+  memset(&acc, 0, sizeof(acc));
+  float t_prev = 0.0f;
+  uint32_t st[3];
+  oracle_taus88_seed(seed, TAG_MM1, dp, rep, st);
+  for (uint64_t n = 0; n < N; ++n) {
+    float a = oracle_exp_variate(oracle_taus88_next(st), lambda);
+    float s = oracle_exp_variate(oracle_taus88_next(st), mu);
+    mm1_customer(a, s, &t_prev, n, K, &acc, NULL, NULL, NULL);
+  }
+  mm1_finish(&acc, N, K, lambda, mu, out, feat);
+  return 0;
 }
