@@ -64,6 +64,21 @@ typedef enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3, MRIP_PI = 4 } mrip_model;
  * mrip_set_shape). LANE0: one replication per wavefront with only its first
  * lane working, the paper's own warp-level form (sections 3 and 4: every
  * thread but the first of its warp disabled). AUTO picks WAVE. */
+/* Stream source. PHILOX (default): counter-based Philox4x32-10, as stated
+ * per model below. TAUS88: the generator the paper's models draw from
+ * (section 5), L'Ecuyer's three-component Tausworthe generator taus88
+ * ((k, q, s) = (31, 13, 12), (29, 2, 4), (28, 3, 17); the output is the xor
+ * of the three component words after each step), with streams split by
+ * Random Spacing (section 5): the stream of (model, dp, replication r)
+ * starts from words x, y, z of Philox block (model tag, dp, r, 5) under the
+ * seed, raised by 2, 8 and 16 when below them; draw d of a replication is
+ * output d of its stream. Running a second set of replications on another
+ * generator checks that the streams do not bias the results (section 5.3).
+ * On TAUS88 streams: pi point i takes outputs 2i, 2i+1; M/M/1 customer n
+ * takes 2n (A) and 2n+1 (S); walk move t of walker w takes bits 2(t&15) of
+ * output w*ceil(steps/16) + (t>>4). */
+typedef enum { MRIP_RNG_PHILOX = 0, MRIP_RNG_TAUS88 = 1 } mrip_rng;
+
 typedef enum {
   MRIP_MAP_AUTO = 0,
   MRIP_MAP_SIMT = 1,
@@ -165,6 +180,14 @@ MRIP_API mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t reps_per_wave, uint32
  * empties). Per-customer values are those of the unsplit run; the means
  * differ only by fp32 summation order. */
 MRIP_API mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep);
+
+/* Stream source of mrip_run (see mrip_rng). TAUS88 is defined for the
+ * random walk, M/M/1 and pi models, every mapping, one wavefront per
+ * replication; MRIP_E_UNSUPPORTED for the forest fire, for a context with
+ * mrip_set_split > 1, and later plan or control-variate calls on it (those
+ * use Philox). Builds and uploads the generator's jump tables (23.6 KB)
+ * once, synchronously. Default PHILOX. */
+MRIP_API mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng);
 
 /* --------------------------------------------------------------- the path */
 
@@ -329,6 +352,14 @@ MRIP_API mrip_status mrip_cv_times(mrip_ctx ctx, float *full_ms, float *prefix_m
  * key = seed). Device pointers, n blocks. */
 MRIP_API mrip_status mrip_philox(uint64_t seed, const uint32_t *ctr_dev, uint64_t n, uint32_t *out_dev,
                         void *hip_stream);
+
+/* Raw taus88 outputs: out_dev[i] = output skip + i of the Random Spacing
+ * stream of (model tag, dp, rep) under `seed` (see mrip_rng), each reached by
+ * jumping from the stream's start with the generator's power-of-two jump
+ * tables. Device pointer, n values. Allocates the tables for the call and
+ * synchronises the stream before freeing them. */
+MRIP_API mrip_status mrip_taus88(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep,
+                                 uint64_t skip, uint64_t n, uint32_t *out_dev, void *hip_stream);
 
 /* Student-t quantile t_{p, dof} for 0.5 <= p < 1, dof > 0 (host). */
 MRIP_API double mrip_t_quantile(double p, double dof);

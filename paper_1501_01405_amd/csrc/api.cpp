@@ -14,6 +14,7 @@
 #include "../../include/mrip.h"
 #include "context.hpp"
 #include "kernels.hpp"
+#include "taus.hpp"
 
 namespace mrip {
 double t_quantile(double p, double nu);
@@ -100,6 +101,23 @@ mrip_status finish_stats(const double *nmv, double confidence, mrip_stats_t *out
   out->confidence = confidence;
   out->t_quantile = mrip::t_quantile(0.5 + 0.5 * confidence, (double)(n - 1));
   out->half_width = out->t_quantile * std::sqrt(nmv[2] / (double)n);
+  return MRIP_OK;
+}
+
+// Plans and the control variate draw from Philox only.
+mrip_status philox_only(mrip_ctx c) {
+  if (c->rng != MRIP_RNG_PHILOX)
+    return (c->err = "plans and the control variate use Philox streams"), MRIP_E_UNSUPPORTED;
+  return MRIP_OK;
+}
+
+mrip_status upload_taus_tables(mrip_ctx c) {
+  if (c->taus_tables.p) return MRIP_OK;
+  std::vector<uint32_t> host((size_t)TAUS_TABLES * TAUS_COLS);
+  taus_build_tables(host.data());
+  HIP_TRY(c, c->taus_tables.ensure(host.size() * sizeof(uint32_t)));
+  HIP_TRY(c, hipMemcpy(c->taus_tables.p, host.data(), host.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice));
   return MRIP_OK;
 }
 
@@ -216,7 +234,24 @@ mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep) {
   if (waves_per_rep > 1 && (ctx->model != MRIP_MM1 || ctx->mapping != MRIP_MAP_WAVE))
     return inval(ctx, "splitting a replication is defined for the M/M/1 WAVE engine");
   if (waves_per_rep > 1 && ctx->rpw != 1) return inval(ctx, "splitting needs reps_per_wave = 1");
+  if (waves_per_rep > 1 && ctx->rng != MRIP_RNG_PHILOX)
+    return (ctx->err = "split replications draw from Philox streams"), MRIP_E_UNSUPPORTED;
   ctx->split = waves_per_rep;
+  return MRIP_OK;
+}
+
+mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (rng != MRIP_RNG_PHILOX && rng != MRIP_RNG_TAUS88) return inval(ctx, "unknown generator");
+  if (rng == MRIP_RNG_TAUS88) {
+    if (ctx->model == MRIP_FF)
+      return (ctx->err = "the forest fire draws from Philox streams"), MRIP_E_UNSUPPORTED;
+    if (ctx->split != 1)
+      return (ctx->err = "split replications draw from Philox streams"), MRIP_E_UNSUPPORTED;
+    mrip_status st = upload_taus_tables(ctx);
+    if (st != MRIP_OK) return st;
+  }
+  ctx->rng = rng;
   return MRIP_OK;
 }
 
@@ -263,6 +298,8 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.n_reps = n_reps;
     a.ssd = ctx->out[0].as<int32_t>();
     a.distinct = ctx->out[1].as<int32_t>();
+    a.rng = ctx->rng;
+    a.taus = ctx->taus_tables.as<uint32_t>();
     if (wave) {
       HIP_TRY(ctx, launch_rw_wave(a, ctx->wg, s));
     } else {
@@ -281,6 +318,8 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.mean_w = ctx->out[0].as<float>();
     a.mean_t = ctx->out[1].as<float>();
     a.mean_i = ctx->out[2].as<float>();
+    a.rng = ctx->rng;
+    a.taus = ctx->taus_tables.as<uint32_t>();
     if (a.feature_prefix > 0) {
       HIP_TRY(ctx, ctx->out[3].ensure(n_reps * 40));
       a.features = ctx->out[3].as<float>();
@@ -295,6 +334,8 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.n_reps = n_reps;
     a.hits = ctx->out[0].as<int32_t>();
     a.estimate = ctx->out[1].as<float>();
+    a.rng = ctx->rng;
+    a.taus = ctx->taus_tables.as<uint32_t>();
     if (wave) HIP_TRY(ctx, launch_pi_wave(a, ctx->wg, s));
     else HIP_TRY(ctx, launch_pi_simt(a, ctx->mapping == MRIP_MAP_LANE0, s));
   } else {
@@ -395,6 +436,7 @@ mrip_status mrip_last_run_ms(mrip_ctx ctx, float *ms) {
 
 mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n) {
   if (!ctx) return MRIP_E_INVAL;
+  if (philox_only(ctx) != MRIP_OK) return MRIP_E_UNSUPPORTED;
   if (ctx->model != MRIP_MM1) return (ctx->err = "plans need an M/M/1 context"), MRIP_E_UNSUPPORTED;
   if (!items || n == 0) return inval(ctx, "empty plan");
   if (n > 0xFFFFFFFFull) return inval(ctx, "plan too large");
@@ -512,6 +554,7 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
 
 mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
   if (!ctx) return MRIP_E_INVAL;
+  if (philox_only(ctx) != MRIP_OK) return MRIP_E_UNSUPPORTED;
   if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
   if (ctx->mapping != MRIP_MAP_WAVE)
     return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
@@ -542,6 +585,7 @@ mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_s
 mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, void *hip_stream,
                           uint32_t *best_rpw, uint32_t *best_wg, float *best_ms) {
   if (!ctx) return MRIP_E_INVAL;
+  if (philox_only(ctx) != MRIP_OK) return MRIP_E_UNSUPPORTED;
   if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
   if (ctx->mapping != MRIP_MAP_WAVE)
     return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
@@ -606,6 +650,25 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
 }
 
 // ------------------------------------------------------------- utilities
+
+mrip_status mrip_taus88(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep, uint64_t skip,
+                        uint64_t n, uint32_t *out_dev, void *hip_stream) {
+  if (n == 0) return MRIP_OK;
+  if (!out_dev || n > 0xFFFFFFFFull * 256) return MRIP_E_INVAL;
+  std::vector<uint32_t> host((size_t)TAUS_TABLES * TAUS_COLS);
+  taus_build_tables(host.data());
+  DevBuf tables;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (tables.ensure(host.size() * sizeof(uint32_t)) != hipSuccess) return MRIP_E_NOMEM;
+  if (hipMemcpy(tables.p, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return MRIP_E_HIP;
+  if (launch_taus_dump(seed, model, dp, rep, skip, n, tables.as<uint32_t>(), out_dev, s) !=
+      hipSuccess)
+    return MRIP_E_HIP;
+  // the tables are freed on return: wait for the kernel that reads them
+  return hipStreamSynchronize(s) == hipSuccess ? MRIP_OK : MRIP_E_HIP;
+}
 
 mrip_status mrip_philox(uint64_t seed, const uint32_t *ctr_dev, uint64_t n, uint32_t *out_dev,
                         void *hip_stream) {

@@ -89,6 +89,9 @@ struct mrip_ctx_s {
   // plans: wavefronts per long item (1 = none) and what counts as long
   uint32_t plan_split = 4;
   uint64_t long_min = 65536;
+  // stream source of mrip_run (MRIP_RNG_*) and, for taus88, its jump tables
+  int rng = MRIP_RNG_PHILOX;
+  mrip::DevBuf taus_tables;
 
   mrip::DevBuf out[4];
   mrip::DevBuf scratch;

@@ -192,6 +192,8 @@ mrip_status mrip_cv_train(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n,
                           const float *theta0, const mrip_cv_hparams *hp_in, uint64_t seed,
                           void *hip_stream) {
   if (!ctx) return MRIP_E_INVAL;
+  if (ctx->rng != MRIP_RNG_PHILOX)
+    return (ctx->err = "the control variate uses Philox streams"), MRIP_E_UNSUPPORTED;
   if (ctx->model != MRIP_MM1) return (ctx->err = "the control variate needs an M/M/1 context"), MRIP_E_UNSUPPORTED;
   const uint64_t K = ctx->mm1.feature_prefix;
   if (K == 0) return bad(ctx, "the context needs feature_prefix > 0");
@@ -450,6 +452,8 @@ mrip_status mrip_cv_apply(mrip_ctx ctx, const mrip_plan_item *full, uint64_t n_f
                           const mrip_plan_item *prefix, uint64_t n_prefix, uint64_t seed,
                           void *hip_stream) {
   if (!ctx) return MRIP_E_INVAL;
+  if (ctx->rng != MRIP_RNG_PHILOX)
+    return (ctx->err = "the control variate uses Philox streams"), MRIP_E_UNSUPPORTED;
   CvState &cv = ctx->cv;
   if (!cv.trained) return (ctx->err = "train the control variate first"), MRIP_E_STATE;
   const uint64_t K = ctx->mm1.feature_prefix;

@@ -14,7 +14,7 @@
 
 namespace mrip {
 
-enum : uint32_t { TAG_RW = 1, TAG_MM1 = 2, TAG_FF = 3 };
+enum : uint32_t { TAG_RW = 1, TAG_MM1 = 2, TAG_FF = 3, TAG_PI = 4 };
 
 struct Block4 {
   uint32_t x, y, z, w;

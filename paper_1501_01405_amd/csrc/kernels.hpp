@@ -7,6 +7,10 @@
 
 namespace mrip {
 
+// Stream source of a run: counter-based Philox (default) or taus88 with
+// Random Spacing (taus.hpp); `taus` points to the device jump tables.
+enum Rng : int { RNG_PHILOX = 0, RNG_TAUS88 = 1 };
+
 // ------------------------------------------------------------ random walk
 struct RwArgs {
   uint64_t seed;
@@ -14,6 +18,8 @@ struct RwArgs {
   uint64_t n_reps;
   int32_t *ssd, *distinct;
   uint32_t *scratch_bitmaps;  // SIMT only: n_reps * grid*grid/32 words
+  int rng;
+  const uint32_t *taus;
 };
 hipError_t launch_rw_wave(const RwArgs &a, uint32_t workgroup, hipStream_t s);
 // one_lane: one working lane per wavefront (the paper's WLP form)
@@ -37,6 +43,8 @@ struct Mm1Args {
   uint32_t *queue_head;         // plan mode: device counter, zero at launch
   float *mean_w, *mean_t, *mean_i;
   float *features;              // n x 10 when feature_prefix > 0
+  int rng;                      // uniform mode only; plans use Philox
+  const uint32_t *taus;
 };
 hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t reps_per_wave, uint32_t workgroup,
                            hipStream_t s);
@@ -74,6 +82,8 @@ struct PiArgs {
   uint64_t n_reps;
   int32_t *hits;
   float *estimate;  // 4 hits / points
+  int rng;
+  const uint32_t *taus;
 };
 hipError_t launch_pi_wave(const PiArgs &a, uint32_t workgroup, hipStream_t s);
 hipError_t launch_pi_simt(const PiArgs &a, bool one_lane, hipStream_t s);
@@ -98,6 +108,10 @@ hipError_t launch_reduce_f64_gather(const void *x, int dtype, const uint32_t *in
                                     hipStream_t s);
 
 // ------------------------------------------------------------ utilities
+// out[i] = output skip + i of the taus88 stream of (model, dp, rep), each
+// reached by its own jump from the stream's start (tests the jump tables).
+hipError_t launch_taus_dump(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep, uint64_t skip,
+                            uint64_t n, const uint32_t *tables, uint32_t *out, hipStream_t s);
 hipError_t launch_philox_dump(uint64_t seed, const uint32_t *ctr, uint64_t n, uint32_t *out,
                               hipStream_t s);
 

@@ -19,8 +19,14 @@
 //
 // SIMT mapping (one replication per lane): the sequential recursion, one
 // customer after the other, as the paper's thread-per-replication form.
+//
+// On taus88 streams customer n takes outputs 2n (A) and 2n+1 (S) of the
+// replication's stream. A WAVE lane reads its P customers' 2P outputs in
+// order and then jumps over the rest of the chunk with a stride table; a
+// SIMT lane reads the stream in order.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "taus.hpp"
 
 namespace mrip {
 
@@ -79,6 +85,31 @@ __device__ __forceinline__ Draw<P> draw_chunk(uint64_t base, const Rep &d, uint3
   }
   return r;
 }
+
+// Draw sources for wave_group: chunk c is requested in order c = 0, 1, ...
+struct PhiloxSource {
+  uint32_t k0, k1;
+  template <int RPW, int P>
+  __device__ __forceinline__ Draw<P> next(uint64_t base, const Rep &d) {
+    return draw_chunk<RPW, P>(base, d, k0, k1);
+  }
+};
+
+struct TausSource {
+  Taus t;
+  const uint32_t *__restrict__ stride;  // jump over the rest of a chunk
+  template <int RPW, int P>
+  __device__ __forceinline__ Draw<P> next(uint64_t, const Rep &d) {
+    Draw<P> r;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      r.A[j] = exp_variate(taus_next(t), d.ca);
+      r.S[j] = exp_variate(taus_next(t), d.cs);
+    }
+    taus_jump_uniform(t, stride);
+    return r;
+  }
+};
 
 // The scanned maps of one chunk: this lane's exclusive prefix (ea, eb) and
 // the four segment totals.
@@ -236,9 +267,8 @@ __device__ __forceinline__ void fixup_chunk(uint64_t base, const Draw<P> &dr, co
 
 // Runs the replications of one wavefront (RPW of them, one per lane group)
 // to completion and writes their outputs.
-template <int RPW>
-__device__ void wave_group(const Rep &d, uint32_t k0, uint32_t k1, uint64_t K,
-                           const Mm1Args &a) {
+template <int RPW, class Src>
+__device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a) {
   constexpr int P = MM1_P;
   constexpr int S = 4 / RPW;
   constexpr int WIDTH = 16 * S;  // lanes per replication
@@ -263,7 +293,7 @@ __device__ void wave_group(const Rep &d, uint32_t k0, uint32_t k1, uint64_t K,
   uint32_t c = 0;
 #define MRIP_CHUNK(F, TL)                                                            \
   {                                                                                  \
-    const Draw<P> cur = draw_chunk<RPW, P>((uint64_t)c * CHUNK, d, k0, k1);         \
+    const Draw<P> cur = src.template next<RPW, P>((uint64_t)c * CHUNK, d);          \
     wave_chunk<RPW, P, F, TL>(c * CHUNK, cur, d, K, carry, acc, ft);                 \
   }
   for (; c < fchunks; ++c) MRIP_CHUNK(true, true)
@@ -338,7 +368,7 @@ __device__ __forceinline__ Rep item_rep(const Mm1Args &a, uint64_t slot, uint64_
   return d;
 }
 
-template <int RPW>
+template <int RPW, int RNG>
 __global__ void mm1_wave_kernel(Mm1Args a, float ca, float cs) {
   constexpr int S = 4 / RPW;
   const int lane = threadIdx.x & 63;
@@ -347,7 +377,17 @@ __global__ void mm1_wave_kernel(Mm1Args a, float ca, float cs) {
   const uint64_t r = wave * RPW + q;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   if (wave * RPW >= a.n_reps) return;  // whole wave idle (wave-uniform)
-  wave_group<RPW>(uniform_rep(a, r, ca, cs), k0, k1, a.feature_prefix, a);
+  const Rep d = uniform_rep(a, r, ca, cs);
+  if (RNG == RNG_TAUS88) {
+    TausSource src;
+    src.t = taus_seed(TAG_MM1, d.dp, d.rep, k0, k1);
+    src.stride = a.taus + (uint64_t)taus_mm1_stride_table(RPW) * TAUS_COLS;
+    taus_skip(src.t, 2 * lane_first_customer<RPW, MM1_P>(0), a.taus);
+    wave_group<RPW>(d, src, a.feature_prefix, a);
+  } else {
+    PhiloxSource src{k0, k1};
+    wave_group<RPW>(d, src, a.feature_prefix, a);
+  }
 }
 
 // Persistent plan kernel: every wave pops units of RPW items (longest first)
@@ -365,8 +405,8 @@ __global__ void mm1_plan_kernel(Mm1Args a, uint64_t n_items) {
     if (lane == 0) unit = atomicAdd(a.queue_head, 1u);
     unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)unit, 0, 64));
     if (unit >= n_units) break;
-    wave_group<RPW>(item_rep(a, (uint64_t)unit * RPW + q, n_items), k0, k1, a.feature_prefix,
-                    a);
+    PhiloxSource src{k0, k1};
+    wave_group<RPW>(item_rep(a, (uint64_t)unit * RPW + q, n_items), src, a.feature_prefix, a);
   }
 }
 
@@ -533,14 +573,14 @@ __global__ __launch_bounds__(256) void mm1_plan_split_kernel(Mm1Args a, uint64_t
     unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)unit, 0, 64));
     if (unit >= n_units) break;
     const uint64_t j = (uint64_t)unit * RPW + q;
-    wave_group<RPW>(item_rep(a, n_long + j, j < n_short ? n_items : 0), k0, k1,
-                    a.feature_prefix, a);
+    PhiloxSource src{k0, k1};
+    wave_group<RPW>(item_rep(a, n_long + j, j < n_short ? n_items : 0), src, a.feature_prefix, a);
   }
 }
 
 // STRIDE = 1: one replication per lane; 64: one working lane per wavefront
 // (the paper's WLP form).
-template <int STRIDE>
+template <int STRIDE, int RNG>
 __global__ void mm1_simt_kernel(Mm1Args a, float ca, float cs) {
   if (threadIdx.x % STRIDE) return;
   const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
@@ -550,8 +590,18 @@ __global__ void mm1_simt_kernel(Mm1Args a, float ca, float cs) {
   float tprev = 0.0f;
   Kahan sw, st, si;
   Feat ft;
+  Taus ts;
+  if (RNG == RNG_TAUS88) ts = taus_seed(TAG_MM1, 0u, (uint32_t)r, k0, k1);
   for (uint64_t k = 0; 2 * k < N; ++k) {
-    const Block4 b = philox((uint32_t)k, 0u, (uint32_t)r, TAG_MM1, k0, k1);
+    Block4 b;
+    if (RNG == RNG_TAUS88) {
+      b.x = taus_next(ts);
+      b.y = taus_next(ts);
+      b.z = taus_next(ts);
+      b.w = taus_next(ts);
+    } else {
+      b = philox((uint32_t)k, 0u, (uint32_t)r, TAG_MM1, k0, k1);
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const uint64_t n = 2 * k + h;
@@ -612,9 +662,16 @@ hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t rpw, uint32_t wg, hipStrea
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (waves + wpb - 1) / wpb;
   const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
-  if (rpw == 1) hipLaunchKernelGGL(mm1_wave_kernel<1>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, ca, cs);
-  else if (rpw == 2) hipLaunchKernelGGL(mm1_wave_kernel<2>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, ca, cs);
-  else hipLaunchKernelGGL(mm1_wave_kernel<4>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, ca, cs);
+  const dim3 g((uint32_t)blocks), b(wg);
+  if (a.rng == RNG_TAUS88) {
+    if (rpw == 1) hipLaunchKernelGGL((mm1_wave_kernel<1, RNG_TAUS88>), g, b, 0, s, a, ca, cs);
+    else if (rpw == 2) hipLaunchKernelGGL((mm1_wave_kernel<2, RNG_TAUS88>), g, b, 0, s, a, ca, cs);
+    else hipLaunchKernelGGL((mm1_wave_kernel<4, RNG_TAUS88>), g, b, 0, s, a, ca, cs);
+  } else {
+    if (rpw == 1) hipLaunchKernelGGL((mm1_wave_kernel<1, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
+    else if (rpw == 2) hipLaunchKernelGGL((mm1_wave_kernel<2, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
+    else hipLaunchKernelGGL((mm1_wave_kernel<4, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
+  }
   return hipGetLastError();
 }
 
@@ -633,8 +690,14 @@ hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s) {
   const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
   const uint64_t blocks = (threads + wg - 1) / wg;
   const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
-  if (one_lane) hipLaunchKernelGGL(mm1_simt_kernel<64>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, ca, cs);
-  else hipLaunchKernelGGL(mm1_simt_kernel<1>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, ca, cs);
+  const dim3 g((uint32_t)blocks), b(wg);
+  if (a.rng == RNG_TAUS88) {
+    if (one_lane) hipLaunchKernelGGL((mm1_simt_kernel<64, RNG_TAUS88>), g, b, 0, s, a, ca, cs);
+    else hipLaunchKernelGGL((mm1_simt_kernel<1, RNG_TAUS88>), g, b, 0, s, a, ca, cs);
+  } else {
+    if (one_lane) hipLaunchKernelGGL((mm1_simt_kernel<64, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
+    else hipLaunchKernelGGL((mm1_simt_kernel<1, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
+  }
   return hipGetLastError();
 }
 

@@ -9,14 +9,17 @@
 // (four per lane per iteration) and sum their counts at the end. SIMT: one
 // replication per lane (STRIDE 1) or per wavefront's first lane (STRIDE 64,
 // the paper's WLP form).
+//
+// On taus88 streams point i takes outputs 2i and 2i+1 of the replication's
+// stream; in the WAVE form lane l takes the contiguous run of points
+// [l B, (l+1) B), B = ceil(points / 64), after jumping 2 l B outputs.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "taus.hpp"
 
 namespace mrip {
 
 namespace {
-
-constexpr uint32_t TAG_PI = 4;
 
 __device__ __forceinline__ uint32_t inside(uint32_t wx, uint32_t wy) {
   const uint64_t a = 2u * (wx >> 8) + 1u, b = 2u * (wy >> 8) + 1u;
@@ -66,12 +69,58 @@ __global__ void pi_simt_kernel(PiArgs a) {
   a.estimate[r] = (float)(4.0 * (double)hits / (double)a.points);
 }
 
+__global__ void pi_wave_taus_kernel(PiArgs a) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t r = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= a.n_reps) return;  // wave-uniform
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  const uint64_t per = (a.points + 63) / 64;
+  const uint64_t p0 = min(a.points, (uint64_t)lane * per), p1 = min(a.points, p0 + per);
+  Taus t = taus_seed(TAG_PI, 0u, (uint32_t)r, k0, k1);
+  taus_skip(t, 2 * p0, a.taus);
+  uint32_t hits = 0;
+  uint64_t i = p0;
+  for (; i + 2 <= p1; i += 2) {
+    const uint32_t x0 = taus_next(t), y0 = taus_next(t);
+    const uint32_t x1 = taus_next(t), y1 = taus_next(t);
+    hits += inside(x0, y0) + inside(x1, y1);
+  }
+  if (i < p1) {
+    const uint32_t x0 = taus_next(t), y0 = taus_next(t);
+    hits += inside(x0, y0);
+  }
+  const int total = group_sum_i((int)hits, 64);
+  if (lane == 0) {
+    a.hits[r] = total;
+    a.estimate[r] = (float)(4.0 * (double)total / (double)a.points);
+  }
+}
+
+template <int STRIDE>
+__global__ void pi_simt_taus_kernel(PiArgs a) {
+  if (threadIdx.x % STRIDE) return;
+  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
+  if (r >= a.n_reps) return;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  Taus t = taus_seed(TAG_PI, 0u, (uint32_t)r, k0, k1);
+  uint32_t hits = 0;
+  for (uint64_t i = 0; i < a.points; ++i) {
+    const uint32_t x = taus_next(t), y = taus_next(t);
+    hits += inside(x, y);
+  }
+  a.hits[r] = (int32_t)hits;
+  a.estimate[r] = (float)(4.0 * (double)hits / (double)a.points);
+}
+
 }  // namespace
 
 hipError_t launch_pi_wave(const PiArgs &a, uint32_t wg, hipStream_t s) {
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (a.n_reps + wpb - 1) / wpb;
-  hipLaunchKernelGGL(pi_wave_kernel, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  if (a.rng == RNG_TAUS88)
+    hipLaunchKernelGGL(pi_wave_taus_kernel, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  else
+    hipLaunchKernelGGL(pi_wave_kernel, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
   return hipGetLastError();
 }
 
@@ -79,8 +128,14 @@ hipError_t launch_pi_simt(const PiArgs &a, bool one_lane, hipStream_t s) {
   const uint32_t wg = 64;
   const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
   const uint64_t blocks = (threads + wg - 1) / wg;
-  if (one_lane) hipLaunchKernelGGL(pi_simt_kernel<64>, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
-  else hipLaunchKernelGGL(pi_simt_kernel<1>, dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  const dim3 g((uint32_t)blocks), b(wg);
+  if (a.rng == RNG_TAUS88) {
+    if (one_lane) hipLaunchKernelGGL(pi_simt_taus_kernel<64>, g, b, 0, s, a);
+    else hipLaunchKernelGGL(pi_simt_taus_kernel<1>, g, b, 0, s, a);
+  } else {
+    if (one_lane) hipLaunchKernelGGL(pi_simt_kernel<64>, g, b, 0, s, a);
+    else hipLaunchKernelGGL(pi_simt_kernel<1>, g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 

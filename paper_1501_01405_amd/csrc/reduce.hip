@@ -6,6 +6,7 @@
 // in int64 for the mean.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "taus.hpp"
 
 namespace mrip {
 
@@ -116,6 +117,15 @@ __global__ void philox_dump_kernel(uint64_t seed, const uint32_t *ctr, uint64_t 
   out[4 * i + 3] = b.w;
 }
 
+__global__ void taus_dump_kernel(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep,
+                                 uint64_t skip, uint64_t n, const uint32_t *tables, uint32_t *out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Taus t = taus_seed(model, dp, rep, (uint32_t)seed, (uint32_t)(seed >> 32));
+  taus_skip(t, skip + i, tables);
+  out[i] = taus_next(t);
+}
+
 }  // namespace
 
 hipError_t launch_reduce_f64(const void *x, int dtype, uint64_t n, const uint64_t *offsets,
@@ -136,6 +146,14 @@ hipError_t launch_reduce_f64_gather(const void *x, int dtype, const uint32_t *in
 hipError_t launch_reduce_f64_multi(const ReduceSet &set, uint32_t n_outputs, uint64_t n,
                                    double *out, hipStream_t s) {
   hipLaunchKernelGGL(reduce_multi_kernel, dim3(n_outputs), dim3(RB), 0, s, set, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_taus_dump(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep, uint64_t skip,
+                            uint64_t n, const uint32_t *tables, uint32_t *out, hipStream_t s) {
+  const uint64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(taus_dump_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, seed, model, dp,
+                     rep, skip, n, tables, out);
   return hipGetLastError();
 }
 

@@ -9,8 +9,14 @@
 // after the other and keeps the replication's bitmap in global memory, the
 // per-thread state the paper's thread-per-replication form implies. The
 // same kernel with one working lane per wavefront is the paper's own WLP.
+//
+// On taus88 streams (RNG = RNG_TAUS88) move t of walker w takes bits
+// 2(t&15) of output w ceil(T/16) + (t>>4) of the replication's stream: each
+// walker reads a contiguous run, so a WAVE lane jumps to its walker's run and
+// a SIMT lane reads the stream in order, walker after walker.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "taus.hpp"
 
 namespace mrip {
 
@@ -24,7 +30,38 @@ __device__ __forceinline__ void step_delta(uint32_t d, int &dx, int &dy) {
 // Set the visited bit of lattice site c (row-major) in an LDS bitmap.
 __device__ __forceinline__ void mark(uint32_t *bm, int c) { atomicOr(&bm[c >> 5], 1u << (c & 31)); }
 
-template <int GRID>
+template <int GRID, bool LDS>
+__device__ __forceinline__ void move1(uint32_t d, bool active, int &x, int &y, int &ux, int &uy,
+                                      uint32_t *bm) {
+  int dx, dy;
+  step_delta(d, dx, dy);
+  ux += dx;
+  uy += dy;
+  x = (x + dx) & (GRID - 1);
+  y = (y + dy) & (GRID - 1);
+  const int c = y * GRID + x;
+  if (LDS) {
+    if (active) mark(bm, c);
+  } else {
+    bm[c >> 5] |= 1u << (c & 31);
+  }
+}
+
+// Up to 16 moves from one 32-bit word (2 bits each, lowest first): moves
+// g .. min(g + 16, steps) - 1.
+template <int GRID, bool LDS>
+__device__ __forceinline__ void walk16(uint32_t word, uint32_t g, uint32_t steps, bool active,
+                                       int &x, int &y, int &ux, int &uy, uint32_t *bm) {
+  if (g + 16u <= steps) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) move1<GRID, LDS>((word >> (2 * i)) & 3u, active, x, y, ux, uy, bm);
+  } else {
+    for (uint32_t i = 0; g + i < steps; ++i)
+      move1<GRID, LDS>((word >> (2 * i)) & 3u, active, x, y, ux, uy, bm);
+  }
+}
+
+template <int GRID, int RNG>
 __global__ void rw_wave_kernel(RwArgs a) {
   constexpr int WORDS = GRID * GRID / 32;
   extern __shared__ uint32_t lds[];
@@ -42,24 +79,18 @@ __global__ void rw_wave_kernel(RwArgs a) {
   int ux = 0, uy = 0;
   if (active) mark(bm, y * GRID + x);
 
-  for (uint32_t g = 0; g < a.steps; g += 64) {
-    const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
-    const uint32_t words[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      uint32_t word = words[j];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (g + 16u * j + i >= a.steps) break;
-        int dx, dy;
-        step_delta(word & 3u, dx, dy);
-        word >>= 2;
-        ux += dx;
-        uy += dy;
-        x = (x + dx) & (GRID - 1);
-        y = (y + dy) & (GRID - 1);
-        if (active) mark(bm, y * GRID + x);
-      }
+  if (RNG == RNG_TAUS88) {
+    Taus t = taus_seed(TAG_RW, 0u, (uint32_t)r, k0, k1);
+    taus_skip(t, (uint64_t)w * ((a.steps + 15) / 16), a.taus);
+    for (uint32_t g = 0; g < a.steps; g += 16)
+      walk16<GRID, true>(taus_next(t), g, a.steps, active, x, y, ux, uy, bm);
+  } else {
+    for (uint32_t g = 0; g < a.steps; g += 64) {
+      const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
+      walk16<GRID, true>(b.x, g, a.steps, active, x, y, ux, uy, bm);
+      walk16<GRID, true>(b.y, g + 16, a.steps, active, x, y, ux, uy, bm);
+      walk16<GRID, true>(b.z, g + 32, a.steps, active, x, y, ux, uy, bm);
+      walk16<GRID, true>(b.w, g + 48, a.steps, active, x, y, ux, uy, bm);
     }
   }
   __syncthreads();
@@ -77,7 +108,7 @@ __global__ void rw_wave_kernel(RwArgs a) {
 // STRIDE = 1: one replication per lane. STRIDE = 64: one replication per
 // wavefront with only its first lane working (the paper's WLP form, 63 of
 // 64 lanes idle).
-template <int GRID, int STRIDE>
+template <int GRID, int STRIDE, int RNG>
 __global__ void rw_simt_kernel(RwArgs a) {
   constexpr int WORDS = GRID * GRID / 32;
   if (threadIdx.x % STRIDE) return;
@@ -87,27 +118,23 @@ __global__ void rw_simt_kernel(RwArgs a) {
   uint32_t *bm = a.scratch_bitmaps + r * WORDS;
   for (int i = 0; i < WORDS; ++i) bm[i] = 0u;
   int ssd = 0;
+  Taus t;
+  if (RNG == RNG_TAUS88) t = taus_seed(TAG_RW, 0u, (uint32_t)r, k0, k1);
   for (uint32_t w = 0; w < a.walkers; ++w) {
     int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
     int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
     int ux = 0, uy = 0;
     bm[(y * GRID + x) >> 5] |= 1u << ((y * GRID + x) & 31);
-    for (uint32_t g = 0; g < a.steps; g += 64) {
-      const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
-      const uint32_t words[4] = {b.x, b.y, b.z, b.w};
-      for (int j = 0; j < 4; ++j) {
-        uint32_t word = words[j];
-        for (int i = 0; i < 16; ++i) {
-          if (g + 16u * j + i >= a.steps) break;
-          int dx, dy;
-          step_delta(word & 3u, dx, dy);
-          word >>= 2;
-          ux += dx;
-          uy += dy;
-          x = (x + dx) & (GRID - 1);
-          y = (y + dy) & (GRID - 1);
-          bm[(y * GRID + x) >> 5] |= 1u << ((y * GRID + x) & 31);
-        }
+    if (RNG == RNG_TAUS88) {
+      for (uint32_t g = 0; g < a.steps; g += 16)
+        walk16<GRID, false>(taus_next(t), g, a.steps, true, x, y, ux, uy, bm);
+    } else {
+      for (uint32_t g = 0; g < a.steps; g += 64) {
+        const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
+        walk16<GRID, false>(b.x, g, a.steps, true, x, y, ux, uy, bm);
+        walk16<GRID, false>(b.y, g + 16, a.steps, true, x, y, ux, uy, bm);
+        walk16<GRID, false>(b.z, g + 32, a.steps, true, x, y, ux, uy, bm);
+        walk16<GRID, false>(b.w, g + 48, a.steps, true, x, y, ux, uy, bm);
       }
     }
     ssd += ux * ux + uy * uy;
@@ -123,7 +150,10 @@ hipError_t wave_launch(const RwArgs &a, uint32_t wg, hipStream_t s) {
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (a.n_reps + wpb - 1) / wpb;
   const size_t lds = (size_t)wpb * (GRID * GRID / 32) * sizeof(uint32_t);
-  hipLaunchKernelGGL(rw_wave_kernel<GRID>, dim3((uint32_t)blocks), dim3(wg), lds, s, a);
+  if (a.rng == RNG_TAUS88)
+    hipLaunchKernelGGL((rw_wave_kernel<GRID, RNG_TAUS88>), dim3((uint32_t)blocks), dim3(wg), lds, s, a);
+  else
+    hipLaunchKernelGGL((rw_wave_kernel<GRID, RNG_PHILOX>), dim3((uint32_t)blocks), dim3(wg), lds, s, a);
   return hipGetLastError();
 }
 
@@ -132,8 +162,14 @@ hipError_t simt_launch(const RwArgs &a, bool one_lane, hipStream_t s) {
   const uint32_t wg = 64;
   const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
   const uint64_t blocks = (threads + wg - 1) / wg;
-  if (one_lane) hipLaunchKernelGGL((rw_simt_kernel<GRID, 64>), dim3((uint32_t)blocks), dim3(wg), 0, s, a);
-  else hipLaunchKernelGGL((rw_simt_kernel<GRID, 1>), dim3((uint32_t)blocks), dim3(wg), 0, s, a);
+  const dim3 g((uint32_t)blocks), b(wg);
+  if (a.rng == RNG_TAUS88) {
+    if (one_lane) hipLaunchKernelGGL((rw_simt_kernel<GRID, 64, RNG_TAUS88>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((rw_simt_kernel<GRID, 1, RNG_TAUS88>), g, b, 0, s, a);
+  } else {
+    if (one_lane) hipLaunchKernelGGL((rw_simt_kernel<GRID, 64, RNG_PHILOX>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((rw_simt_kernel<GRID, 1, RNG_PHILOX>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 

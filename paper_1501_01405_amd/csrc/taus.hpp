@@ -1,0 +1,112 @@
+// Second generator: L'Ecuyer's three-component Tausworthe generator taus88
+// (Math. Comp. 65, 1996), the generator the paper's models draw from
+// (section 5), with streams split by Random Spacing (section 5: each
+// replication's stream starts from a random state).
+//
+// Component j keeps a k_j-bit state in the top bits of a word and advances
+// s_j steps of the linear recurrence of the trinomial z^k + z^q + 1 at a
+// time; the output is the xor of the three words after the step.
+// (k, q, s) = (31, 13, 12), (29, 2, 4), (28, 3, 17).
+//
+// Random Spacing: the stream of (model, dp, replication) starts from words
+// x, y, z of Philox block (model, dp, rep, 5) under the run's seed, each
+// raised by 2, 8 or 16 when its k-bit part would be zero. Draw d of a
+// replication is output d of its stream.
+//
+// Every step is linear over GF(2), so d steps are one 88-column matrix
+// (per component, the images of the k state bits); lanes that start inside
+// a stream jump there with tables of such matrices built on the host
+// (taus_tables.cpp): tables 0..63 advance 2^j outputs, the next three the
+// per-chunk strides of the M/M/1 wavefront engine.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include "device.hpp"
+#endif
+
+namespace mrip {
+
+constexpr int TAUS_K0 = 31, TAUS_Q0 = 13, TAUS_S0 = 12;
+constexpr int TAUS_K1 = 29, TAUS_Q1 = 2, TAUS_S1 = 4;
+constexpr int TAUS_K2 = 28, TAUS_Q2 = 3, TAUS_S2 = 17;
+constexpr int TAUS_COLS = TAUS_K0 + TAUS_K1 + TAUS_K2;  // 88 words per table
+constexpr int TAUS_POW2 = 64;                           // tables 2^0 .. 2^63
+constexpr int TAUS_TABLES = TAUS_POW2 + 3;              // + M/M/1 strides, rpw 1, 2, 4
+constexpr uint32_t TAG_TAUS_SEED = 5;
+
+// Outputs skipped between two chunks of one lane in the M/M/1 wavefront
+// engine: a chunk takes 2 * 512 / rpw outputs, 16 of them this lane's.
+constexpr uint64_t taus_mm1_stride(uint32_t rpw) { return 2ull * 512 / rpw - 16; }
+constexpr int taus_mm1_stride_table(uint32_t rpw) {
+  return TAUS_POW2 + (rpw == 1 ? 0 : rpw == 2 ? 1 : 2);
+}
+
+// Host: fill `out` (TAUS_TABLES x TAUS_COLS words) with the jump tables.
+void taus_build_tables(uint32_t *out);
+
+#if defined(__HIPCC__)
+struct Taus {
+  uint32_t z0, z1, z2;
+};
+
+template <int K, int Q, int S>
+__device__ __forceinline__ uint32_t taus_component(uint32_t z) {
+  const uint32_t keep = 0xFFFFFFFFu << (32 - K);
+  return ((z & keep) << S) ^ (((z << Q) ^ z) >> (K - S));
+}
+
+__device__ __forceinline__ uint32_t taus_next(Taus &t) {
+  t.z0 = taus_component<TAUS_K0, TAUS_Q0, TAUS_S0>(t.z0);
+  t.z1 = taus_component<TAUS_K1, TAUS_Q1, TAUS_S1>(t.z1);
+  t.z2 = taus_component<TAUS_K2, TAUS_Q2, TAUS_S2>(t.z2);
+  return t.z0 ^ t.z1 ^ t.z2;
+}
+
+// image of the k-bit state of z under one component's table columns
+template <int K>
+__device__ __forceinline__ uint32_t taus_apply(uint32_t z, const uint32_t *__restrict__ cols) {
+  uint32_t acc = 0u;
+  // a short unroll keeps one column and one mask live at a time
+#pragma unroll 4
+  for (int b = 0; b < K; ++b) {
+    const uint32_t m = (uint32_t)((int32_t)(z << (K - 1 - b)) >> 31);  // bit 32-K+b
+    acc ^= m & cols[b];
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void taus_jump(Taus &t, const uint32_t *__restrict__ table) {
+  t.z0 = taus_apply<TAUS_K0>(t.z0, table);
+  t.z1 = taus_apply<TAUS_K1>(t.z1, table + TAUS_K0);
+  t.z2 = taus_apply<TAUS_K2>(t.z2, table + TAUS_K0 + TAUS_K1);
+}
+
+// The same jump for a table address that is uniform across the wavefront
+// (a kernel argument plus a constant): the table is re-read at every jump
+// with scalar loads instead of being kept in 88 scalar registers across the
+// caller's loop, where it would spill.
+__device__ __forceinline__ void taus_jump_uniform(Taus &t, const uint32_t *__restrict__ table) {
+  asm volatile("" : "+s"(table));
+  taus_jump(t, table);
+}
+
+// Random Spacing start state of the stream of (model, dp, rep).
+__device__ __forceinline__ Taus taus_seed(uint32_t model, uint32_t dp, uint32_t rep, uint32_t k0,
+                                          uint32_t k1) {
+  const Block4 b = philox(model, dp, rep, TAG_TAUS_SEED, k0, k1);
+  Taus t;
+  t.z0 = b.x < 2u ? b.x + 2u : b.x;
+  t.z1 = b.y < 8u ? b.y + 8u : b.y;
+  t.z2 = b.z < 16u ? b.z + 16u : b.z;
+  return t;
+}
+
+// Advance by d outputs with the power-of-two tables.
+__device__ __forceinline__ void taus_skip(Taus &t, uint64_t d, const uint32_t *__restrict__ tables) {
+  for (int j = 0; d != 0; ++j, d >>= 1)
+    if (d & 1u) taus_jump(t, tables + (uint64_t)j * TAUS_COLS);
+}
+#endif
+
+}  // namespace mrip

@@ -17,6 +17,7 @@ MRIP_OK, MRIP_E_INVAL, MRIP_E_NOMEM, MRIP_E_HIP, MRIP_E_STATE, MRIP_E_TOO_FEW, \
     MRIP_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MRIP_RW, MRIP_MM1, MRIP_FF, MRIP_PI = 1, 2, 3, 4
 MRIP_MAP_AUTO, MRIP_MAP_SIMT, MRIP_MAP_WAVE, MRIP_MAP_LANE0 = 0, 1, 2, 3
+MRIP_RNG_PHILOX, MRIP_RNG_TAUS88 = 0, 1
 MRIP_MLP_PARAMS = 18049
 MRIP_CV_BETA_BINS = 16
 
@@ -76,6 +77,7 @@ _SIGS = {
     "mrip_set_shape": (st, [ctx_t, u32, u32]),
     "mrip_set_split": (st, [ctx_t, u32]),
     "mrip_set_plan_split": (st, [ctx_t, u32, u64]),
+    "mrip_set_rng": (st, [ctx_t, C.c_int]),
     "mrip_get_shape": (st, [ctx_t, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32),
                             C.POINTER(u32)]),
     "mrip_run": (st, [ctx_t, u64, u64, vp]),
@@ -101,6 +103,7 @@ _SIGS = {
                            C.POINTER(mrip_stats_t)]),
     "mrip_cv_times": (st, [ctx_t, C.POINTER(f32), C.POINTER(f32), C.POINTER(f32)]),
     "mrip_philox": (st, [u64, vp, u64, vp, vp]),
+    "mrip_taus88": (st, [u64, u32, u32, u32, u64, u64, vp, vp]),
     "mrip_t_quantile": (f64, [f64, f64]),
     "mrip_status_string": (C.c_char_p, [C.c_int]),
     "mrip_last_error": (C.c_char_p, [ctx_t]),
@@ -188,6 +191,10 @@ def mrip_set_split(ctx, waves_per_rep):
 
 def mrip_set_plan_split(ctx, waves_per_item, long_min=0):
     check(load().mrip_set_plan_split(ctx, waves_per_item, long_min), ctx)
+
+
+def mrip_set_rng(ctx, rng):
+    check(load().mrip_set_rng(ctx, rng), ctx)
 
 
 def mrip_get_shape(ctx):
@@ -328,6 +335,10 @@ def mrip_philox(seed, ctr, n, out, stream=None):
     check(load().mrip_philox(seed, _ptr(ctr), n, _ptr(out), stream))
 
 
+def mrip_taus88(seed, model, dp, rep, skip, n, out, stream=None):
+    check(load().mrip_taus88(seed, model, dp, rep, skip, n, _ptr(out), stream))
+
+
 def mrip_t_quantile(p, dof):
     return load().mrip_t_quantile(p, dof)
 
@@ -388,6 +399,9 @@ class Context:
 
     def shape(self):
         return mrip_get_shape(self.ctx)
+
+    def set_rng(self, rng):
+        mrip_set_rng(self.ctx, rng)
 
     def run(self, n_reps, seed=42, stream=None):
         mrip_run(self.ctx, n_reps, seed, current_stream() if stream is None else stream)

@@ -105,3 +105,22 @@ def test_calls_out_of_order_and_bad_shapes():
     assert L.mrip_plan_stats(ctx, 0, 0.95, C.byref(s)) == mrip.MRIP_E_STATE
     assert b"no" in L.mrip_last_error(ctx)
     L.mrip_destroy(ctx)
+
+
+def test_generator_choice_checks():
+    # error paths only: choosing taus88 successfully uploads jump tables
+    L = mrip.load()
+    ctx = mrip.ctx_t()
+    assert L.mrip_create(C.byref(ctx), mrip.MRIP_FF, C.byref(mrip.ff_params()), 0) == 0
+    assert L.mrip_set_rng(ctx, mrip.MRIP_RNG_TAUS88) == mrip.MRIP_E_UNSUPPORTED
+    assert L.mrip_set_rng(ctx, 7) == mrip.MRIP_E_INVAL
+    assert L.mrip_set_rng(ctx, mrip.MRIP_RNG_PHILOX) == mrip.MRIP_OK
+    L.mrip_destroy(ctx)
+    ctx = mrip.ctx_t()
+    assert L.mrip_create(C.byref(ctx), mrip.MRIP_MM1, C.byref(mrip.mm1_params()), 0) == 0
+    assert L.mrip_set_split(ctx, 2) == mrip.MRIP_OK
+    assert L.mrip_set_rng(ctx, mrip.MRIP_RNG_TAUS88) == mrip.MRIP_E_UNSUPPORTED
+    assert b"Philox" in L.mrip_last_error(ctx)
+    L.mrip_destroy(ctx)
+    assert L.mrip_taus88(1, 4, 0, 0, 0, 0, None, None) == mrip.MRIP_OK  # n = 0: nothing to do
+    assert L.mrip_taus88(1, 4, 0, 0, 0, 5, None, None) == mrip.MRIP_E_INVAL
