@@ -21,12 +21,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 R, N, LAM, MU = 1024, 100000, 0.9, 1.0
-SPLIT = 2  # wavefronts per replication (two per SIMD at 1024 replications)
-# HBM bytes per launch of mm1_split_kernel<2> from rocprofv3 FETCH_SIZE and
+SPLIT = 4  # wavefronts per replication (four per SIMD at 1024 replications)
+# HBM bytes per launch of mm1_split_kernel<SPLIT> from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by the same counter on a 256 MiB copy
 # (profiles/mm1_split_hbm_counters.md); to be re-measured (or set to None)
 # whenever the kernel changes.
-TRAFFIC_BYTES = (116.0 * 2.00 + 48.0 * 1.00) * 1024
+TRAFFIC_BYTES = (144.5 * 2.00 + 96.0 * 1.00) * 1024
 # Peak vector issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, the rate
 # behind the published fp32 vector figure (157.3 TFLOP/s counts an FMA as 2).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
@@ -221,6 +221,29 @@ def extras(torch, mrip, inputs):
     out["cv_1e5"] = cv_experiment(mrip, inputs, 100000)
     out["cv_1e4"] = cv_experiment(mrip, inputs, 10000)
 
+    # the second generator (taus88 with Random Spacing): the same replications
+    # on both generators, their kernel times and the z-score of the difference
+    # of the two estimates (section 5.3: a second generator checks that the
+    # streams do not bias the results)
+    cases = (("mm1_1024x1e5_wait", mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), 0, R * N),
+             ("pi_1024x1e6", mrip.MRIP_PI, mrip.pi_params(1_000_000), 1, 1024 * 10**6),
+             ("rw_1024x64x1000_ssd", mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), 0,
+              1024 * 64 * 1000))
+    tau = {}
+    for name, model, params, o, events in cases:
+        row = {}
+        for gname, g in (("philox", mrip.MRIP_RNG_PHILOX), ("taus88", mrip.MRIP_RNG_TAUS88)):
+            ctx = mrip.Context(model, params, mrip.MRIP_MAP_WAVE)
+            ctx.set_rng(g)
+            v, ms = rate(ctx, 1024, events, runs=2)
+            st = ctx.stats(o)
+            row[gname] = {"kernel_ms": ms, "events_per_s": v, "mean": st["mean"],
+                          "half_width": st["half_width"], "var": st["var"]}
+        a, b = row["philox"], row["taus88"]
+        row["z_difference"] = (a["mean"] - b["mean"]) / math.sqrt((a["var"] + b["var"]) / 1024)
+        tau[name] = row
+    out["taus88_vs_philox"] = tau
+
     # uneven plan: 64 dp x 32 reps, N log-uniform in [1e4, 1e6], one launch
     items = inputs.plan_table()
     ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), mrip.MRIP_MAP_WAVE)
@@ -287,13 +310,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic (Philox4x32-10 streams generated on the device, seed 42+step)",
         "config": {"workload": "M/M/1 MRIP, 1024 replications x 100000 customers, "
-                               "lambda=0.9, mu=1, one replication per wavefront pair",
+                               "lambda=0.9, mu=1, one replication per %d wavefronts" % SPLIT,
                    "replications": R, "customers": N, "mapping": "WAVE",
                    "waves_per_replication": SPLIT},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": TRAFFIC_BYTES,
-                     "kernel": "mm1_split_kernel<2>", "avg_kernel_ms": avg_kernel_ms,
+                     "kernel": "mm1_split_kernel<%d>" % SPLIT, "avg_kernel_ms": avg_kernel_ms,
                      "slots_per_customer": slots},
         "ci": {"mean_wq": ci["mean"], "half_width_95": ci["half_width"],
                "gpu_seconds_per_step": ms_step * 1e-3,

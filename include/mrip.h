@@ -171,14 +171,16 @@ MRIP_API void mrip_destroy(mrip_ctx ctx);
  * size (64, 256 or 1024). Outputs do not depend on it. Defaults 1 and 256. */
 MRIP_API mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t reps_per_wave, uint32_t workgroup);
 
-/* Wavefronts per replication for mrip_run on an M/M/1 WAVE context: 1, 2
- * or 4 (default 1; needs reps_per_wave = 1). With 2 or 4, the wavefronts of
- * a 256-thread workgroup each take an equal run of the replication's
- * customers, start from an empty system, and then in order re-run their
- * leading chunks from the carry the previous part left until the two
- * trajectories meet (Lindley's recursion forgets its start once the queue
- * empties). Per-customer values are those of the unsplit run; the means
- * differ only by fp32 summation order. */
+/* Wavefronts per replication for mrip_run on an M/M/1 WAVE context: 1, 2,
+ * 4 or 8 (default 1; needs reps_per_wave = 1). With more than one, the
+ * wavefronts of a workgroup (256 threads, or 512 for 8) each take an equal
+ * run of the replication's customers from an empty system; then every part
+ * at once re-runs its leading chunks from the carry its predecessor ended
+ * with until the two trajectories meet (Lindley's recursion forgets its
+ * start once the queue empties), and, in order, a part whose predecessor
+ * never met corrects again from that part's true end. Per-customer values
+ * are those of the unsplit run; the means differ only by fp32 summation
+ * order. */
 MRIP_API mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep);
 
 /* Stream source of mrip_run (see mrip_rng). TAUS88 is defined for the
@@ -207,6 +209,15 @@ MRIP_API mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence
 MRIP_API mrip_status mrip_outputs(mrip_ctx ctx, uint32_t output, void *dst, uint64_t bytes,
                          int dst_is_device);
 
+/* Bind a caller-owned device buffer (for example a torch tensor) as output
+ * `output` (a scalar output, or 3 = the M/M/1 features): later runs and
+ * plan runs write there instead of into a buffer of the context, and the
+ * statistics reduce it. It must hold at least the run's output (n values,
+ * 4 bytes each, 40 per replication for features; MRIP_E_INVAL at the run
+ * otherwise), be 4-byte aligned, and stay alive until the run's results
+ * have been read. ptr_dev NULL unbinds (back to the context's buffer). */
+MRIP_API mrip_status mrip_bind_output(mrip_ctx ctx, uint32_t output, void *ptr_dev, uint64_t bytes);
+
 /* Device pointer to output `output` of the last run (valid until the next
  * run or mrip_destroy); for zero-copy readers on the same stream. */
 MRIP_API mrip_status mrip_output_ptr(mrip_ctx ctx, uint32_t output, const void **ptr_dev);
@@ -233,6 +244,18 @@ MRIP_API mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, ui
  * pop work from a device queue, then reduce per design point. Outputs are
  * indexed like the uploaded items. Asynchronous. */
 MRIP_API mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream);
+
+/* Resume a plan (section 1: an experimental plan is a set of replication
+ * runs; a long one may be stopped and restarted): run every uploaded item
+ * i with skip_done[i] == 0, longest first as mrip_run_plan does, and leave
+ * the outputs of the others as the output buffers hold them (from an
+ * earlier plan run on this context, or results the caller restored into a
+ * bound output); then reduce every design point over all items.
+ * skip_done: host array of n_items bytes, NULL = run everything.
+ * Synchronises the stream before reusing its queue buffer; then
+ * asynchronous. */
+MRIP_API mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *skip_done,
+                                          void *hip_stream);
 
 /* Stats of output 0 (mean W) over the items of design point `dp` in the
  * last plan run. Synchronises. */

@@ -64,31 +64,57 @@ uint32_t ff_threshold(double prob) {
   return (uint32_t)v;
 }
 
+// The run's statistics land in pinned host memory that the reduction
+// kernel writes directly (no copy launch); mrip_stats waits for ev_stats.
 mrip_status ensure_events(mrip_ctx c) {
-  if (!c->ev0) HIP_TRY(c, hipEventCreate(&c->ev0));
-  if (!c->ev1) HIP_TRY(c, hipEventCreate(&c->ev1));
   if (!c->ev_stats) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_stats, hipEventDisableTiming));
-  if (!c->stats_host) HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, sizeof(double) * 3 * 4,
-                                               hipHostMallocDefault));
+  if (!c->stats_host) {
+    HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, sizeof(double) * 3 * 4,
+                             hipHostMallocMapped));
+    HIP_TRY(c, hipHostGetDevicePointer((void **)&c->stats_view, c->stats_host, 0));
+  }
   return MRIP_OK;
 }
 
-// Events bracketing one simulation-kernel launch: the context's last-run
-// pair and the next slot of the run-history ring.
+// Events bracketing one simulation-kernel launch: the next slot of the
+// run-history ring (the last run's pair is the slot before `launches`).
 mrip_status record_begin(mrip_ctx c, hipStream_t s) {
   const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
   if (!c->ring0[slot]) HIP_TRY(c, hipEventCreate(&c->ring0[slot]));
   if (!c->ring1[slot]) HIP_TRY(c, hipEventCreate(&c->ring1[slot]));
-  HIP_TRY(c, hipEventRecord(c->ev0, s));
   HIP_TRY(c, hipEventRecord(c->ring0[slot], s));
   return MRIP_OK;
 }
 
 mrip_status record_end(mrip_ctx c, hipStream_t s) {
   const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
-  HIP_TRY(c, hipEventRecord(c->ev1, s));
   HIP_TRY(c, hipEventRecord(c->ring1[slot], s));
   ++c->launches;
+  return MRIP_OK;
+}
+
+// Kernel milliseconds of the context's last simulation launch.
+mrip_status last_launch_ms(mrip_ctx c, float *ms) {
+  const uint32_t slot = (uint32_t)((c->launches - 1) % mrip_ctx_s::RING);
+  HIP_TRY(c, hipEventSynchronize(c->ring1[slot]));
+  HIP_TRY(c, hipEventElapsedTime(ms, c->ring0[slot], c->ring1[slot]));
+  return MRIP_OK;
+}
+
+// Device buffer for output o of a run over n items: the caller's bound
+// buffer when there is one (it must hold `need` bytes), else the context's.
+mrip_status output_buffer(mrip_ctx c, uint32_t o, uint64_t need, void **p) {
+  if (c->bound[o].p) {
+    if (c->bound[o].bytes < need) {
+      c->err = "bound output " + std::to_string(o) + " is smaller than the run's output";
+      return MRIP_E_INVAL;
+    }
+    *p = c->bound[o].p;
+  } else {
+    HIP_TRY(c, c->out[o].ensure(need));
+    *p = c->out[o].p;
+  }
+  c->cur[o] = *p;
   return MRIP_OK;
 }
 
@@ -229,8 +255,8 @@ mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t rpw, uint32_t wg) {
 
 mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep) {
   if (!ctx) return MRIP_E_INVAL;
-  if (waves_per_rep != 1 && waves_per_rep != 2 && waves_per_rep != 4)
-    return inval(ctx, "waves_per_rep must be 1, 2 or 4");
+  if (waves_per_rep != 1 && waves_per_rep != 2 && waves_per_rep != 4 && waves_per_rep != 8)
+    return inval(ctx, "waves_per_rep must be 1, 2, 4 or 8");
   if (waves_per_rep > 1 && (ctx->model != MRIP_MM1 || ctx->mapping != MRIP_MAP_WAVE))
     return inval(ctx, "splitting a replication is defined for the M/M/1 WAVE engine");
   if (waves_per_rep > 1 && ctx->rpw != 1) return inval(ctx, "splitting needs reps_per_wave = 1");
@@ -283,8 +309,11 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
   const uint32_t nout = scalar_outputs(ctx->model);
-  for (uint32_t o = 0; o < nout; ++o) HIP_TRY(ctx, ctx->out[o].ensure(n_reps * 4));
-  HIP_TRY(ctx, ctx->stats.ensure(sizeof(double) * 3 * 4));
+  void *outp[4] = {};
+  for (uint32_t o = 0; o < nout; ++o) {
+    st = output_buffer(ctx, o, n_reps * 4, &outp[o]);
+    if (st != MRIP_OK) return st;
+  }
   const bool wave = ctx->mapping == MRIP_MAP_WAVE;
 
   st = record_begin(ctx, s);
@@ -296,8 +325,8 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.grid = ctx->rw.grid;
     a.steps = ctx->rw.steps;
     a.n_reps = n_reps;
-    a.ssd = ctx->out[0].as<int32_t>();
-    a.distinct = ctx->out[1].as<int32_t>();
+    a.ssd = (int32_t *)outp[0];
+    a.distinct = (int32_t *)outp[1];
     a.rng = ctx->rng;
     a.taus = ctx->taus_tables.as<uint32_t>();
     if (wave) {
@@ -315,14 +344,15 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.mu = ctx->mm1.mu;
     a.customers = ctx->mm1.customers;
     a.feature_prefix = ctx->mm1.feature_prefix;
-    a.mean_w = ctx->out[0].as<float>();
-    a.mean_t = ctx->out[1].as<float>();
-    a.mean_i = ctx->out[2].as<float>();
+    a.mean_w = (float *)outp[0];
+    a.mean_t = (float *)outp[1];
+    a.mean_i = (float *)outp[2];
     a.rng = ctx->rng;
     a.taus = ctx->taus_tables.as<uint32_t>();
     if (a.feature_prefix > 0) {
-      HIP_TRY(ctx, ctx->out[3].ensure(n_reps * 40));
-      a.features = ctx->out[3].as<float>();
+      st = output_buffer(ctx, 3, n_reps * 40, &outp[3]);
+      if (st != MRIP_OK) return st;
+      a.features = (float *)outp[3];
     }
     if (wave && ctx->split > 1) HIP_TRY(ctx, launch_mm1_split(a, ctx->split, s));
     else if (wave) HIP_TRY(ctx, launch_mm1_wave(a, ctx->rpw, ctx->wg, s));
@@ -332,8 +362,8 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.seed = seed;
     a.points = ctx->pi.points;
     a.n_reps = n_reps;
-    a.hits = ctx->out[0].as<int32_t>();
-    a.estimate = ctx->out[1].as<float>();
+    a.hits = (int32_t *)outp[0];
+    a.estimate = (float *)outp[1];
     a.rng = ctx->rng;
     a.taus = ctx->taus_tables.as<uint32_t>();
     if (wave) HIP_TRY(ctx, launch_pi_wave(a, ctx->wg, s));
@@ -346,7 +376,7 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.tp = ff_threshold(ctx->ff.p_grow);
     a.tf = ff_threshold(ctx->ff.f_light);
     a.n_reps = n_reps;
-    a.burnt = ctx->out[0].as<int32_t>();
+    a.burnt = (int32_t *)outp[0];
     if (wave) {
       HIP_TRY(ctx, launch_ff_wave(a, ctx->wg, s));
     } else {
@@ -357,16 +387,14 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   }
   st = record_end(ctx, s);
   if (st != MRIP_OK) return st;
-  // all scalar outputs in one reduction launch; the triples go to pinned
-  // host memory on the same stream so mrip_stats only waits for an event
+  // all scalar outputs in one reduction launch, written straight into
+  // pinned host memory, so mrip_stats only waits for an event
   ReduceSet set{};
   for (uint32_t o = 0; o < nout; ++o) {
-    set.x[o] = ctx->out[o].p;
+    set.x[o] = outp[o];
     set.dtype[o] = output_dtype(ctx->model, o);
   }
-  HIP_TRY(ctx, launch_reduce_f64_multi(set, nout, n_reps, ctx->stats.as<double>(), s));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->stats_host, ctx->stats.p, sizeof(double) * 3 * nout,
-                              hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, launch_reduce_f64_multi(set, nout, n_reps, ctx->stats_view, s));
   HIP_TRY(ctx, hipEventRecord(ctx->ev_stats, s));
   ctx->last = RUN_UNIFORM;
   ctx->last_n = n_reps;
@@ -392,7 +420,7 @@ mrip_status mrip_output_ptr(mrip_ctx ctx, uint32_t output, const void **ptr) {
   if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
   const bool feat = ctx->model == MRIP_MM1 && output == 3 && ctx->mm1.feature_prefix > 0;
   if (output >= scalar_outputs(ctx->model) && !feat) return inval(ctx, "no such output");
-  *ptr = ctx->out[output].p;
+  *ptr = ctx->cur[output];
   return MRIP_OK;
 }
 
@@ -405,7 +433,7 @@ mrip_status mrip_outputs(mrip_ctx ctx, uint32_t output, void *dst, uint64_t byte
   const uint64_t need = ctx->last_n * (feat ? 40 : 4);
   if (bytes < need) return inval(ctx, "destination too small");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
-  HIP_TRY(ctx, hipMemcpy(dst, ctx->out[output].p, need,
+  HIP_TRY(ctx, hipMemcpy(dst, ctx->cur[output], need,
                          dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
   return MRIP_OK;
 }
@@ -427,9 +455,7 @@ mrip_status mrip_run_history_ms(mrip_ctx ctx, float *ms, uint32_t max_n, uint32_
 mrip_status mrip_last_run_ms(mrip_ctx ctx, float *ms) {
   if (!ctx || !ms) return MRIP_E_INVAL;
   if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
-  HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
-  HIP_TRY(ctx, hipEventElapsedTime(ms, ctx->ev0, ctx->ev1));
-  return MRIP_OK;
+  return last_launch_ms(ctx, ms);
 }
 
 // ------------------------------------------------------------------ plan
@@ -493,6 +519,7 @@ mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n)
   ctx->dp_ids = ids;
   ctx->lpt_customers.resize(n);
   for (uint64_t j = 0; j < n; ++j) ctx->lpt_customers[j] = cust[order[j]];
+  ctx->lpt_order = order;
   return MRIP_OK;
 }
 
@@ -508,14 +535,18 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
                                  uint32_t split, bool reduce) {
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
-  for (uint32_t o = 0; o < 3; ++o) HIP_TRY(ctx, ctx->out[o].ensure(ctx->n_items * 4));
-  HIP_TRY(ctx, ctx->stats.ensure(sizeof(double) * 3 * 4));
+  void *outp[4] = {};
+  for (uint32_t o = 0; o < 3; ++o) {
+    st = output_buffer(ctx, o, ctx->n_items * 4, &outp[o]);
+    if (st != MRIP_OK) return st;
+  }
   Mm1Args a{};
   a.seed = seed;
   a.feature_prefix = ctx->mm1.feature_prefix;
   if (a.feature_prefix > 0) {
-    HIP_TRY(ctx, ctx->out[3].ensure(ctx->n_items * 40));
-    a.features = ctx->out[3].as<float>();
+    st = output_buffer(ctx, 3, ctx->n_items * 40, &outp[3]);
+    if (st != MRIP_OK) return st;
+    a.features = (float *)outp[3];
   }
   a.items.dp = ctx->it_dp.as<uint32_t>();
   a.items.rep = ctx->it_rep.as<uint32_t>();
@@ -524,28 +555,31 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
   a.items.mu = ctx->it_mu.as<float>();
   a.items.order = order;
   a.queue_head = ctx->queue.as<uint32_t>();
-  a.mean_w = ctx->out[0].as<float>();
-  a.mean_t = ctx->out[1].as<float>();
-  a.mean_i = ctx->out[2].as<float>();
+  a.mean_w = (float *)outp[0];
+  a.mean_t = (float *)outp[1];
+  a.mean_i = (float *)outp[2];
   HIP_TRY(ctx, launch_zero_u32(a.queue_head, 2, s));
   st = record_begin(ctx, s);
   if (st != MRIP_OK) return st;
-  if (split > 1 && n_long > 0) HIP_TRY(ctx, launch_mm1_plan_split(a, n, n_long, split, rpw, s));
-  else HIP_TRY(ctx, launch_mm1_plan(a, n, rpw, wg, s));
+  if (n == 0) {
+    // nothing left to simulate (a resumed plan): only the reductions run
+  } else if (split > 1 && n_long > 0) {
+    HIP_TRY(ctx, launch_mm1_plan_split(a, n, n_long, split, rpw, s));
+  } else {
+    HIP_TRY(ctx, launch_mm1_plan(a, n, rpw, wg, s));
+  }
   st = record_end(ctx, s);
   if (st != MRIP_OK) return st;
   if (reduce) {
-    HIP_TRY(ctx, launch_reduce_f64_gather(ctx->out[0].p, 1, ctx->dp_index.as<uint32_t>(),
+    HIP_TRY(ctx, launch_reduce_f64_gather(outp[0], 1, ctx->dp_index.as<uint32_t>(),
                                           ctx->dp_offsets.as<uint64_t>(), (uint32_t)ctx->dp_ids.size(),
                                           ctx->dp_stats.as<double>(), s));
     ReduceSet set{};
     for (uint32_t o = 0; o < 3; ++o) {
-      set.x[o] = ctx->out[o].p;
+      set.x[o] = outp[o];
       set.dtype[o] = 1;
     }
-    HIP_TRY(ctx, launch_reduce_f64_multi(set, 3, ctx->n_items, ctx->stats.as<double>(), s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->stats_host, ctx->stats.p, sizeof(double) * 9,
-                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, launch_reduce_f64_multi(set, 3, ctx->n_items, ctx->stats_view, s));
     HIP_TRY(ctx, hipEventRecord(ctx->ev_stats, s));
   }
   ctx->last_stream = s;
@@ -564,6 +598,53 @@ mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
   if (st != MRIP_OK) return st;
   ctx->last = RUN_PLAN;
   ctx->last_n = ctx->n_items;
+  return MRIP_OK;
+}
+
+mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *skip_done,
+                                 void *hip_stream) {
+  if (!ctx) return MRIP_E_INVAL;
+  if (philox_only(ctx) != MRIP_OK) return MRIP_E_UNSUPPORTED;
+  if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
+  if (ctx->mapping != MRIP_MAP_WAVE)
+    return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
+  if (!skip_done) return mrip_run_plan(ctx, seed, hip_stream);
+  hipStream_t s = (hipStream_t)hip_stream;
+  // the remaining items, still longest first
+  std::vector<uint32_t> todo;
+  std::vector<uint64_t> todo_n;
+  todo.reserve(ctx->n_items);
+  for (uint64_t j = 0; j < ctx->n_items; ++j) {
+    const uint32_t i = ctx->lpt_order[j];
+    if (!skip_done[i]) {
+      todo.push_back(i);
+      todo_n.push_back(ctx->lpt_customers[j]);
+    }
+  }
+  // a previous resume may still read the queue buffer
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  if (!todo.empty()) {
+    HIP_TRY(ctx, ctx->resume_order.ensure(4 * todo.size()));
+    HIP_TRY(ctx, hipMemcpy(ctx->resume_order.p, todo.data(), 4 * todo.size(),
+                           hipMemcpyHostToDevice));
+  }
+  const uint64_t n_long = count_long(todo_n, todo.size(), ctx->long_min);
+  mrip_status st = run_plan_impl(ctx, seed, s, ctx->resume_order.as<uint32_t>(), todo.size(),
+                                 n_long, ctx->rpw, ctx->wg, ctx->plan_split, true);
+  if (st != MRIP_OK) return st;
+  ctx->last = RUN_PLAN;
+  ctx->last_n = ctx->n_items;
+  return MRIP_OK;
+}
+
+mrip_status mrip_bind_output(mrip_ctx ctx, uint32_t output, void *ptr_dev, uint64_t bytes) {
+  if (!ctx) return MRIP_E_INVAL;
+  const bool feat = ctx->model == MRIP_MM1 && output == 3;
+  if (output >= scalar_outputs(ctx->model) && !feat) return inval(ctx, "no such output");
+  if (ptr_dev && (bytes == 0 || ((uintptr_t)ptr_dev & 3u)))
+    return inval(ctx, "a bound output needs a non-empty, 4-byte aligned buffer");
+  ctx->bound[output].p = ptr_dev;
+  ctx->bound[output].bytes = ptr_dev ? bytes : 0;
   return MRIP_OK;
 }
 
@@ -627,9 +708,9 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
     for (int rep = 0; rep < 3; ++rep) {  // the first launch warms up
       mrip_status st = run_plan_impl(ctx, seed, s, order, n, n_long, sh.rpw, sh.wg, sh.split, false);
       if (st != MRIP_OK) return st;
-      HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
       float ms = 0.f;
-      HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      st = last_launch_ms(ctx, &ms);
+      if (st != MRIP_OK) return st;
       if (rep > 0) t_min = std::min(t_min, ms);
     }
     if (t_min < best) {

@@ -94,14 +94,21 @@ struct mrip_ctx_s {
   mrip::DevBuf taus_tables;
 
   mrip::DevBuf out[4];
+  // caller-owned output buffers (mrip_bind_output) and the buffers the last
+  // run wrote (bound or owned)
+  struct Bound {
+    void *p = nullptr;
+    uint64_t bytes = 0;
+  } bound[4];
+  void *cur[4] = {};
   mrip::DevBuf scratch;
-  mrip::DevBuf stats;  // 3 doubles per scalar output
-  double *stats_host = nullptr;     // pinned copy of `stats`, filled on the run's stream
-  hipEvent_t ev_stats = nullptr;    // recorded after that copy
+  // (n, mean, var) per scalar output: pinned host memory written by the
+  // reduction kernel through its device view
+  double *stats_host = nullptr, *stats_view = nullptr;
+  hipEvent_t ev_stats = nullptr;    // recorded after that reduction
   mrip::RunKind last = mrip::RUN_NONE;
   uint64_t last_n = 0;
   hipStream_t last_stream = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the last simulation kernel
   // event pairs of the last RING simulation-kernel launches (run history)
   static constexpr uint32_t RING = 256;
   hipEvent_t ring0[RING] = {}, ring1[RING] = {};
@@ -111,6 +118,8 @@ struct mrip_ctx_s {
   // plan
   uint64_t n_items = 0, n_long = 0;
   std::vector<uint64_t> lpt_customers;  // customers in longest-first order
+  std::vector<uint32_t> lpt_order;      // item indices in longest-first order
+  mrip::DevBuf resume_order;            // the queue of a resumed plan
   mrip::DevBuf it_dp, it_rep, it_n, it_lambda, it_mu, it_order, queue, dp_index, dp_offsets,
       dp_stats;
   std::vector<uint32_t> dp_ids;
@@ -121,8 +130,6 @@ struct mrip_ctx_s {
   ~mrip_ctx_s() {
     if (stats_host) (void)hipHostFree(stats_host);
     if (ev_stats) (void)hipEventDestroy(ev_stats);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
     for (uint32_t i = 0; i < RING; ++i) {
       if (ring0[i]) (void)hipEventDestroy(ring0[i]);
       if (ring1[i]) (void)hipEventDestroy(ring1[i]);

@@ -11,6 +11,12 @@ namespace mrip {
 // Random Spacing (taus.hpp); `taus` points to the device jump tables.
 enum Rng : int { RNG_PHILOX = 0, RNG_TAUS88 = 1 };
 
+// Outputs to reduce: x[o] holds n values of dtype[o] (0 = int32, 1 = fp32).
+struct ReduceSet {
+  const void *x[4];
+  int dtype[4];
+};
+
 // ------------------------------------------------------------ random walk
 struct RwArgs {
   uint64_t seed;
@@ -95,11 +101,7 @@ hipError_t launch_pi_simt(const PiArgs &a, bool one_lane, hipStream_t s);
 hipError_t launch_reduce_f64(const void *x, int dtype, uint64_t n, const uint64_t *offsets,
                              uint32_t n_segments, double *out, hipStream_t s);
 // Several outputs of n values each in one launch (one workgroup each):
-// out[3*o + {0,1,2}] for output o.
-struct ReduceSet {
-  const void *x[4];
-  int dtype[4];
-};
+// out[3*o + {0,1,2}] for output o (ReduceSet is declared above).
 hipError_t launch_reduce_f64_multi(const ReduceSet &set, uint32_t n_outputs, uint64_t n,
                                    double *out, hipStream_t s);
 // Gathered variant: segment g reads x[index[offsets[g] .. offsets[g+1])].

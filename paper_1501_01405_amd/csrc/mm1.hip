@@ -420,14 +420,36 @@ __global__ void mm1_plan_kernel(Mm1Args a, uint64_t n_items) {
 // takes it for the smaller one too), so the rest of the speculative pass is
 // already exact. Per-customer values equal the unsplit engine's; only the
 // summation order of the means differs. Part 0 keeps the feature chunks.
+// Workgroup of the split kernels: 256 threads (4 / X replications) for
+// X <= 4 wavefronts per replication, one replication of X wavefronts above.
+template <int X>
+constexpr int split_wg() {
+  return X <= 4 ? 256 : 64 * X;
+}
+template <int X>
+constexpr int split_slots() {
+  return split_wg<X>() / (64 * X);
+}
+
 template <int X>
 struct SplitShared {
-  float spec[4 / X][X], truth[4 / X][X];
-  float sum[4 / X][X][3];
+  float spec[split_slots<X>()][X], fin[split_slots<X>()][X];
+  float sum[split_slots<X>()][X][3];
 };
 
 // Part h of replication d (slot `slot` of the workgroup); every thread of
-// the 256-thread workgroup must call it (it holds X + 1 barriers).
+// the workgroup must call it (it holds X + 2 barriers, whatever the data).
+//
+// Phase 1: every part runs its chunks from carry 0 (exact for part 0).
+// Phase 2: every part h >= 1 at once takes the carry part h-1 ended with in
+// phase 1 as its true start and re-runs its leading chunks from both starts,
+// adding the difference of the sums, until the two trajectories are
+// bit-identical (Lindley's recursion forgets its start once the queue
+// empties; carries are ordered, so once they meet they stay equal). The
+// assumption holds whenever part h-1 met its own trajectory.
+// Phase 3: in order, a part whose assumed start differs from its
+// predecessor's true end (the predecessor never coupled) corrects again
+// from that end.
 template <int X>
 __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, uint32_t k1,
                                   uint64_t K, const Mm1Args &a, SplitShared<X> &sh) {
@@ -458,23 +480,40 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
   if (lane == 0) sh.spec[slot][h] = carry;
   __syncthreads();
 
-  // phase 2: parts 1..X-1 in order correct their leading chunks
+  // the part's correction from true start `cin`; returns its true end
+  Sums fix;
+  auto correct = [&](float cin) -> float {
+    fix = Sums();
+    float ct = cin, cs = 0.0f;
+    bool coupled = false;
+    for (uint32_t cc = cb; cc < ce && !coupled; ++cc) {
+      const Draw<P> dr = draw_chunk<1, P>((uint64_t)cc * CHUNK, d, k0, k1);
+      if (cc < full) fixup_chunk<P, false>((uint64_t)cc * CHUNK, dr, d, ct, cs, fix);
+      else fixup_chunk<P, true>((uint64_t)cc * CHUNK, dr, d, ct, cs, fix);
+      coupled = __builtin_amdgcn_readfirstlane((int)(__float_as_uint(ct) == __float_as_uint(cs))) != 0;
+    }
+    return coupled ? carry : ct;
+  };
+
+  // phase 2: all parts at once, each from its predecessor's phase-1 end
+  float fin = carry;
+  if (split && h >= 1) fin = correct(sh.spec[slot][h - 1]);
+  if (lane == 0) sh.fin[slot][h] = fin;
+  __syncthreads();
+
+  // phase 3: in order, only where the assumed start was not the true one
 #pragma unroll
   for (int j = 1; j < X; ++j) {
-    if (h == j && cb < ce) {
-      float ct = j == 1 ? sh.spec[slot][0] : sh.truth[slot][j - 1];
-      float cspec = 0.0f;
-      bool coupled = false;
-      for (c = cb; c < ce && !coupled; ++c) {
-        const Draw<P> dr = draw_chunk<1, P>((uint64_t)c * CHUNK, d, k0, k1);
-        if (c < full) fixup_chunk<P, false>((uint64_t)c * CHUNK, dr, d, ct, cspec, acc);
-        else fixup_chunk<P, true>((uint64_t)c * CHUNK, dr, d, ct, cspec, acc);
-        coupled = __builtin_amdgcn_readfirstlane((int)(__float_as_uint(ct) == __float_as_uint(cspec))) != 0;
-      }
-      if (lane == 0) sh.truth[slot][j] = coupled ? sh.spec[slot][j] : ct;
+    if (split && h == j &&
+        __float_as_uint(sh.fin[slot][j - 1]) != __float_as_uint(sh.spec[slot][j - 1])) {
+      const float f = correct(sh.fin[slot][j - 1]);
+      if (lane == 0) sh.fin[slot][j] = f;
     }
     __syncthreads();
   }
+  acc.w.add(fix.w.value());
+  acc.t.add(fix.t.value());
+  acc.i.add(fix.i.value());
 
   // phase 3: part sums, then the replication's means in part order
   const float sw = group_sum_compensated(acc.w.value(), 64);
@@ -526,8 +565,8 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
 }
 
 template <int X>
-__global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, float cs) {
-  constexpr int SLOTS = 4 / X;  // replications per 256-thread workgroup
+__global__ __launch_bounds__(split_wg<X>()) void mm1_split_kernel(Mm1Args a, float ca, float cs) {
+  constexpr int SLOTS = split_slots<X>();  // replications per workgroup
   __shared__ SplitShared<X> sh;
   const int wave = threadIdx.x >> 6;
   const int slot = wave / X, h = wave % X;
@@ -545,7 +584,8 @@ __global__ __launch_bounds__(256) void mm1_split_kernel(Mm1Args a, float ca, flo
 template <int X, int RPW>
 __global__ __launch_bounds__(256) void mm1_plan_split_kernel(Mm1Args a, uint64_t n_items,
                                                              uint64_t n_long) {
-  constexpr int SLOTS = 4 / X;
+  constexpr int SLOTS = split_slots<X>();
+  static_assert(split_wg<X>() == 256, "plans split over 2 or 4 wavefronts");
   constexpr int S = 4 / RPW;
   __shared__ SplitShared<X> sh;
   __shared__ uint32_t sh_pop;
@@ -675,14 +715,20 @@ hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t rpw, uint32_t wg, hipStrea
   return hipGetLastError();
 }
 
+template <int X>
+hipError_t split_launch(const Mm1Args &a, float ca, float cs, hipStream_t s) {
+  const uint64_t blocks = (a.n_reps + split_slots<X>() - 1) / split_slots<X>();
+  hipLaunchKernelGGL(mm1_split_kernel<X>, dim3((uint32_t)blocks), dim3(split_wg<X>()), 0, s, a,
+                     ca, cs);
+  return hipGetLastError();
+}
+
 hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s) {
   const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
-  const uint32_t slots = 4 / waves_per_rep;
-  const uint64_t blocks = (a.n_reps + slots - 1) / slots;
-  if (waves_per_rep == 2) hipLaunchKernelGGL(mm1_split_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, s, a, ca, cs);
-  else if (waves_per_rep == 4) hipLaunchKernelGGL(mm1_split_kernel<4>, dim3((uint32_t)blocks), dim3(256), 0, s, a, ca, cs);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (waves_per_rep == 2) return split_launch<2>(a, ca, cs, s);
+  if (waves_per_rep == 4) return split_launch<4>(a, ca, cs, s);
+  if (waves_per_rep == 8) return split_launch<8>(a, ca, cs, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s) {

@@ -84,6 +84,8 @@ _SIGS = {
     "mrip_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t)]),
     "mrip_outputs": (st, [ctx_t, u32, vp, u64, C.c_int]),
     "mrip_output_ptr": (st, [ctx_t, u32, C.POINTER(vp)]),
+    "mrip_bind_output": (st, [ctx_t, u32, vp, u64]),
+    "mrip_run_plan_resume": (st, [ctx_t, u64, vp, vp]),
     "mrip_last_run_ms": (st, [ctx_t, C.POINTER(f32)]),
     "mrip_run_history_ms": (st, [ctx_t, C.POINTER(f32), u32, C.POINTER(u32)]),
     "mrip_plan_set": (st, [ctx_t, vp, u64]),
@@ -241,6 +243,22 @@ def mrip_plan_set(ctx, items):
 
 def mrip_run_plan(ctx, seed, stream=None):
     check(load().mrip_run_plan(ctx, seed, stream), ctx)
+
+
+def mrip_bind_output(ctx, output, tensor):
+    """Bind a torch device tensor as output `output` (None unbinds)."""
+    if tensor is None:
+        check(load().mrip_bind_output(ctx, output, None, 0), ctx)
+    else:
+        nbytes = tensor.numel() * tensor.element_size()
+        check(load().mrip_bind_output(ctx, output, tensor.data_ptr(), nbytes), ctx)
+
+
+def mrip_run_plan_resume(ctx, seed, skip_done, stream=None):
+    skip = None
+    if skip_done is not None:
+        skip = np.ascontiguousarray(skip_done, dtype=np.uint8)
+    check(load().mrip_run_plan_resume(ctx, seed, _ptr(skip), stream), ctx)
 
 
 def mrip_plan_stats(ctx, dp, confidence=0.95):
@@ -432,6 +450,15 @@ class Context:
 
     def run_plan(self, seed=42, stream=None):
         mrip_run_plan(self.ctx, seed, current_stream() if stream is None else stream)
+
+    def bind_output(self, output, tensor):
+        mrip_bind_output(self.ctx, output, tensor)
+        self._bound = getattr(self, "_bound", {})
+        self._bound[output] = tensor  # keep the buffer alive while bound
+
+    def run_plan_resume(self, skip_done, seed=42, stream=None):
+        mrip_run_plan_resume(self.ctx, seed, skip_done,
+                             current_stream() if stream is None else stream)
 
     def plan_stats(self, dp, confidence=0.95):
         return mrip_plan_stats(self.ctx, dp, confidence)

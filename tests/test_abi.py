@@ -99,6 +99,8 @@ def test_calls_out_of_order_and_bad_shapes():
     assert L.mrip_set_split(ctx, 2) == mrip.MRIP_E_INVAL  # needs reps_per_wave = 1
     assert L.mrip_set_shape(ctx, 1, 256) == mrip.MRIP_OK
     assert L.mrip_set_split(ctx, 3) == mrip.MRIP_E_INVAL
+    assert L.mrip_set_split(ctx, 8) == mrip.MRIP_OK
+    assert L.mrip_set_split(ctx, 16) == mrip.MRIP_E_INVAL
     assert L.mrip_set_split(ctx, 4) == mrip.MRIP_OK
     assert L.mrip_set_shape(ctx, 2, 256) == mrip.MRIP_E_INVAL
     assert L.mrip_run_plan(ctx, 42, None) == mrip.MRIP_E_STATE
@@ -124,3 +126,19 @@ def test_generator_choice_checks():
     L.mrip_destroy(ctx)
     assert L.mrip_taus88(1, 4, 0, 0, 0, 0, None, None) == mrip.MRIP_OK  # n = 0: nothing to do
     assert L.mrip_taus88(1, 4, 0, 0, 0, 5, None, None) == mrip.MRIP_E_INVAL
+
+
+def test_bind_output_and_resume_checks():
+    L = mrip.load()
+    ctx = mrip.ctx_t()
+    assert L.mrip_create(C.byref(ctx), mrip.MRIP_RW, C.byref(mrip.rw_params()), 0) == 0
+    assert L.mrip_bind_output(ctx, 2, None, 0) == mrip.MRIP_E_INVAL  # the walk has 2 outputs
+    assert L.mrip_bind_output(ctx, 0, 0x1002, 64) == mrip.MRIP_E_INVAL  # misaligned
+    assert L.mrip_bind_output(ctx, 0, 0x1000, 0) == mrip.MRIP_E_INVAL  # empty
+    assert L.mrip_bind_output(ctx, 1, None, 0) == mrip.MRIP_OK  # unbind
+    L.mrip_destroy(ctx)
+    ctx = mrip.ctx_t()
+    assert L.mrip_create(C.byref(ctx), mrip.MRIP_MM1, C.byref(mrip.mm1_params()), 0) == 0
+    assert L.mrip_bind_output(ctx, 3, None, 0) == mrip.MRIP_OK  # features are output 3
+    assert L.mrip_run_plan_resume(ctx, 42, None, None) == mrip.MRIP_E_STATE  # no plan
+    L.mrip_destroy(ctx)

@@ -1,0 +1,101 @@
+"""GPU tests of the boundary's caller-owned outputs and plan resume: a bound
+torch buffer receives exactly the outputs (and statistics) of an unbound
+run, and a plan resumed from saved outputs of its finished items gives the
+outputs and per-design-point statistics of an uninterrupted run."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import SIMT, WAVE, announce
+from paper_1501_01405_amd import inputs, mrip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("split", [1, 2])
+def test_bound_outputs_receive_the_run(gpu, split):
+    announce("bind output mm1", split)
+    N, R = 20000, 300
+    ref = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, N, 100), WAVE)
+    ref.set_split(split)
+    ref.run(R, seed=4)
+    want = [ref.output(o).cpu().numpy() for o in range(4)]
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, N, 100), WAVE)
+    ctx.set_split(split)
+    bufs = [torch.full((R + 5,), -1.0, device="cuda") for _ in range(3)]
+    feat = torch.zeros((R, 10), device="cuda")
+    for o in range(3):
+        ctx.bind_output(o, bufs[o])
+    ctx.bind_output(3, feat)
+    ctx.run(R, seed=4)
+    for o in range(3):
+        got = bufs[o].cpu().numpy()
+        assert np.array_equal(got[:R], want[o])
+        assert np.all(got[R:] == -1.0)  # nothing written past the run
+        assert ctx.stats(o) == ref.stats(o)
+    assert np.array_equal(feat.cpu().numpy(), want[3])
+    small = torch.zeros(R - 1, device="cuda")
+    ctx.bind_output(0, small)
+    with pytest.raises(mrip.MripError):
+        ctx.run(R, seed=4)
+    ctx.bind_output(0, None)  # back to the context's own buffer
+    ctx.run(R, seed=4)
+    assert np.array_equal(ctx.output(0).cpu().numpy(), want[0])
+
+
+def test_bound_outputs_other_models(gpu):
+    announce("bind output rw / pi")
+    for model, params, mapping in ((mrip.MRIP_RW, mrip.rw_params(64, 64, 200), SIMT),
+                                   (mrip.MRIP_PI, mrip.pi_params(5000), WAVE)):
+        ref = mrip.Context(model, params, mapping)
+        ref.run(70, seed=2)
+        ctx = mrip.Context(model, params, mapping)
+        b = torch.zeros(70, dtype=torch.int32, device="cuda")
+        ctx.bind_output(0, b)
+        ctx.run(70, seed=2)
+        assert np.array_equal(b.cpu().numpy(), ref.output(0).cpu().numpy())
+        assert ctx.stats(0) == ref.stats(0)
+
+
+def _plan():
+    items = inputs.plan_table()
+    keep = np.concatenate([np.arange(0, 2048, 7), [0, 1, 2]])  # a smaller plan, longest kept
+    order = np.argsort(-items["customers"], kind="stable")[:8]
+    sel = np.unique(np.concatenate([keep, order]))
+    return items[sel]
+
+
+def test_resumed_plan_equals_uninterrupted_plan(gpu):
+    announce("plan resume")
+    items = _plan()
+    n = len(items)
+    full = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), WAVE)
+    full.plan_set(items)
+    full.run_plan(seed=9)
+    want = [full.output(o).cpu().numpy() for o in range(3)]
+    dps = sorted(set(items["dp"].tolist()))
+    want_stats = {dp: full.plan_stats(dp) for dp in dps}
+
+    rng = np.random.default_rng(1)
+    done = (rng.random(n) < 0.5).astype(np.uint8)
+    done[np.argmax(items["customers"])] = 1  # the longest item finished before the stop
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), WAVE)
+    ctx.plan_set(items)
+    bufs = []
+    for o in range(3):
+        t = torch.full((n,), float("nan"), device="cuda")
+        t[torch.from_numpy(done.astype(bool)).cuda()] = torch.from_numpy(want[o][done == 1]).cuda()
+        ctx.bind_output(o, t)
+        bufs.append(t)
+    ctx.run_plan_resume(done, seed=9)
+    for o in range(3):
+        assert np.array_equal(bufs[o].cpu().numpy(), want[o])
+    for dp in dps:
+        assert ctx.plan_stats(dp) == want_stats[dp]
+    # everything already done: only the reductions run
+    ctx.run_plan_resume(np.ones(n, np.uint8), seed=9)
+    for dp in dps:
+        assert ctx.plan_stats(dp) == want_stats[dp]
+    # nothing done: the whole plan
+    ctx.run_plan_resume(np.zeros(n, np.uint8), seed=9)
+    assert np.array_equal(bufs[0].cpu().numpy(), want[0])
