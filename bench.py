@@ -63,20 +63,46 @@ def parse():
                     help="target wall time of the CPU-oracle sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with a 256 MiB device-to-device copy (calibrates HBM counters)")
+    ap.add_argument("--mapping-counters", action="store_true",
+                    help="only run the walk and the forest fire once per mapping (for "
+                         "rocprofv3 memory counters, the paper's TLP vs WLP table)")
     return ap.parse_args()
 
 
+def mapping_counters(mrip):
+    """The random walk (1024 x 64 walkers x 1000 steps, the paper's model for
+    its TLP vs WLP memory-access table) and the forest fire (256 x 128^2 x 200)
+    once in each mapping, so that a counter run sees one launch of each."""
+    maps = (("simt", mrip.MRIP_MAP_SIMT), ("lane0", mrip.MRIP_MAP_LANE0),
+            ("wave", mrip.MRIP_MAP_WAVE))
+    out = {}
+    for name, mp in maps:
+        ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), mp)
+        ctx.run(1024, seed=42)
+        out["rw_" + name] = ctx.last_ms()
+    for name, mp in (maps[0], maps[2]):
+        ctx = mrip.Context(mrip.MRIP_FF, mrip.ff_params(128, 200, 0.01, 1e-5), mp)
+        ctx.run(256, seed=42)
+        out["ff_" + name] = ctx.last_ms()
+    print(json.dumps({"mapping_counters_kernel_ms": out}), flush=True)
+
+
 def timed_steps(ctx, steps, warmup, torch, mrip):
-    stream = torch.cuda.current_stream()
+    """K whole MRIP passes (replications, device reduction, interval). Run
+    k + 1 is enqueued before run k's interval is read (the library keeps each
+    run's statistics in its own slot), so the device does not wait for the
+    host between steps; every step's interval is still read."""
+    stream = torch.cuda.current_stream().cuda_stream
     for i in range(warmup):
-        ctx.run(R, seed=1000 + i)
+        ctx.run(R, seed=1000 + i, stream=stream)
         ctx.stats(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    half = None
-    for i in range(steps):
-        ctx.run(R, seed=42 + i, stream=stream.cuda_stream)
-        half = ctx.stats(0)  # the interval closes the step (synchronises)
+    ctx.run(R, seed=42, stream=stream)
+    for i in range(1, steps):
+        ctx.run(R, seed=42 + i, stream=stream)
+        ctx.stats_back(1, 0)  # the interval of step i - 1
+    half = ctx.stats(0)  # the last step's interval closes the timed region
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kernel_ms = ctx.history_ms(steps)
@@ -275,6 +301,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     mrip.load()
+    if args.mapping_counters:
+        mapping_counters(mrip)
+        return
 
     ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_WAVE)
     ctx.set_split(SPLIT)

@@ -203,6 +203,14 @@ MRIP_API mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void
  * MRIP_E_TOO_FEW if fewer than two replications. */
 MRIP_API mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence, mrip_stats_t *out);
 
+/* The same for the run `back` runs before the last one (0 = the last, at
+ * most 3), so a loop may enqueue run k + 1 before it reads run k's interval
+ * and keep the device busy meanwhile. Each run (mrip_run, mrip_run_plan)
+ * keeps its statistics in its own slot of a 4-run ring in pinned host
+ * memory; MRIP_E_STATE for runs no longer kept. Waits for that run only. */
+MRIP_API mrip_status mrip_stats_back(mrip_ctx ctx, uint32_t back, uint32_t output,
+                                     double confidence, mrip_stats_t *out);
+
 /* Copy output `output` of the last run (n_reps values; 10 per replication
  * for M/M/1 features) to dst, a device pointer if dst_is_device, else host.
  * `bytes` must be at least the output's size. Synchronises. */

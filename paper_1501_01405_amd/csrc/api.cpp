@@ -65,14 +65,31 @@ uint32_t ff_threshold(double prob) {
 }
 
 // The run's statistics land in pinned host memory that the reduction
-// kernel writes directly (no copy launch); mrip_stats waits for ev_stats.
+// kernel writes directly (no copy launch), one ring slot per run; reading
+// them waits for that slot's event.
 mrip_status ensure_events(mrip_ctx c) {
-  if (!c->ev_stats) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_stats, hipEventDisableTiming));
+  for (uint32_t i = 0; i < mrip_ctx_s::STATS_RING; ++i)
+    if (!c->ev_stats[i])
+      HIP_TRY(c, hipEventCreateWithFlags(&c->ev_stats[i], hipEventDisableTiming));
   if (!c->stats_host) {
-    HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, sizeof(double) * 3 * 4,
-                             hipHostMallocMapped));
+    const size_t bytes = sizeof(double) * mrip_ctx_s::STATS_RING * mrip_ctx_s::STATS_SLOT;
+    HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, bytes, hipHostMallocMapped));
     HIP_TRY(c, hipHostGetDevicePointer((void **)&c->stats_view, c->stats_host, 0));
   }
+  return MRIP_OK;
+}
+
+// Device view of the next run's statistics slot.
+double *next_stats_slot(mrip_ctx c) {
+  const uint32_t slot = (uint32_t)(c->stats_runs % mrip_ctx_s::STATS_RING);
+  return c->stats_view + (size_t)slot * mrip_ctx_s::STATS_SLOT;
+}
+
+// Mark the slot written by the reduction just enqueued on s.
+mrip_status commit_stats_slot(mrip_ctx c, hipStream_t s) {
+  const uint32_t slot = (uint32_t)(c->stats_runs % mrip_ctx_s::STATS_RING);
+  HIP_TRY(c, hipEventRecord(c->ev_stats[slot], s));
+  ++c->stats_runs;
   return MRIP_OK;
 }
 
@@ -394,25 +411,35 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     set.x[o] = outp[o];
     set.dtype[o] = output_dtype(ctx->model, o);
   }
-  HIP_TRY(ctx, launch_reduce_f64_multi(set, nout, n_reps, ctx->stats_view, s));
-  HIP_TRY(ctx, hipEventRecord(ctx->ev_stats, s));
+  HIP_TRY(ctx, launch_reduce_f64_multi(set, nout, n_reps, next_stats_slot(ctx), s));
+  st = commit_stats_slot(ctx, s);
+  if (st != MRIP_OK) return st;
   ctx->last = RUN_UNIFORM;
   ctx->last_n = n_reps;
   ctx->last_stream = s;
   return MRIP_OK;
 }
 
-mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence, mrip_stats_t *out) {
+mrip_status mrip_stats_back(mrip_ctx ctx, uint32_t back, uint32_t output, double confidence,
+                            mrip_stats_t *out) {
   if (!ctx || !out) return MRIP_E_INVAL;
   if (!(confidence > 0.0 && confidence < 1.0)) return inval(ctx, "confidence must be in (0, 1)");
-  if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
+  if (ctx->last == RUN_NONE || ctx->stats_runs == 0) return (ctx->err = "no run yet"), MRIP_E_STATE;
   if (output >= scalar_outputs(ctx->model)) return inval(ctx, "no such scalar output");
-  HIP_TRY(ctx, hipEventSynchronize(ctx->ev_stats));
+  if (back >= mrip_ctx_s::STATS_RING || back >= ctx->stats_runs)
+    return (ctx->err = "no statistics kept for that run"), MRIP_E_STATE;
+  const uint32_t slot = (uint32_t)((ctx->stats_runs - 1 - back) % mrip_ctx_s::STATS_RING);
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev_stats[slot]));
   double nmv[3];
-  std::memcpy(nmv, ctx->stats_host + 3 * output, sizeof(nmv));
+  std::memcpy(nmv, ctx->stats_host + (size_t)slot * mrip_ctx_s::STATS_SLOT + 3 * output,
+              sizeof(nmv));
   mrip_status st = finish_stats(nmv, confidence, out);
   if (st == MRIP_E_TOO_FEW) ctx->err = "fewer than two replications";
   return st;
+}
+
+mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence, mrip_stats_t *out) {
+  return mrip_stats_back(ctx, 0, output, confidence, out);
 }
 
 mrip_status mrip_output_ptr(mrip_ctx ctx, uint32_t output, const void **ptr) {
@@ -579,8 +606,9 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
       set.x[o] = outp[o];
       set.dtype[o] = 1;
     }
-    HIP_TRY(ctx, launch_reduce_f64_multi(set, 3, ctx->n_items, ctx->stats_view, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_stats, s));
+    HIP_TRY(ctx, launch_reduce_f64_multi(set, 3, ctx->n_items, next_stats_slot(ctx), s));
+    st = commit_stats_slot(ctx, s);
+    if (st != MRIP_OK) return st;
   }
   ctx->last_stream = s;
   return MRIP_OK;

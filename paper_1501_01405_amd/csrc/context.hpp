@@ -104,8 +104,12 @@ struct mrip_ctx_s {
   mrip::DevBuf scratch;
   // (n, mean, var) per scalar output: pinned host memory written by the
   // reduction kernel through its device view
+  // A ring of STATS_RING slots, one per run, so a caller may read run k's
+  // statistics after enqueuing run k + 1.
+  static constexpr uint32_t STATS_RING = 4, STATS_SLOT = 12;  // doubles per slot
   double *stats_host = nullptr, *stats_view = nullptr;
-  hipEvent_t ev_stats = nullptr;    // recorded after that reduction
+  hipEvent_t ev_stats[STATS_RING] = {};  // recorded after each slot's reduction
+  uint64_t stats_runs = 0;               // reductions enqueued so far
   mrip::RunKind last = mrip::RUN_NONE;
   uint64_t last_n = 0;
   hipStream_t last_stream = nullptr;
@@ -129,7 +133,8 @@ struct mrip_ctx_s {
 
   ~mrip_ctx_s() {
     if (stats_host) (void)hipHostFree(stats_host);
-    if (ev_stats) (void)hipEventDestroy(ev_stats);
+    for (uint32_t i = 0; i < STATS_RING; ++i)
+      if (ev_stats[i]) (void)hipEventDestroy(ev_stats[i]);
     for (uint32_t i = 0; i < RING; ++i) {
       if (ring0[i]) (void)hipEventDestroy(ring0[i]);
       if (ring1[i]) (void)hipEventDestroy(ring1[i]);

@@ -82,6 +82,7 @@ _SIGS = {
                             C.POINTER(u32)]),
     "mrip_run": (st, [ctx_t, u64, u64, vp]),
     "mrip_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t)]),
+    "mrip_stats_back": (st, [ctx_t, u32, u32, f64, C.POINTER(mrip_stats_t)]),
     "mrip_outputs": (st, [ctx_t, u32, vp, u64, C.c_int]),
     "mrip_output_ptr": (st, [ctx_t, u32, C.POINTER(vp)]),
     "mrip_bind_output": (st, [ctx_t, u32, vp, u64]),
@@ -214,6 +215,12 @@ def mrip_run(ctx, n_reps, seed, stream=None):
 def mrip_stats(ctx, output=0, confidence=0.95):
     s = mrip_stats_t()
     check(load().mrip_stats(ctx, output, confidence, C.byref(s)), ctx)
+    return s.as_dict()
+
+
+def mrip_stats_back(ctx, back, output=0, confidence=0.95):
+    s = mrip_stats_t()
+    check(load().mrip_stats_back(ctx, back, output, confidence, C.byref(s)), ctx)
     return s.as_dict()
 
 
@@ -427,6 +434,9 @@ class Context:
 
     def stats(self, output=0, confidence=0.95):
         return mrip_stats(self.ctx, output, confidence)
+
+    def stats_back(self, back, output=0, confidence=0.95):
+        return mrip_stats_back(self.ctx, back, output, confidence)
 
     def output(self, output=0, n=None):
         import torch

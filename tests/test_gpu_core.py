@@ -88,3 +88,20 @@ def test_rw_many_replications_sampled(gpu):
         ids = [0, 1, 8191, 16383]
         essd, edist = core.rw_many(5, ids, 64, 64, 1000)
         assert np.array_equal(ssd[ids], essd) and np.array_equal(dist[ids], edist)
+
+
+def test_statistics_of_earlier_runs_are_kept(gpu):
+    # a pipelined loop enqueues run k + 1 before reading run k's interval
+    announce("stats ring")
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 5000), WAVE)
+    seeds = [5, 6, 7, 8, 9]
+    for s in seeds:
+        ctx.run(64, seed=s)
+    for back in range(4):
+        one = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 5000), WAVE)
+        one.run(64, seed=seeds[-1 - back])
+        for o in range(3):
+            assert ctx.stats_back(back, o) == one.stats(o)
+    assert ctx.stats_back(0, 1) == ctx.stats(1)
+    with pytest.raises(mrip.MripError):
+        ctx.stats_back(4, 0)  # only the last four runs are kept
