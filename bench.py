@@ -251,16 +251,17 @@ def extras(torch, mrip, inputs):
     # on both generators, their kernel times and the z-score of the difference
     # of the two estimates (section 5.3: a second generator checks that the
     # streams do not bias the results)
-    cases = (("mm1_1024x1e5_wait", mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), 0, R * N),
-             ("pi_1024x1e6", mrip.MRIP_PI, mrip.pi_params(1_000_000), 1, 1024 * 10**6),
+    cases = (("mm1_1024x1e5_wait", mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), 0, R * N, SPLIT),
+             ("pi_1024x1e6", mrip.MRIP_PI, mrip.pi_params(1_000_000), 1, 1024 * 10**6, 1),
              ("rw_1024x64x1000_ssd", mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), 0,
-              1024 * 64 * 1000))
+              1024 * 64 * 1000, 1))
     tau = {}
-    for name, model, params, o, events in cases:
+    for name, model, params, o, events, split in cases:
         row = {}
         for gname, g in (("philox", mrip.MRIP_RNG_PHILOX), ("taus88", mrip.MRIP_RNG_TAUS88)):
             ctx = mrip.Context(model, params, mrip.MRIP_MAP_WAVE)
             ctx.set_rng(g)
+            ctx.set_split(split)
             v, ms = rate(ctx, 1024, events, runs=2)
             st = ctx.stats(o)
             row[gname] = {"kernel_ms": ms, "events_per_s": v, "mean": st["mean"],

@@ -184,11 +184,13 @@ MRIP_API mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t reps_per_wave, uint32
 MRIP_API mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep);
 
 /* Stream source of mrip_run (see mrip_rng). TAUS88 is defined for the
- * random walk, M/M/1 and pi models, every mapping, one wavefront per
- * replication; MRIP_E_UNSUPPORTED for the forest fire, for a context with
- * mrip_set_split > 1, and later plan or control-variate calls on it (those
- * use Philox). Builds and uploads the generator's jump tables (23.6 KB)
- * once, synchronously. Default PHILOX. */
+ * random walk, M/M/1 and pi models in every mapping; its M/M/1 WAVE engine
+ * gives each of the replication's lanes (16, 32 or 64 of a wavefront, or 2
+ * or 4 wavefronts with mrip_set_split) a contiguous run of customers.
+ * MRIP_E_UNSUPPORTED for the forest fire, for splits over 8 wavefronts, and
+ * for later plan or control-variate calls on the context (those use
+ * Philox). Builds and uploads the generator's jump tables (22.5 KB) once,
+ * synchronously. Default PHILOX. */
 MRIP_API mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng);
 
 /* --------------------------------------------------------------- the path */

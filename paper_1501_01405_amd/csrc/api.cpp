@@ -277,8 +277,8 @@ mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep) {
   if (waves_per_rep > 1 && (ctx->model != MRIP_MM1 || ctx->mapping != MRIP_MAP_WAVE))
     return inval(ctx, "splitting a replication is defined for the M/M/1 WAVE engine");
   if (waves_per_rep > 1 && ctx->rpw != 1) return inval(ctx, "splitting needs reps_per_wave = 1");
-  if (waves_per_rep > 1 && ctx->rng != MRIP_RNG_PHILOX)
-    return (ctx->err = "split replications draw from Philox streams"), MRIP_E_UNSUPPORTED;
+  if (waves_per_rep > 4 && ctx->rng != MRIP_RNG_PHILOX)
+    return (ctx->err = "taus88 replications split over at most 4 wavefronts"), MRIP_E_UNSUPPORTED;
   ctx->split = waves_per_rep;
   return MRIP_OK;
 }
@@ -289,8 +289,8 @@ mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng) {
   if (rng == MRIP_RNG_TAUS88) {
     if (ctx->model == MRIP_FF)
       return (ctx->err = "the forest fire draws from Philox streams"), MRIP_E_UNSUPPORTED;
-    if (ctx->split != 1)
-      return (ctx->err = "split replications draw from Philox streams"), MRIP_E_UNSUPPORTED;
+    if (ctx->split > 4)
+      return (ctx->err = "taus88 replications split over at most 4 wavefronts"), MRIP_E_UNSUPPORTED;
     mrip_status st = upload_taus_tables(ctx);
     if (st != MRIP_OK) return st;
   }

@@ -55,6 +55,9 @@ struct Mm1Args {
 hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t reps_per_wave, uint32_t workgroup,
                            hipStream_t s);
 hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s);
+// taus88 streams, WAVE mapping: lanes_per_rep (16, 32, 64, 128 or 256)
+// lanes per replication, each on a contiguous run of its customers.
+hipError_t launch_mm1_taus(const Mm1Args &a, uint32_t lanes_per_rep, hipStream_t s);
 // WAVE mapping with each replication split over 2 or 4 wavefronts of a
 // 256-thread workgroup (speculate from carry 0, then correct in order).
 hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s);

@@ -21,9 +21,10 @@
 // customer after the other, as the paper's thread-per-replication form.
 //
 // On taus88 streams customer n takes outputs 2n (A) and 2n+1 (S) of the
-// replication's stream. A WAVE lane reads its P customers' 2P outputs in
-// order and then jumps over the rest of the chunk with a stride table; a
-// SIMT lane reads the stream in order.
+// replication's stream, a sequential generator: the wavefront engine gives
+// every lane a contiguous run of customers instead (mm1_taus_kernel: one
+// jump per lane, two passes over its run); a SIMT lane reads the stream in
+// order.
 #include "device.hpp"
 #include "kernels.hpp"
 #include "taus.hpp"
@@ -92,22 +93,6 @@ struct PhiloxSource {
   template <int RPW, int P>
   __device__ __forceinline__ Draw<P> next(uint64_t base, const Rep &d) {
     return draw_chunk<RPW, P>(base, d, k0, k1);
-  }
-};
-
-struct TausSource {
-  Taus t;
-  const uint32_t *__restrict__ stride;  // jump over the rest of a chunk
-  template <int RPW, int P>
-  __device__ __forceinline__ Draw<P> next(uint64_t, const Rep &d) {
-    Draw<P> r;
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      r.A[j] = exp_variate(taus_next(t), d.ca);
-      r.S[j] = exp_variate(taus_next(t), d.cs);
-    }
-    taus_jump_uniform(t, stride);
-    return r;
   }
 };
 
@@ -368,7 +353,7 @@ __device__ __forceinline__ Rep item_rep(const Mm1Args &a, uint64_t slot, uint64_
   return d;
 }
 
-template <int RPW, int RNG>
+template <int RPW>
 __global__ void mm1_wave_kernel(Mm1Args a, float ca, float cs) {
   constexpr int S = 4 / RPW;
   const int lane = threadIdx.x & 63;
@@ -378,15 +363,173 @@ __global__ void mm1_wave_kernel(Mm1Args a, float ca, float cs) {
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   if (wave * RPW >= a.n_reps) return;  // whole wave idle (wave-uniform)
   const Rep d = uniform_rep(a, r, ca, cs);
-  if (RNG == RNG_TAUS88) {
-    TausSource src;
-    src.t = taus_seed(TAG_MM1, d.dp, d.rep, k0, k1);
-    src.stride = a.taus + (uint64_t)taus_mm1_stride_table(RPW) * TAUS_COLS;
-    taus_skip(src.t, 2 * lane_first_customer<RPW, MM1_P>(0), a.taus);
-    wave_group<RPW>(d, src, a.feature_prefix, a);
-  } else {
-    PhiloxSource src{k0, k1};
-    wave_group<RPW>(d, src, a.feature_prefix, a);
+  PhiloxSource src{k0, k1};
+  wave_group<RPW>(d, src, a.feature_prefix, a);
+}
+
+// taus88 streams, WAVE mapping. The LPR lanes of a replication (16 or 32 of
+// a wavefront, or 1, 2 or 4 whole wavefronts) each take a contiguous run of
+// B = ceil(N / LPR) customers, so a lane reads its run of the stream in
+// order after one jump. Pass 1 composes the run's max-plus map; the maps
+// are scanned in lane order (shuffles inside a wavefront, the wavefronts'
+// totals through LDS), which gives each lane the system time before its
+// run; pass 2 re-reads the run from the saved state and applies Lindley's
+// recursion. No speculation: the scan is exact max-plus composition.
+template <int LPR>
+__global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, float cs) {
+  constexpr int G = LPR < 64 ? LPR : 64;  // lanes of one replication inside a wavefront
+  constexpr int RPB = 256 / LPR;          // replications per workgroup
+  __shared__ float sh_a[4], sh_b[4];      // wavefront totals of the scan
+  __shared__ float sh_f[4][11];           // per-wavefront partial sums
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = tid % LPR;                // lane within the replication
+  const int g = lane % G;                 // lane within its group of one wavefront
+  const uint64_t r = (uint64_t)blockIdx.x * RPB + tid / LPR;
+  const uint64_t N = r < a.n_reps ? a.customers : 0, K = a.feature_prefix;
+  const uint64_t B = (a.customers + LPR - 1) / LPR;
+  const uint64_t n0 = min(N, (uint64_t)j * B), n1 = min(N, n0 + B);
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  Taus t0 = taus_seed(TAG_MM1, 0u, (uint32_t)r, k0, k1);
+  taus_skip(t0, 2 * n0, a.taus);
+
+  // pass 1: the run's composite map T -> max(ma, T + mb)
+  float ma = kNegInf, mb = 0.0f;
+  Taus t = t0;
+  for (uint64_t n = n0; n < n1; ++n) {
+    const float A = exp_variate(taus_next(t), ca);
+    const float S = exp_variate(taus_next(t), cs);
+    const float bj = S - A;
+    ma = fmaxf(S, ma + bj);
+    mb = mb + bj;
+  }
+  // inclusive scan in lane order (earlier runs first)
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    const float pa = __shfl_up(ma, o, G), pb = __shfl_up(mb, o, G);
+    if (g >= o) {
+      ma = fmaxf(ma, pa + mb);
+      mb = pb + mb;
+    }
+  }
+  float ea = __shfl_up(ma, 1, G), eb = __shfl_up(mb, 1, G);
+  if (g == 0) {
+    ea = kNegInf;
+    eb = 0.0f;
+  }
+  // system time entering this wavefront's part of the replication
+  float carry = 0.0f;
+  if (LPR > 64) {
+    if (lane == 63) {
+      sh_a[wave] = ma;
+      sh_b[wave] = mb;
+    }
+    __syncthreads();
+    for (int w = wave - j / 64; w < wave; ++w) carry = fmaxf(sh_a[w], carry + sh_b[w]);
+  }
+  float T = fmaxf(ea, carry + eb);
+
+  // pass 2: Lindley's recursion over the run, from the saved stream state
+  t = t0;
+  Kahan kw, kt, ki;
+  Feat ft;
+  uint64_t n = n0;
+  const uint64_t nf = min(n1, max(n0, K));  // customers of the feature prefix
+  for (; n < nf; ++n) {
+    const float A = exp_variate(taus_next(t), ca);
+    const float S = exp_variate(taus_next(t), cs);
+    const float dlt = T - A;
+    const float W = fmaxf(0.0f, dlt);
+    const float I = W - dlt;
+    T = W + S;
+    kw.add(W);
+    kt.add(T);
+    ki.add(I);
+    ft.sa += A;
+    ft.ss += S;
+    ft.sw += W;
+    ft.st += T;
+    ft.si += I;
+    ft.zeros += (W == 0.0f);
+    ft.wmax = fmaxf(ft.wmax, W);
+    if (n + 1 == K) ft.tlast = T;
+  }
+  while (n < n1) {
+    // plain fp32 sums over up to 8 customers, then one compensated add
+    const uint64_t ne = min(n1, n + 8);
+    float sw = 0.0f, st = 0.0f, si = 0.0f;
+    for (; n < ne; ++n) {
+      const float A = exp_variate(taus_next(t), ca);
+      const float S = exp_variate(taus_next(t), cs);
+      const float dlt = T - A;
+      const float W = fmaxf(0.0f, dlt);
+      const float I = W - dlt;
+      T = W + S;
+      sw += W;
+      st += T;
+      si += I;
+    }
+    kw.add(sw);
+    kt.add(st);
+    ki.add(si);
+  }
+
+  // the replication's sums: lanes of the wavefront, then its wavefronts in
+  // order. v: W, T, I, then the features' A, S, W, T, zeros, max W, T_{K-1}, I
+  float v[11];
+  v[0] = group_sum_compensated(kw.value(), G);
+  v[1] = group_sum_compensated(kt.value(), G);
+  v[2] = group_sum_compensated(ki.value(), G);
+  v[3] = group_sum_compensated(ft.sa, G);
+  v[4] = group_sum_compensated(ft.ss, G);
+  v[5] = group_sum_compensated(ft.sw, G);
+  v[6] = group_sum_compensated(ft.st, G);
+  v[7] = (float)group_sum_i(ft.zeros, G);
+  v[8] = group_max(ft.wmax, G);
+  v[9] = group_sum_compensated(ft.tlast, G);
+  v[10] = group_sum_compensated(ft.si, G);
+  if (LPR > 64) {
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 11; ++k) sh_f[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (j == 0) {  // lane 0 of the replication's first wavefront
+#pragma unroll
+      for (int k = 0; k < 11; ++k) {
+        float hi = sh_f[wave][k], lo = 0.0f;
+        for (int w = wave + 1; w < wave + LPR / 64; ++w) {
+          if (k == 8) {
+            hi = fmaxf(hi, sh_f[w][k]);
+          } else {
+            float s2, e;
+            two_sum(hi, sh_f[w][k], s2, e);
+            hi = s2;
+            lo += e;
+          }
+        }
+        v[k] = hi + lo;
+      }
+    }
+  }
+  if (j == 0 && N > 0) {
+    const float nf_ = (float)N;
+    a.mean_w[r] = v[0] / nf_;
+    a.mean_t[r] = v[1] / nf_;
+    a.mean_i[r] = v[2] / nf_;
+    if (K > 0) {
+      const float kf = (float)K;
+      float *f = a.features + r * 10;
+      f[0] = a.lambda / a.mu;
+      f[1] = a.mu;
+      f[2] = v[3] / kf;
+      f[3] = v[4] / kf;
+      f[4] = v[5] / kf;
+      f[5] = v[6] / kf;
+      f[6] = v[7] / kf;
+      f[7] = v[8];
+      f[8] = v[10] / kf;
+      f[9] = v[9];
+    }
   }
 }
 
@@ -697,21 +840,36 @@ float host_neg_mean_ln2(float rate) {
 
 }  // namespace
 
+template <int LPR>
+hipError_t taus_launch(const Mm1Args &a, hipStream_t s) {
+  constexpr uint32_t RPB = 256 / LPR;
+  const uint64_t blocks = (a.n_reps + RPB - 1) / RPB;
+  const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
+  hipLaunchKernelGGL(mm1_taus_kernel<LPR>, dim3((uint32_t)blocks), dim3(256), 0, s, a, ca, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_mm1_taus(const Mm1Args &a, uint32_t lanes_per_rep, hipStream_t s) {
+  switch (lanes_per_rep) {
+    case 16: return taus_launch<16>(a, s);
+    case 32: return taus_launch<32>(a, s);
+    case 64: return taus_launch<64>(a, s);
+    case 128: return taus_launch<128>(a, s);
+    case 256: return taus_launch<256>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t rpw, uint32_t wg, hipStream_t s) {
   const uint64_t waves = (a.n_reps + rpw - 1) / rpw;
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (waves + wpb - 1) / wpb;
   const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
   const dim3 g((uint32_t)blocks), b(wg);
-  if (a.rng == RNG_TAUS88) {
-    if (rpw == 1) hipLaunchKernelGGL((mm1_wave_kernel<1, RNG_TAUS88>), g, b, 0, s, a, ca, cs);
-    else if (rpw == 2) hipLaunchKernelGGL((mm1_wave_kernel<2, RNG_TAUS88>), g, b, 0, s, a, ca, cs);
-    else hipLaunchKernelGGL((mm1_wave_kernel<4, RNG_TAUS88>), g, b, 0, s, a, ca, cs);
-  } else {
-    if (rpw == 1) hipLaunchKernelGGL((mm1_wave_kernel<1, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
-    else if (rpw == 2) hipLaunchKernelGGL((mm1_wave_kernel<2, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
-    else hipLaunchKernelGGL((mm1_wave_kernel<4, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
-  }
+  if (a.rng == RNG_TAUS88) return launch_mm1_taus(a, 64 / rpw, s);
+  if (rpw == 1) hipLaunchKernelGGL(mm1_wave_kernel<1>, g, b, 0, s, a, ca, cs);
+  else if (rpw == 2) hipLaunchKernelGGL(mm1_wave_kernel<2>, g, b, 0, s, a, ca, cs);
+  else hipLaunchKernelGGL(mm1_wave_kernel<4>, g, b, 0, s, a, ca, cs);
   return hipGetLastError();
 }
 
@@ -724,6 +882,7 @@ hipError_t split_launch(const Mm1Args &a, float ca, float cs, hipStream_t s) {
 }
 
 hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s) {
+  if (a.rng == RNG_TAUS88) return launch_mm1_taus(a, 64 * waves_per_rep, s);
   const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
   if (waves_per_rep == 2) return split_launch<2>(a, ca, cs, s);
   if (waves_per_rep == 4) return split_launch<4>(a, ca, cs, s);

@@ -16,8 +16,7 @@
 // Every step is linear over GF(2), so d steps are one 88-column matrix
 // (per component, the images of the k state bits); lanes that start inside
 // a stream jump there with tables of such matrices built on the host
-// (taus_tables.cpp): tables 0..63 advance 2^j outputs, the next three the
-// per-chunk strides of the M/M/1 wavefront engine.
+// (taus_tables.cpp): table j advances 2^j outputs.
 #pragma once
 #include <stdint.h>
 
@@ -32,15 +31,8 @@ constexpr int TAUS_K1 = 29, TAUS_Q1 = 2, TAUS_S1 = 4;
 constexpr int TAUS_K2 = 28, TAUS_Q2 = 3, TAUS_S2 = 17;
 constexpr int TAUS_COLS = TAUS_K0 + TAUS_K1 + TAUS_K2;  // 88 words per table
 constexpr int TAUS_POW2 = 64;                           // tables 2^0 .. 2^63
-constexpr int TAUS_TABLES = TAUS_POW2 + 3;              // + M/M/1 strides, rpw 1, 2, 4
+constexpr int TAUS_TABLES = TAUS_POW2;
 constexpr uint32_t TAG_TAUS_SEED = 5;
-
-// Outputs skipped between two chunks of one lane in the M/M/1 wavefront
-// engine: a chunk takes 2 * 512 / rpw outputs, 16 of them this lane's.
-constexpr uint64_t taus_mm1_stride(uint32_t rpw) { return 2ull * 512 / rpw - 16; }
-constexpr int taus_mm1_stride_table(uint32_t rpw) {
-  return TAUS_POW2 + (rpw == 1 ? 0 : rpw == 2 ? 1 : 2);
-}
 
 // Host: fill `out` (TAUS_TABLES x TAUS_COLS words) with the jump tables.
 void taus_build_tables(uint32_t *out);
@@ -82,14 +74,6 @@ __device__ __forceinline__ void taus_jump(Taus &t, const uint32_t *__restrict__ 
   t.z2 = taus_apply<TAUS_K2>(t.z2, table + TAUS_K0 + TAUS_K1);
 }
 
-// The same jump for a table address that is uniform across the wavefront
-// (a kernel argument plus a constant): the table is re-read at every jump
-// with scalar loads instead of being kept in 88 scalar registers across the
-// caller's loop, where it would spill.
-__device__ __forceinline__ void taus_jump_uniform(Taus &t, const uint32_t *__restrict__ table) {
-  asm volatile("" : "+s"(table));
-  taus_jump(t, table);
-}
 
 // Random Spacing start state of the stream of (model, dp, rep).
 __device__ __forceinline__ Taus taus_seed(uint32_t model, uint32_t dp, uint32_t rep, uint32_t k0,

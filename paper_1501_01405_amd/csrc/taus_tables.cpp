@@ -1,8 +1,8 @@
 // Jump tables of the taus88 generator (see taus.hpp). One step of a
 // component is linear over GF(2) in its k state bits, so d steps are a
 // matrix; it is kept as the images of the k state bits (columns), and
-// matrices compose column by column. Tables 0..63 advance 2^j outputs (the
-// j-th square of one step); the M/M/1 chunk strides are products of those.
+// matrices compose column by column. Table j advances 2^j outputs (the j-th
+// square of one step).
 #include <stdint.h>
 
 #include <cstring>
@@ -66,18 +66,6 @@ void taus_build_tables(uint32_t *out) {
   for (int j = 1; j < TAUS_POW2; ++j)
     for (int c = 0; c < 3; ++c) pow2[j][c] = compose(pow2[j - 1][c], pow2[j - 1][c]);
   for (int j = 0; j < TAUS_POW2; ++j) store(pow2[j], out + (size_t)j * TAUS_COLS);
-  const uint32_t rpws[3] = {1, 2, 4};
-  for (int i = 0; i < 3; ++i) {
-    const uint64_t d = taus_mm1_stride(rpws[i]);
-    Mat m[3];
-    bool first = true;
-    for (int j = 0; j < TAUS_POW2; ++j) {
-      if (!((d >> j) & 1u)) continue;
-      for (int c = 0; c < 3; ++c) m[c] = first ? pow2[j][c] : compose(pow2[j][c], m[c]);
-      first = false;
-    }
-    store(m, out + (size_t)taus_mm1_stride_table(rpws[i]) * TAUS_COLS);
-  }
 }
 
 }  // namespace mrip

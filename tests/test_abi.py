@@ -120,9 +120,9 @@ def test_generator_choice_checks():
     L.mrip_destroy(ctx)
     ctx = mrip.ctx_t()
     assert L.mrip_create(C.byref(ctx), mrip.MRIP_MM1, C.byref(mrip.mm1_params()), 0) == 0
-    assert L.mrip_set_split(ctx, 2) == mrip.MRIP_OK
+    assert L.mrip_set_split(ctx, 8) == mrip.MRIP_OK
     assert L.mrip_set_rng(ctx, mrip.MRIP_RNG_TAUS88) == mrip.MRIP_E_UNSUPPORTED
-    assert b"Philox" in L.mrip_last_error(ctx)
+    assert b"4 wavefronts" in L.mrip_last_error(ctx)
     L.mrip_destroy(ctx)
     assert L.mrip_taus88(1, 4, 0, 0, 0, 0, None, None) == mrip.MRIP_OK  # n = 0: nothing to do
     assert L.mrip_taus88(1, 4, 0, 0, 0, 5, None, None) == mrip.MRIP_E_INVAL

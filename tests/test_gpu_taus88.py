@@ -82,13 +82,20 @@ def test_rw_bit_exact(gpu, mapping, walkers, grid, steps, R):
     assert np.array_equal(ctx.output(1).cpu().numpy(), distinct)
 
 
-@pytest.mark.parametrize("mapping,rpw,wg", [(SIMT, 1, 64), (LANE0, 1, 64), (WAVE, 1, 256),
-                                            (WAVE, 2, 64), (WAVE, 4, 1024)])
+@pytest.mark.parametrize("mapping,rpw,wg,split", [(SIMT, 1, 64, 1), (LANE0, 1, 64, 1),
+                                                  (WAVE, 1, 256, 1), (WAVE, 2, 64, 1),
+                                                  (WAVE, 4, 1024, 1), (WAVE, 1, 256, 2),
+                                                  (WAVE, 1, 256, 4)])
 @pytest.mark.parametrize("N,R,lam,K", [(1, 3, 0.9, 0), (100, 5, 0.5, 0), (513, 33, 0.9, 0),
-                                       (5000, 24, 0.9, 1000), (20000, 9, 0.95, 0)])
-def test_mm1_matches_oracle(gpu, mapping, rpw, wg, N, R, lam, K):
-    announce("mm1 taus88", mapping, rpw, wg, N, R, lam, K)
+                                       (5000, 24, 0.9, 1000), (20000, 9, 0.95, 0),
+                                       (777, 7, 0.8, 300)])
+def test_mm1_matches_oracle(gpu, mapping, rpw, wg, split, N, R, lam, K):
+    # the lanes of a replication take contiguous runs: N below, at and past
+    # one customer per lane, and feature prefixes that end inside a run
+    announce("mm1 taus88", mapping, rpw, wg, split, N, R, lam, K)
     ctx = _ctx(mrip.MRIP_MM1, mrip.mm1_params(lam, 1.0, N, K), mapping, rpw, wg)
+    if split > 1:
+        ctx.set_split(split)
     ctx.run(R, seed=3)
     outs = np.stack([ctx.output(o).cpu().numpy() for o in range(3)], axis=1)
     res = core.mm1_many(3, R, N, lam, 1.0, features=K, threads=core.default_threads(),
@@ -102,10 +109,12 @@ def test_mm1_matches_oracle(gpu, mapping, rpw, wg, N, R, lam, K):
         assert np.abs(feat[:, 6] - res[1][:, 6]).max() <= 2.0 / K
 
 
-def test_mm1_wave_sampled_at_full_size(gpu):
+@pytest.mark.parametrize("split", [1, 4])
+def test_mm1_wave_sampled_at_full_size(gpu, split):
     # 1024 x 1e5 (lambda 0.9) on taus88, WAVE: sampled replications
-    announce("mm1 taus88 1024 x 1e5")
+    announce("mm1 taus88 1024 x 1e5", split)
     ctx = _ctx(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 100000), WAVE)
+    ctx.set_split(split)
     ctx.run(1024, seed=8)
     outs = np.stack([ctx.output(o).cpu().numpy() for o in range(3)], axis=1)
     ids = [0, 1, 517, 1023]
@@ -157,6 +166,6 @@ def test_philox_only_paths_refuse_taus88(gpu):
     with pytest.raises(mrip.MripError):
         ctx.plan_set(items)
     with pytest.raises(mrip.MripError):
-        ctx.set_split(2)
+        ctx.set_split(8)
     ctx.set_rng(mrip.MRIP_RNG_PHILOX)
-    ctx.set_split(2)  # back on Philox, splitting is allowed again
+    ctx.set_split(8)  # back on Philox, splitting over 8 is allowed again
