@@ -105,3 +105,20 @@ def test_statistics_of_earlier_runs_are_kept(gpu):
     assert ctx.stats_back(0, 1) == ctx.stats(1)
     with pytest.raises(mrip.MripError):
         ctx.stats_back(4, 0)  # only the last four runs are kept
+
+
+@pytest.mark.parametrize("rng", [mrip.MRIP_RNG_PHILOX, mrip.MRIP_RNG_TAUS88])
+def test_rw_segmented_and_sequential_forms_agree(gpu, rng):
+    # up to 2048 replications the walk runs as a segmented scan, beyond it
+    # one wave per replication walks its steps in order: same outputs
+    announce("rw forms", rng)
+    for W, G, T in ((64, 64, 1000), (7, 32, 77), (64, 128, 3000)):
+        small = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T), WAVE)
+        small.set_rng(rng)
+        small.run(2048, seed=9)
+        big = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T), WAVE)
+        big.set_rng(rng)
+        big.run(2049, seed=9)
+        for o in range(2):
+            assert np.array_equal(small.output(o).cpu().numpy(),
+                                  big.output(o).cpu().numpy()[:2048])
