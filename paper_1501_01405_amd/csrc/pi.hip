@@ -13,6 +13,10 @@
 // On taus88 streams point i takes outputs 2i and 2i+1 of the replication's
 // stream; in the WAVE form lane l takes the contiguous run of points
 // [l B, (l+1) B), B = ceil(points / 64), after jumping 2 l B outputs.
+//
+// With few replications a wavefront each leaves the chip idle, so
+// pi_wide_kernel<X> gives a replication X wavefronts (a workgroup); the hit
+// count is an integer sum, identical however the points are shared out.
 #include "device.hpp"
 #include "kernels.hpp"
 #include "taus.hpp"
@@ -112,9 +116,74 @@ __global__ void pi_simt_taus_kernel(PiArgs a) {
   a.estimate[r] = (float)(4.0 * (double)hits / (double)a.points);
 }
 
+template <int X, int RNG>
+__global__ __launch_bounds__(64 * X) void pi_wide_kernel(PiArgs a) {
+  constexpr uint32_t L = 64 * X;  // lanes per replication
+  __shared__ uint32_t sh[X];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t r = blockIdx.x;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  uint32_t hits = 0;
+  if (RNG == RNG_TAUS88) {
+    const uint64_t per = (a.points + L - 1) / L;
+    const uint64_t p0 = min(a.points, (uint64_t)tid * per), p1 = min(a.points, p0 + per);
+    Taus t = taus_seed(TAG_PI, 0u, (uint32_t)r, k0, k1);
+    taus_skip(t, 2 * p0, a.taus);
+    uint64_t i = p0;
+    for (; i + 2 <= p1; i += 2) {
+      const uint32_t x0 = taus_next(t), y0 = taus_next(t);
+      const uint32_t x1 = taus_next(t), y1 = taus_next(t);
+      hits += inside(x0, y0) + inside(x1, y1);
+    }
+    if (i < p1) {
+      const uint32_t x0 = taus_next(t), y0 = taus_next(t);
+      hits += inside(x0, y0);
+    }
+  } else {
+    const uint64_t blocks = (a.points + 1) / 2;
+    uint64_t k = tid;
+    for (; k + 3 * L < blocks; k += 4 * L) {
+      hits += block_hits(k, a.points, (uint32_t)r, k0, k1);
+      hits += block_hits(k + L, a.points, (uint32_t)r, k0, k1);
+      hits += block_hits(k + 2 * L, a.points, (uint32_t)r, k0, k1);
+      hits += block_hits(k + 3 * L, a.points, (uint32_t)r, k0, k1);
+    }
+    for (; k < blocks; k += L) hits += block_hits(k, a.points, (uint32_t)r, k0, k1);
+  }
+  const int wave_total = group_sum_i((int)hits, 64);
+  if ((tid & 63) == 0) sh[tid >> 6] = (uint32_t)wave_total;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t total = 0;
+    for (int w = 0; w < X; ++w) total += sh[w];
+    a.hits[r] = (int32_t)total;
+    a.estimate[r] = (float)(4.0 * (double)total / (double)a.points);
+  }
+}
+
+template <int X>
+hipError_t wide_launch(const PiArgs &a, hipStream_t s) {
+  if (a.rng == RNG_TAUS88)
+    hipLaunchKernelGGL((pi_wide_kernel<X, RNG_TAUS88>), dim3((uint32_t)a.n_reps), dim3(64 * X),
+                       0, s, a);
+  else
+    hipLaunchKernelGGL((pi_wide_kernel<X, RNG_PHILOX>), dim3((uint32_t)a.n_reps), dim3(64 * X),
+                       0, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_pi_wave(const PiArgs &a, uint32_t wg, hipStream_t s) {
+  // aim at about 4096 wavefronts (four per SIMD) when replications are few
+  // and long enough to share out
+  if (a.n_reps < 4096 && a.points >= 65536) {
+    const uint64_t x = 4096 / a.n_reps;
+    if (x >= 16) return wide_launch<16>(a, s);
+    if (x >= 8) return wide_launch<8>(a, s);
+    if (x >= 4) return wide_launch<4>(a, s);
+    if (x >= 2) return wide_launch<2>(a, s);
+  }
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (a.n_reps + wpb - 1) / wpb;
   if (a.rng == RNG_TAUS88)

@@ -44,3 +44,17 @@ def test_pi_paper_configuration(gpu):
     e = ostats.summarize(est)
     assert abs(s["mean"] - e["mean"]) <= 1e-12 * e["mean"]
     assert abs(s["mean"] - math.pi) < 5 * s["half_width"]
+
+
+@pytest.mark.parametrize("R", [2049, 1500, 700, 300, 100])
+@pytest.mark.parametrize("rng", ["philox", "taus88"])
+def test_pi_shared_out_over_wavefronts(gpu, R, rng):
+    # fewer than 4096 long replications get 2, 4, 8 or 16 wavefronts each
+    # (R = 1500, 700, 300, 100); the counts are the same integer sums
+    announce("pi wide", R, rng)
+    N = 65537
+    ctx = mrip.Context(mrip.MRIP_PI, mrip.pi_params(N), WAVE)
+    ctx.set_rng(mrip.MRIP_RNG_PHILOX if rng == "philox" else mrip.MRIP_RNG_TAUS88)
+    ctx.run(R, seed=31)
+    ref = core.pi_many(31, R, N, threads=core.default_threads(), rng=rng)
+    assert np.array_equal(ctx.output(0).cpu().numpy(), ref)
