@@ -74,8 +74,9 @@ def parse():
 
 def mapping_counters(mrip):
     """The random walk (1024 x 64 walkers x 1000 steps, the paper's model for
-    its TLP vs WLP memory-access table) and the forest fire (256 x 128^2 x 200)
-    once in each mapping, so that a counter run sees one launch of each."""
+    its TLP vs WLP memory-access table), the forest fire (256 x 128^2 x 200)
+    and the M/M/1 workload once in each mapping, so that a counter run sees
+    one launch of each."""
     maps = (("simt", mrip.MRIP_MAP_SIMT), ("lane0", mrip.MRIP_MAP_LANE0),
             ("wave", mrip.MRIP_MAP_WAVE))
     out = {}
@@ -87,6 +88,14 @@ def mapping_counters(mrip):
         ctx = mrip.Context(mrip.MRIP_FF, mrip.ff_params(128, 200, 0.01, 1e-5), mp)
         ctx.run(256, seed=42)
         out["ff_" + name] = ctx.last_ms()
+    # the headline M/M/1 workload in its three forms (one-lane: 1e4 customers)
+    for name, mp, n in (("simt", mrip.MRIP_MAP_SIMT, N), ("lane0", mrip.MRIP_MAP_LANE0, 10000),
+                        ("wave", mrip.MRIP_MAP_WAVE, N)):
+        ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, n), mp)
+        if mp == mrip.MRIP_MAP_WAVE:
+            ctx.set_split(SPLIT)
+        ctx.run(R, seed=42)
+        out["mm1_" + name] = ctx.last_ms()
     print(json.dumps({"mapping_counters_kernel_ms": out}), flush=True)
 
 
