@@ -167,8 +167,12 @@ MRIP_API mrip_status mrip_create(mrip_ctx *out, mrip_model model, const void *pa
                         mrip_mapping mapping);
 MRIP_API void mrip_destroy(mrip_ctx ctx);
 
-/* WAVE launch shape: replications per wavefront (1, 2 or 4) and workgroup
- * size (64, 256 or 1024). Outputs do not depend on it. Defaults 1 and 256. */
+/* WAVE launch shape: replications per wavefront (1, 2 or 4; M/M/1 only)
+ * and workgroup size (64, 256 or 1024) of the one-wavefront-per-replication
+ * kernels. Outputs do not depend on it. Defaults 1 and 256. Runs of few
+ * replications use workgroup-per-replication forms instead, whose size the
+ * model fixes: the walk up to 2048 replications (16 lanes per walker), pi
+ * below 4096 replications of at least 65536 points (2 to 16 wavefronts). */
 MRIP_API mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t reps_per_wave, uint32_t workgroup);
 
 /* Wavefronts per replication for mrip_run on an M/M/1 WAVE context: 1, 2,
@@ -178,9 +182,11 @@ MRIP_API mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t reps_per_wave, uint32
  * at once re-runs its leading chunks from the carry its predecessor ended
  * with until the two trajectories meet (Lindley's recursion forgets its
  * start once the queue empties), and, in order, a part whose predecessor
- * never met corrects again from that part's true end. Per-customer values
- * are those of the unsplit run; the means differ only by fp32 summation
- * order. */
+ * never met corrects again from that part's true end. On Philox streams the
+ * per-customer values are those of the unsplit run and the means differ
+ * only by fp32 summation order; on taus88 streams (at most 4) each lane
+ * takes a run of N / (64 split) customers, so values agree to fp32
+ * rounding. */
 MRIP_API mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep);
 
 /* Stream source of mrip_run (see mrip_rng). TAUS88 is defined for the
@@ -201,8 +207,8 @@ MRIP_API mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng);
 MRIP_API mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_stream);
 
 /* Mean, unbiased variance and Student-t interval of output `output` of the
- * last run (paper section 1). Synchronises the stream of that run.
- * MRIP_E_TOO_FEW if fewer than two replications. */
+ * last run (paper section 1). Waits for that run's reduction (an event on
+ * its stream). MRIP_E_TOO_FEW if fewer than two replications. */
 MRIP_API mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence, mrip_stats_t *out);
 
 /* The same for the run `back` runs before the last one (0 = the last, at
