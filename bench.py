@@ -258,6 +258,7 @@ def extras(torch, mrip, inputs):
 
     out["cv_1e5"] = cv_experiment(mrip, inputs, 100000)
     out["cv_1e4"] = cv_experiment(mrip, inputs, 10000)
+    out["cv_2e3"] = cv_experiment(mrip, inputs, 2000)  # prefix = half the run
 
     # the second generator (taus88 with Random Spacing): the same replications
     # on both generators, their kernel times and the z-score of the difference
