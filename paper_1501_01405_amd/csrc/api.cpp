@@ -71,6 +71,10 @@ mrip_status ensure_events(mrip_ctx c) {
   for (uint32_t i = 0; i < mrip_ctx_s::STATS_RING; ++i)
     if (!c->ev_stats[i])
       HIP_TRY(c, hipEventCreateWithFlags(&c->ev_stats[i], hipEventDisableTiming));
+  for (uint32_t i = 0; i < 2; ++i)
+    if (!c->ev_set_free[i])
+      HIP_TRY(c, hipEventCreateWithFlags(&c->ev_set_free[i], hipEventDisableTiming));
+  if (!c->red_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->red_stream, hipStreamNonBlocking));
   if (!c->stats_host) {
     const size_t bytes = sizeof(double) * mrip_ctx_s::STATS_RING * mrip_ctx_s::STATS_SLOT;
     HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, bytes, hipHostMallocMapped));
@@ -83,6 +87,13 @@ mrip_status ensure_events(mrip_ctx c) {
 double *next_stats_slot(mrip_ctx c) {
   const uint32_t slot = (uint32_t)(c->stats_runs % mrip_ctx_s::STATS_RING);
   return c->stats_view + (size_t)slot * mrip_ctx_s::STATS_SLOT;
+}
+
+// Before a run on stream s writes output set `set`: wait for the reduction
+// that may still be reading it.
+mrip_status claim_set(mrip_ctx c, uint32_t set, hipStream_t s) {
+  if (c->set_pending[set]) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_set_free[set], 0));
+  return MRIP_OK;
 }
 
 // Mark the slot written by the reduction just enqueued on s.
@@ -119,8 +130,9 @@ mrip_status last_launch_ms(mrip_ctx c, float *ms) {
 }
 
 // Device buffer for output o of a run over n items: the caller's bound
-// buffer when there is one (it must hold `need` bytes), else the context's.
-mrip_status output_buffer(mrip_ctx c, uint32_t o, uint64_t need, void **p) {
+// buffer when there is one (it must hold `need` bytes), else the context's
+// buffer of output set `set`.
+mrip_status output_buffer(mrip_ctx c, uint32_t set, uint32_t o, uint64_t need, void **p) {
   if (c->bound[o].p) {
     if (c->bound[o].bytes < need) {
       c->err = "bound output " + std::to_string(o) + " is smaller than the run's output";
@@ -128,8 +140,8 @@ mrip_status output_buffer(mrip_ctx c, uint32_t o, uint64_t need, void **p) {
     }
     *p = c->bound[o].p;
   } else {
-    HIP_TRY(c, c->out[o].ensure(need));
-    *p = c->out[o].p;
+    HIP_TRY(c, c->out[set][o].ensure(need));
+    *p = c->out[set][o].p;
   }
   c->cur[o] = *p;
   return MRIP_OK;
@@ -255,6 +267,7 @@ mrip_status mrip_create(mrip_ctx *out, mrip_model model, const void *params,
 void mrip_destroy(mrip_ctx ctx) {
   if (!ctx) return;
   if (ctx->last_stream) (void)hipStreamSynchronize(ctx->last_stream);
+  if (ctx->red_stream) (void)hipStreamSynchronize(ctx->red_stream);
   delete ctx;
 }
 
@@ -326,9 +339,17 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
   const uint32_t nout = scalar_outputs(ctx->model);
+  // With the outputs in the context's buffers, the reduction runs on the
+  // library's own stream, so the next run's simulation need not wait for
+  // it: runs alternate between two output sets.
+  bool overlap = true;
+  for (uint32_t o = 0; o < 4; ++o) overlap = overlap && !ctx->bound[o].p;
+  const uint32_t set = overlap ? ctx->next_set : 0u;
+  st = claim_set(ctx, set, s);
+  if (st != MRIP_OK) return st;
   void *outp[4] = {};
   for (uint32_t o = 0; o < nout; ++o) {
-    st = output_buffer(ctx, o, n_reps * 4, &outp[o]);
+    st = output_buffer(ctx, set, o, n_reps * 4, &outp[o]);
     if (st != MRIP_OK) return st;
   }
   const bool wave = ctx->mapping == MRIP_MAP_WAVE;
@@ -367,7 +388,7 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.rng = ctx->rng;
     a.taus = ctx->taus_tables.as<uint32_t>();
     if (a.feature_prefix > 0) {
-      st = output_buffer(ctx, 3, n_reps * 40, &outp[3]);
+      st = output_buffer(ctx, set, 3, n_reps * 40, &outp[3]);
       if (st != MRIP_OK) return st;
       a.features = (float *)outp[3];
     }
@@ -406,14 +427,27 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   if (st != MRIP_OK) return st;
   // all scalar outputs in one reduction launch, written straight into
   // pinned host memory, so mrip_stats only waits for an event
-  ReduceSet set{};
+  ReduceSet rs{};
   for (uint32_t o = 0; o < nout; ++o) {
-    set.x[o] = outp[o];
-    set.dtype[o] = output_dtype(ctx->model, o);
+    rs.x[o] = outp[o];
+    rs.dtype[o] = output_dtype(ctx->model, o);
   }
-  HIP_TRY(ctx, launch_reduce_f64_multi(set, nout, n_reps, next_stats_slot(ctx), s));
-  st = commit_stats_slot(ctx, s);
+  hipStream_t rstream = s;
+  if (overlap) {
+    // the reduction waits for this run's simulation (the event just
+    // recorded after it) on the library's stream
+    const uint32_t slot = (uint32_t)((ctx->launches - 1) % mrip_ctx_s::RING);
+    rstream = ctx->red_stream;
+    HIP_TRY(ctx, hipStreamWaitEvent(rstream, ctx->ring1[slot], 0));
+  }
+  HIP_TRY(ctx, launch_reduce_f64_multi(rs, nout, n_reps, next_stats_slot(ctx), rstream));
+  st = commit_stats_slot(ctx, rstream);
   if (st != MRIP_OK) return st;
+  if (overlap) {
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_set_free[set], rstream));
+    ctx->set_pending[set] = true;
+    ctx->next_set = set ^ 1u;
+  }
   ctx->last = RUN_UNIFORM;
   ctx->last_n = n_reps;
   ctx->last_stream = s;
@@ -562,16 +596,18 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
                                  uint32_t split, bool reduce) {
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
+  st = claim_set(ctx, 0, s);
+  if (st != MRIP_OK) return st;
   void *outp[4] = {};
   for (uint32_t o = 0; o < 3; ++o) {
-    st = output_buffer(ctx, o, ctx->n_items * 4, &outp[o]);
+    st = output_buffer(ctx, 0, o, ctx->n_items * 4, &outp[o]);
     if (st != MRIP_OK) return st;
   }
   Mm1Args a{};
   a.seed = seed;
   a.feature_prefix = ctx->mm1.feature_prefix;
   if (a.feature_prefix > 0) {
-    st = output_buffer(ctx, 3, ctx->n_items * 40, &outp[3]);
+    st = output_buffer(ctx, 0, 3, ctx->n_items * 40, &outp[3]);
     if (st != MRIP_OK) return st;
     a.features = (float *)outp[3];
   }

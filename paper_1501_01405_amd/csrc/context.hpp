@@ -93,7 +93,13 @@ struct mrip_ctx_s {
   int rng = MRIP_RNG_PHILOX;
   mrip::DevBuf taus_tables;
 
-  mrip::DevBuf out[4];
+  // Two sets of output buffers: a uniform run writes one while the
+  // reduction of the run before it, on red_stream, still reads the other.
+  mrip::DevBuf out[2][4];
+  uint32_t next_set = 0;                 // output set of the next uniform run
+  bool set_pending[2] = {};              // a reduction may still read set i
+  hipEvent_t ev_set_free[2] = {};        // recorded after that reduction
+  hipStream_t red_stream = nullptr;      // the library's stream for reductions
   // caller-owned output buffers (mrip_bind_output) and the buffers the last
   // run wrote (bound or owned)
   struct Bound {
@@ -135,6 +141,9 @@ struct mrip_ctx_s {
     if (stats_host) (void)hipHostFree(stats_host);
     for (uint32_t i = 0; i < STATS_RING; ++i)
       if (ev_stats[i]) (void)hipEventDestroy(ev_stats[i]);
+    for (uint32_t i = 0; i < 2; ++i)
+      if (ev_set_free[i]) (void)hipEventDestroy(ev_set_free[i]);
+    if (red_stream) (void)hipStreamDestroy(red_stream);
     for (uint32_t i = 0; i < RING; ++i) {
       if (ring0[i]) (void)hipEventDestroy(ring0[i]);
       if (ring1[i]) (void)hipEventDestroy(ring1[i]);
