@@ -304,8 +304,8 @@ def extras(torch, mrip, inputs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(replications shard trivially; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (replications "
+              "would shard by id ranges, with one all-gather of outputs)", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -53,7 +53,7 @@ typedef enum {
   MRIP_E_HIP = -3,         /* a HIP runtime call failed                       */
   MRIP_E_STATE = -4,       /* call out of order (e.g. stats before any run)   */
   MRIP_E_TOO_FEW = -5,     /* fewer than two replications for an interval     */
-  MRIP_E_UNSUPPORTED = -6  /* valid request this build does not implement     */
+  MRIP_E_UNSUPPORTED = -6  /* valid request the library does not implement    */
 } mrip_status;
 
 typedef enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3, MRIP_PI = 4 } mrip_model;
