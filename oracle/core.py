@@ -34,9 +34,11 @@ def lib():
         L.oracle_rw_direction.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
         L.oracle_rw_direction.restype = C.c_int
         L.oracle_rw.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
-                                C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+                                C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int64)]
         L.oracle_rw_injected.argtypes = [u8p, C.c_uint32, C.c_uint32, C.c_uint32,
-                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64)]
         L.oracle_mm1.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_float,
                                  C.c_float, C.c_uint64, f32p, C.c_void_p]
         L.oracle_mm1_injected.argtypes = [f32p, f32p, C.c_uint64, C.c_void_p, C.c_void_p,
@@ -106,38 +108,42 @@ def rw_direction(seed, rep, walker, t):
     return lib().oracle_rw_direction(seed, rep, walker, t)
 
 
-def rw(seed, rep, walkers=64, grid=64, steps=1000):
-    """(ssd, distinct) of one random-walk replication."""
-    s, d = C.c_int64(), C.c_int64()
-    _check(lib().oracle_rw(seed, rep, walkers, grid, steps, C.byref(s), C.byref(d)), "rw")
-    return s.value, d.value
+def rw(seed, rep, walkers=64, grid=64, steps=1000, walker_sites=False):
+    """(ssd, distinct) of one random-walk replication, and the per-walker
+    site count sum when walker_sites."""
+    s, d, v = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().oracle_rw(seed, rep, walkers, grid, steps, C.byref(s), C.byref(d),
+                           C.byref(v)), "rw")
+    return (s.value, d.value, v.value) if walker_sites else (s.value, d.value)
 
 
-def rw_injected(dirs):
+def rw_injected(dirs, walker_sites=False):
     """dirs: (walkers, steps) array of moves 0..3 on a 64x64 torus."""
     dirs = np.ascontiguousarray(dirs, dtype=np.uint8)
     w, t = dirs.shape
-    s, d = C.c_int64(), C.c_int64()
-    _check(lib().oracle_rw_injected(dirs.reshape(-1), w, 64, t, C.byref(s), C.byref(d)),
-           "rw_injected")
-    return s.value, d.value
+    s, d, v = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().oracle_rw_injected(dirs.reshape(-1), w, 64, t, C.byref(s), C.byref(d),
+                                    C.byref(v)), "rw_injected")
+    return (s.value, d.value, v.value) if walker_sites else (s.value, d.value)
 
 
-def rw_taus(seed, rep, walkers=64, grid=64, steps=1000):
-    """(ssd, distinct) of one replication on its taus88 stream."""
-    s, d = C.c_int64(), C.c_int64()
-    _check(lib().oracle_rw_taus(seed, rep, walkers, grid, steps, C.byref(s), C.byref(d)),
-           "rw_taus")
-    return s.value, d.value
+def rw_taus(seed, rep, walkers=64, grid=64, steps=1000, walker_sites=False):
+    """rw() on the replication's taus88 stream."""
+    s, d, v = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().oracle_rw_taus(seed, rep, walkers, grid, steps, C.byref(s), C.byref(d),
+                                C.byref(v)), "rw_taus")
+    return (s.value, d.value, v.value) if walker_sites else (s.value, d.value)
 
 
-def rw_many(seed, reps, walkers=64, grid=64, steps=1000, threads=1, rng="philox"):
-    """Outputs (ssd[R], distinct[R]) for replications 0..reps-1 (or an id list)."""
+def rw_many(seed, reps, walkers=64, grid=64, steps=1000, threads=1, rng="philox",
+            walker_sites=False):
+    """Outputs (ssd[R], distinct[R]) for replications 0..reps-1 (or an id
+    list), and walker_sites[R] when requested."""
     ids = list(range(reps)) if isinstance(reps, int) else list(reps)
     one = rw if rng == "philox" else rw_taus
-    res = _map(lambda r: one(seed, r, walkers, grid, steps), ids, threads)
-    return (np.array([a for a, _ in res], dtype=np.int64),
-            np.array([b for _, b in res], dtype=np.int64))
+    res = _map(lambda r: one(seed, r, walkers, grid, steps, True), ids, threads)
+    out = tuple(np.array([x[i] for x in res], dtype=np.int64) for i in range(3))
+    return out if walker_sites else out[:2]
 
 
 # ---------------------------------------------------------------- M/M/1

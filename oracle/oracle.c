@@ -107,7 +107,9 @@ EXPORT float oracle_exp_variate(uint32_t x, float rate) {
 /* w in replication r takes 2 bits of Philox block (t>>6, w, r, TAG_RW):     */
 /* word (t>>4)&3, bits 2*(t&15)..+1. 0:+x 1:-x 2:+y 3:-y.                    */
 /* Outputs: ssd = sum over walkers of the squared unwrapped displacement;   */
-/* distinct = number of lattice sites visited by any walker (starts incl.). */
+/* distinct = number of lattice sites visited by any walker (starts incl.); */
+/* walker_sites = sum over walkers of the number of sites each one visited  */
+/* (its start included).                                                    */
 /* ------------------------------------------------------------------------ */
 EXPORT int oracle_rw_direction(uint64_t seed, uint32_t rep, uint32_t walker, uint32_t t) {
   uint32_t blk[4];
@@ -116,17 +118,26 @@ EXPORT int oracle_rw_direction(uint64_t seed, uint32_t rep, uint32_t walker, uin
 }
 
 /* Core walk over an explicit direction source: dirs == NULL draws from
- * Philox, else dirs[w * T + t] gives the move. Returns 0 on success. */
+ * Philox, else dirs[w * T + t] gives the move. walker_sites_out may be
+ * NULL. Returns 0 on success. */
 static int rw_core(uint64_t seed, uint32_t rep, uint32_t W, uint32_t L, uint32_t T,
-                   const uint8_t *dirs, int64_t *ssd_out, int64_t *distinct_out) {
+                   const uint8_t *dirs, int64_t *ssd_out, int64_t *distinct_out,
+                   int64_t *walker_sites_out) {
   uint8_t *visited = (uint8_t *)calloc((size_t)L * L, 1);
-  if (!visited) return -1;
-  int64_t ssd = 0;
+  uint8_t *mine = (uint8_t *)calloc((size_t)L * L, 1);  /* this walker's sites */
+  if (!visited || !mine) {
+    free(visited);
+    free(mine);
+    return -1;
+  }
+  int64_t ssd = 0, walker_sites = 0;
   for (uint32_t w = 0; w < W; ++w) {
     int64_t x = ((w % 8u) * (L / 8u) + L / 16u) % L;
     int64_t y = ((w / 8u) * (L / 8u) + L / 16u) % L;
     int64_t ux = 0, uy = 0;
+    memset(mine, 0, (size_t)L * L);
     visited[y * L + x] = 1;
+    mine[y * L + x] = 1;
     for (uint32_t t = 0; t < T; ++t) {
       int d = dirs ? (int)dirs[(size_t)w * T + t] : oracle_rw_direction(seed, rep, w, t);
       int64_t dx = 0, dy = 0;
@@ -139,25 +150,30 @@ static int rw_core(uint64_t seed, uint32_t rep, uint32_t W, uint32_t L, uint32_t
       x = (x + dx + L) % L;
       y = (y + dy + L) % L;
       visited[y * L + x] = 1;
+      mine[y * L + x] = 1;
     }
     ssd += ux * ux + uy * uy;
+    for (size_t i = 0; i < (size_t)L * L; ++i) walker_sites += mine[i];
   }
   int64_t distinct = 0;
   for (size_t i = 0; i < (size_t)L * L; ++i) distinct += visited[i];
   free(visited);
+  free(mine);
   *ssd_out = ssd;
   *distinct_out = distinct;
+  if (walker_sites_out) *walker_sites_out = walker_sites;
   return 0;
 }
 
 EXPORT int oracle_rw(uint64_t seed, uint32_t rep, uint32_t walkers, uint32_t grid,
-                     uint32_t steps, int64_t *ssd, int64_t *distinct) {
-  return rw_core(seed, rep, walkers, grid, steps, NULL, ssd, distinct);
+                     uint32_t steps, int64_t *ssd, int64_t *distinct, int64_t *walker_sites) {
+  return rw_core(seed, rep, walkers, grid, steps, NULL, ssd, distinct, walker_sites);
 }
 
 EXPORT int oracle_rw_injected(const uint8_t *dirs, uint32_t walkers, uint32_t grid,
-                              uint32_t steps, int64_t *ssd, int64_t *distinct) {
-  return rw_core(0, 0, walkers, grid, steps, dirs, ssd, distinct);
+                              uint32_t steps, int64_t *ssd, int64_t *distinct,
+                              int64_t *walker_sites) {
+  return rw_core(0, 0, walkers, grid, steps, dirs, ssd, distinct, walker_sites);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -436,7 +452,8 @@ EXPORT int64_t oracle_pi_taus(uint64_t seed, uint32_t rep, uint64_t points) {
 }
 
 EXPORT int oracle_rw_taus(uint64_t seed, uint32_t rep, uint32_t walkers, uint32_t grid,
-                          uint32_t steps, int64_t *ssd, int64_t *distinct) {
+                          uint32_t steps, int64_t *ssd, int64_t *distinct,
+                          int64_t *walker_sites) {
   uint8_t *dirs = (uint8_t *)malloc((size_t)walkers * steps + 1);
   if (!dirs) return -1;
   uint32_t st[3];
@@ -449,7 +466,7 @@ EXPORT int oracle_rw_taus(uint64_t seed, uint32_t rep, uint32_t walkers, uint32_
         dirs[(size_t)w * steps + t] = (uint8_t)((word >> (2u * (t & 15u))) & 3u);
     }
   }
-  int rc = rw_core(0, 0, walkers, grid, steps, dirs, ssd, distinct);
+  int rc = rw_core(0, 0, walkers, grid, steps, dirs, ssd, distinct, walker_sites);
   free(dirs);
   return rc;
 }

@@ -3,7 +3,10 @@
 Independent facts used: the unbiased lattice walk has mean-square
 displacement exactly t; the squared displacement has the parity of t; the
 exact distribution of visited sites for short walks comes from enumerating
-all 4^T paths; hand-traced paths, including one that wraps the torus.
+all 4^T paths; hand-traced paths, including one that wraps the torus. The
+per-walker site counts: one walker's count is the union's; with several
+walkers it is the sum of the union counts of each walker's moves run alone
+(the count of a path does not depend on where it starts on the torus).
 """
 import itertools
 import math
@@ -104,3 +107,35 @@ def test_exact_distribution_by_enumeration():
     dof = len(dist) - 1
     assert chi2 < dof + 6 * math.sqrt(2 * dof)
     assert abs(np.mean(sds) - T) < 4 * np.std(sds) / math.sqrt(R)
+
+
+def test_walker_sites_hand_traced():
+    # two walkers: a 6-site path and a back-and-forth on one edge
+    dirs = np.array([[0, 0, 2, 1, 3, 3], [0, 1, 0, 1, 0, 1]])
+    s, d, v = core.rw_injected(dirs, walker_sites=True)
+    assert v == 6 + 2
+    assert d == 8  # the two walkers start on different lattice points
+    # one walker: the per-walker count is the union count
+    for moves in ([0, 0, 2, 1, 3, 3], [3] * 70, [0] * 64):
+        s, d, v = core.rw_injected(np.array([moves]), walker_sites=True)
+        assert v == d
+
+
+def test_walker_sites_is_the_sum_of_single_walker_runs():
+    rng = np.random.default_rng(4)
+    for W, T in ((5, 37), (64, 200), (17, 1)):
+        dirs = rng.integers(0, 4, (W, T)).astype(np.uint8)
+        _, _, v = core.rw_injected(dirs, walker_sites=True)
+        assert v == sum(core.rw_injected(dirs[w:w + 1])[1] for w in range(W))
+
+
+def test_walker_sites_of_a_philox_run_agree_with_single_walkers():
+    # the Philox-driven oracle walk against its own moves injected walker by walker
+    seed, rep, W, T = 5, 3, 9, 150
+    _, _, v = core.rw(seed, rep, W, 64, T, walker_sites=True)
+    dirs = np.array([[core.rw_direction(seed, rep, w, t) for t in range(T)] for w in range(W)],
+                    np.uint8)
+    assert v == sum(core.rw_injected(dirs[w:w + 1])[1] for w in range(W))
+    ssd, distinct, vs = core.rw_many(seed, 40, 64, 64, 1000, threads=core.default_threads(),
+                                     walker_sites=True)
+    assert np.all(vs >= distinct) and np.all(vs <= 64 * 1001)

@@ -141,6 +141,8 @@ def test_rw_on_reference_stream():
             dirs[w, t] = (int(words[w * per + (t >> 4)]) >> (2 * (t & 15))) & 3
     # the injected walk on a 64 x 64 torus is pinned separately
     assert core.rw_taus(seed, rep, W, 64, T) == core.rw_injected(dirs)
+    _, _, v = core.rw_taus(seed, rep, W, 64, T, walker_sites=True)
+    assert v == sum(core.rw_injected(dirs[w:w + 1])[1] for w in range(W))
 
 
 def test_mm1_on_reference_stream():
