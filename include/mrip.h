@@ -95,11 +95,17 @@ typedef enum {
  * grid/16). Move t of walker w in replication r is 2 bits of block
  * (t>>6, w, r, 1): word (t>>4)&3, bits 2(t&15); 0:+x 1:-x 2:+y 3:-y.
  * Outputs: 0 = int32 sum of squared unwrapped displacements,
- *          1 = int32 number of distinct sites visited (starts included).
+ *          1 = int32 number of distinct sites visited (starts included),
+ *          2 = when walker_sites != 0, int32 sum over walkers of the
+ *              number of sites each one visited (its start included): the
+ *              union count nearly fills the torus, this one does not.
+ *              Costs a bitmap per walker in device memory (WAVE: walkers *
+ *              grid^2 / 8 bytes per replication) and its updates.
  * Requires walkers * steps^2 < 2^31. */
 typedef struct {
   uint32_t size;
   uint32_t walkers, grid, steps;
+  uint32_t walker_sites; /* 0 or 1 */
 } mrip_rw_params;
 
 /* M/M/1 queue (paper section 5.1, second model), starting empty. Customer n

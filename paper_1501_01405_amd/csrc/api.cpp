@@ -42,8 +42,9 @@ mrip_status inval(mrip_ctx c, const char *why) {
     if (_e != hipSuccess) return hip_fail((ctx), _e, #expr); \
   } while (0)
 
-uint32_t scalar_outputs(mrip_model m) {
-  return m == MRIP_RW ? 2 : m == MRIP_MM1 ? 3 : m == MRIP_PI ? 2 : 1;
+uint32_t scalar_outputs(mrip_ctx c) {
+  const mrip_model m = c->model;
+  return m == MRIP_RW ? (c->rw.walker_sites ? 3 : 2) : m == MRIP_MM1 ? 3 : m == MRIP_PI ? 2 : 1;
 }
 
 // dtype of scalar output o for the reduction kernel: 0 = int32, 1 = fp32
@@ -188,6 +189,7 @@ mrip_status validate(mrip_model model, const void *params, mrip_mapping map, std
     if (!is_pow2_grid(p->grid)) return why = "grid must be 16, 32, 64 or 128", MRIP_E_INVAL;
     if ((double)p->walkers * (double)p->steps * (double)p->steps >= 2147483648.0)
       return why = "walkers * steps^2 must be < 2^31", MRIP_E_INVAL;
+    if (p->walker_sites > 1) return why = "walker_sites must be 0 or 1", MRIP_E_INVAL;
     return MRIP_OK;
   }
   if (model == MRIP_MM1) {
@@ -338,7 +340,7 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   hipStream_t s = (hipStream_t)hip_stream;
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
-  const uint32_t nout = scalar_outputs(ctx->model);
+  const uint32_t nout = scalar_outputs(ctx);
   // With the outputs in the context's buffers, the reduction runs on the
   // library's own stream, so the next run's simulation need not wait for
   // it: runs alternate between two output sets.
@@ -367,8 +369,27 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.distinct = (int32_t *)outp[1];
     a.rng = ctx->rng;
     a.taus = ctx->taus_tables.as<uint32_t>();
+    uint64_t chunk = n_reps;  // replications per launch
+    if (ctx->rw.walker_sites) {
+      const uint64_t bytes = (uint64_t)a.grid * a.grid / 8;  // one bitmap
+      const uint64_t per_rep = wave ? a.walkers * bytes : bytes;
+      // WAVE keeps a bitmap per walker: launch at most WALKER_SCRATCH_MAX
+      // bytes' worth of replications at a time (each launch reuses them)
+      if (wave) chunk = std::max<uint64_t>(1, std::min(n_reps, WALKER_SCRATCH_MAX / per_rep));
+      HIP_TRY(ctx, ctx->walker_scratch.ensure(chunk * per_rep));
+      a.walker_bitmaps = ctx->walker_scratch.as<uint32_t>();
+      a.walker_sites = (int32_t *)outp[2];
+    }
     if (wave) {
-      HIP_TRY(ctx, launch_rw_wave(a, ctx->wg, s));
+      for (uint64_t r0 = 0; r0 < n_reps; r0 += chunk) {
+        RwArgs b = a;
+        b.rep0 = r0;
+        b.n_reps = std::min(chunk, n_reps - r0);
+        b.ssd += r0;
+        b.distinct += r0;
+        if (b.walker_sites) b.walker_sites += r0;
+        HIP_TRY(ctx, launch_rw_wave(b, ctx->wg, s));
+      }
     } else {
       HIP_TRY(ctx, ctx->scratch.ensure(n_reps * (uint64_t)a.grid * a.grid / 8));
       a.scratch_bitmaps = ctx->scratch.as<uint32_t>();
@@ -459,7 +480,7 @@ mrip_status mrip_stats_back(mrip_ctx ctx, uint32_t back, uint32_t output, double
   if (!ctx || !out) return MRIP_E_INVAL;
   if (!(confidence > 0.0 && confidence < 1.0)) return inval(ctx, "confidence must be in (0, 1)");
   if (ctx->last == RUN_NONE || ctx->stats_runs == 0) return (ctx->err = "no run yet"), MRIP_E_STATE;
-  if (output >= scalar_outputs(ctx->model)) return inval(ctx, "no such scalar output");
+  if (output >= scalar_outputs(ctx)) return inval(ctx, "no such scalar output");
   if (back >= mrip_ctx_s::STATS_RING || back >= ctx->stats_runs)
     return (ctx->err = "no statistics kept for that run"), MRIP_E_STATE;
   const uint32_t slot = (uint32_t)((ctx->stats_runs - 1 - back) % mrip_ctx_s::STATS_RING);
@@ -480,7 +501,7 @@ mrip_status mrip_output_ptr(mrip_ctx ctx, uint32_t output, const void **ptr) {
   if (!ctx || !ptr) return MRIP_E_INVAL;
   if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
   const bool feat = ctx->model == MRIP_MM1 && output == 3 && ctx->mm1.feature_prefix > 0;
-  if (output >= scalar_outputs(ctx->model) && !feat) return inval(ctx, "no such output");
+  if (output >= scalar_outputs(ctx) && !feat) return inval(ctx, "no such output");
   *ptr = ctx->cur[output];
   return MRIP_OK;
 }
@@ -490,7 +511,7 @@ mrip_status mrip_outputs(mrip_ctx ctx, uint32_t output, void *dst, uint64_t byte
   if (!ctx || !dst) return MRIP_E_INVAL;
   if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
   const bool feat = ctx->model == MRIP_MM1 && output == 3 && ctx->mm1.feature_prefix > 0;
-  if (output >= scalar_outputs(ctx->model) && !feat) return inval(ctx, "no such output");
+  if (output >= scalar_outputs(ctx) && !feat) return inval(ctx, "no such output");
   const uint64_t need = ctx->last_n * (feat ? 40 : 4);
   if (bytes < need) return inval(ctx, "destination too small");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
@@ -704,7 +725,7 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
 mrip_status mrip_bind_output(mrip_ctx ctx, uint32_t output, void *ptr_dev, uint64_t bytes) {
   if (!ctx) return MRIP_E_INVAL;
   const bool feat = ctx->model == MRIP_MM1 && output == 3;
-  if (output >= scalar_outputs(ctx->model) && !feat) return inval(ctx, "no such output");
+  if (output >= scalar_outputs(ctx) && !feat) return inval(ctx, "no such output");
   if (ptr_dev && (bytes == 0 || ((uintptr_t)ptr_dev & 3u)))
     return inval(ctx, "a bound output needs a non-empty, 4-byte aligned buffer");
   ctx->bound[output].p = ptr_dev;

@@ -26,7 +26,17 @@ struct RwArgs {
   uint32_t *scratch_bitmaps;  // SIMT only: n_reps * grid*grid/32 words
   int rng;
   const uint32_t *taus;
+  // per-walker site counts (nullptr = off): output and the walkers' own
+  // bitmaps (WAVE: n_reps * walkers * grid*grid/32 words, SIMT: n_reps *
+  // grid*grid/32)
+  int32_t *walker_sites;
+  uint32_t *walker_bitmaps;
+  // replication id of output 0: outputs and bitmaps are indexed from 0,
+  // random streams by rep0 + index
+  uint64_t rep0;
 };
+// device bytes of per-walker bitmaps one WAVE launch may use
+constexpr uint64_t WALKER_SCRATCH_MAX = 1ull << 30;
 hipError_t launch_rw_wave(const RwArgs &a, uint32_t workgroup, hipStream_t s);
 // one_lane: one working lane per wavefront (the paper's WLP form)
 hipError_t launch_rw_simt(const RwArgs &a, bool one_lane, hipStream_t s);

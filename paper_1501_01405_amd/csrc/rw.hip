@@ -14,6 +14,9 @@
 // segment from there, marking the sites. Both forms give identical outputs;
 // the launcher picks by the number of replications.
 //
+// Optionally (PW) every walker also marks a bitmap of its own, in global
+// memory, and output 2 is the sum over walkers of their popcounts.
+//
 // SIMT mapping: one replication per lane; the lane walks its walkers one
 // after the other and keeps the replication's bitmap in global memory, the
 // per-thread state the paper's thread-per-replication form implies. The
@@ -39,9 +42,19 @@ __device__ __forceinline__ void step_delta(uint32_t d, int &dx, int &dy) {
 // Set the visited bit of lattice site c (row-major) in an LDS bitmap.
 __device__ __forceinline__ void mark(uint32_t *bm, int c) { atomicOr(&bm[c >> 5], 1u << (c & 31)); }
 
-template <int GRID, bool LDS>
+// Walker bitmap modes: none, owned by this lane (plain read-modify-write),
+// shared by the walker's segment lanes (global atomic or).
+enum : int { WB_NONE = 0, WB_OWN = 1, WB_SHARED = 2 };
+
+template <int WB>
+__device__ __forceinline__ void mark_walker(uint32_t *wb, int c, bool active) {
+  if (WB == WB_OWN && active) wb[c >> 5] |= 1u << (c & 31);
+  if (WB == WB_SHARED && active) atomicOr(&wb[c >> 5], 1u << (c & 31));
+}
+
+template <int GRID, bool LDS, int WB>
 __device__ __forceinline__ void move1(uint32_t d, bool active, int &x, int &y, int &ux, int &uy,
-                                      uint32_t *bm) {
+                                      uint32_t *bm, uint32_t *wb) {
   int dx, dy;
   step_delta(d, dx, dy);
   ux += dx;
@@ -54,25 +67,29 @@ __device__ __forceinline__ void move1(uint32_t d, bool active, int &x, int &y, i
   } else {
     bm[c >> 5] |= 1u << (c & 31);
   }
+  mark_walker<WB>(wb, c, active);
 }
 
 // Up to 16 moves from one 32-bit word (2 bits each, lowest first): moves
 // g .. min(g + 16, steps) - 1.
-template <int GRID, bool LDS>
+template <int GRID, bool LDS, int WB = WB_NONE>
 __device__ __forceinline__ void walk16(uint32_t word, uint32_t g, uint32_t steps, bool active,
-                                       int &x, int &y, int &ux, int &uy, uint32_t *bm) {
+                                       int &x, int &y, int &ux, int &uy, uint32_t *bm,
+                                       uint32_t *wb = nullptr) {
   if (g + 16u <= steps) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) move1<GRID, LDS>((word >> (2 * i)) & 3u, active, x, y, ux, uy, bm);
+    for (int i = 0; i < 16; ++i)
+      move1<GRID, LDS, WB>((word >> (2 * i)) & 3u, active, x, y, ux, uy, bm, wb);
   } else {
     for (uint32_t i = 0; g + i < steps; ++i)
-      move1<GRID, LDS>((word >> (2 * i)) & 3u, active, x, y, ux, uy, bm);
+      move1<GRID, LDS, WB>((word >> (2 * i)) & 3u, active, x, y, ux, uy, bm, wb);
   }
 }
 
-template <int GRID, int RNG>
+template <int GRID, int RNG, bool PW>
 __global__ void rw_wave_kernel(RwArgs a) {
   constexpr int WORDS = GRID * GRID / 32;
+  constexpr int WB = PW ? WB_OWN : WB_NONE;
   extern __shared__ uint32_t lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t r = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
@@ -87,19 +104,26 @@ __global__ void rw_wave_kernel(RwArgs a) {
   int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
   int ux = 0, uy = 0;
   if (active) mark(bm, y * GRID + x);
+  // this walker's own bitmap (global memory, owned by this lane)
+  uint32_t *wb = nullptr;
+  if (PW && active) {
+    wb = a.walker_bitmaps + (r * a.walkers + w) * WORDS;
+    for (int i = 0; i < WORDS; ++i) wb[i] = 0u;
+    mark_walker<WB>(wb, y * GRID + x, true);
+  }
 
   if (RNG == RNG_TAUS88) {
-    Taus t = taus_seed(TAG_RW, 0u, (uint32_t)r, k0, k1);
+    Taus t = taus_seed(TAG_RW, 0u, (uint32_t)(a.rep0 + r), k0, k1);
     taus_skip(t, (uint64_t)w * ((a.steps + 15) / 16), a.taus);
     for (uint32_t g = 0; g < a.steps; g += 16)
-      walk16<GRID, true>(taus_next(t), g, a.steps, active, x, y, ux, uy, bm);
+      walk16<GRID, true, WB>(taus_next(t), g, a.steps, active, x, y, ux, uy, bm, wb);
   } else {
     for (uint32_t g = 0; g < a.steps; g += 64) {
-      const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
-      walk16<GRID, true>(b.x, g, a.steps, active, x, y, ux, uy, bm);
-      walk16<GRID, true>(b.y, g + 16, a.steps, active, x, y, ux, uy, bm);
-      walk16<GRID, true>(b.z, g + 32, a.steps, active, x, y, ux, uy, bm);
-      walk16<GRID, true>(b.w, g + 48, a.steps, active, x, y, ux, uy, bm);
+      const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
+      walk16<GRID, true, WB>(b.x, g, a.steps, active, x, y, ux, uy, bm, wb);
+      walk16<GRID, true, WB>(b.y, g + 16, a.steps, active, x, y, ux, uy, bm, wb);
+      walk16<GRID, true, WB>(b.z, g + 32, a.steps, active, x, y, ux, uy, bm, wb);
+      walk16<GRID, true, WB>(b.w, g + 48, a.steps, active, x, y, ux, uy, bm, wb);
     }
   }
   __syncthreads();
@@ -108,50 +132,67 @@ __global__ void rw_wave_kernel(RwArgs a) {
   cnt = group_sum_i(cnt, 64);
   const int sd = active ? ux * ux + uy * uy : 0;
   const int ssd = group_sum_i(sd, 64);
+  int mine = 0;
+  if (PW) {
+    if (active)
+      for (int i = 0; i < WORDS; ++i) mine += __popc(wb[i]);
+    mine = group_sum_i(mine, 64);
+  }
   if (lane == 0 && r < a.n_reps) {
     a.ssd[r] = ssd;
     a.distinct[r] = cnt;
+    if (PW) a.walker_sites[r] = mine;
   }
 }
 
 // STRIDE = 1: one replication per lane. STRIDE = 64: one replication per
 // wavefront with only its first lane working (the paper's WLP form, 63 of
 // 64 lanes idle).
-template <int GRID, int STRIDE, int RNG>
+template <int GRID, int STRIDE, int RNG, bool PW>
 __global__ void rw_simt_kernel(RwArgs a) {
   constexpr int WORDS = GRID * GRID / 32;
+  constexpr int WB = PW ? WB_OWN : WB_NONE;
   if (threadIdx.x % STRIDE) return;
   const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
   if (r >= a.n_reps) return;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   uint32_t *bm = a.scratch_bitmaps + r * WORDS;
   for (int i = 0; i < WORDS; ++i) bm[i] = 0u;
-  int ssd = 0;
+  // one walker bitmap per replication, cleared for every walker
+  uint32_t *wb = PW ? a.walker_bitmaps + r * WORDS : nullptr;
+  int ssd = 0, mine = 0;
   Taus t;
-  if (RNG == RNG_TAUS88) t = taus_seed(TAG_RW, 0u, (uint32_t)r, k0, k1);
+  if (RNG == RNG_TAUS88) t = taus_seed(TAG_RW, 0u, (uint32_t)(a.rep0 + r), k0, k1);
   for (uint32_t w = 0; w < a.walkers; ++w) {
     int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
     int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
     int ux = 0, uy = 0;
     bm[(y * GRID + x) >> 5] |= 1u << ((y * GRID + x) & 31);
+    if (PW) {
+      for (int i = 0; i < WORDS; ++i) wb[i] = 0u;
+      mark_walker<WB>(wb, y * GRID + x, true);
+    }
     if (RNG == RNG_TAUS88) {
       for (uint32_t g = 0; g < a.steps; g += 16)
-        walk16<GRID, false>(taus_next(t), g, a.steps, true, x, y, ux, uy, bm);
+        walk16<GRID, false, WB>(taus_next(t), g, a.steps, true, x, y, ux, uy, bm, wb);
     } else {
       for (uint32_t g = 0; g < a.steps; g += 64) {
-        const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
-        walk16<GRID, false>(b.x, g, a.steps, true, x, y, ux, uy, bm);
-        walk16<GRID, false>(b.y, g + 16, a.steps, true, x, y, ux, uy, bm);
-        walk16<GRID, false>(b.z, g + 32, a.steps, true, x, y, ux, uy, bm);
-        walk16<GRID, false>(b.w, g + 48, a.steps, true, x, y, ux, uy, bm);
+        const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
+        walk16<GRID, false, WB>(b.x, g, a.steps, true, x, y, ux, uy, bm, wb);
+        walk16<GRID, false, WB>(b.y, g + 16, a.steps, true, x, y, ux, uy, bm, wb);
+        walk16<GRID, false, WB>(b.z, g + 32, a.steps, true, x, y, ux, uy, bm, wb);
+        walk16<GRID, false, WB>(b.w, g + 48, a.steps, true, x, y, ux, uy, bm, wb);
       }
     }
     ssd += ux * ux + uy * uy;
+    if (PW)
+      for (int i = 0; i < WORDS; ++i) mine += __popc(wb[i]);
   }
   int cnt = 0;
   for (int i = 0; i < WORDS; ++i) cnt += __popc(bm[i]);
   a.ssd[r] = ssd;
   a.distinct[r] = cnt;
+  if (PW) a.walker_sites[r] = mine;
 }
 
 // Net displacement of moves g .. min(g + 16, steps) - 1 of one word.
@@ -165,24 +206,31 @@ __device__ __forceinline__ void word_displacement(uint32_t word, uint32_t g, uin
   dy += __popc(hi & ~lo) - __popc(hi & lo);
 }
 
-template <int GRID, int RNG>
+template <int GRID, int RNG, bool PW>
 __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
   constexpr int WORDS = GRID * GRID / 32;
+  constexpr int WB = PW ? WB_SHARED : WB_NONE;
   __shared__ uint32_t bm[WORDS];
-  __shared__ int sh_ssd[16], sh_cnt[16];
+  __shared__ int sh_ssd[16], sh_cnt[16], sh_mine[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t w = (uint32_t)tid >> 4, sgi = (uint32_t)tid & 15u;
   const uint64_t r = blockIdx.x;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   for (int i = tid; i < WORDS; i += blockDim.x) bm[i] = 0u;
-  __syncthreads();
+  // the walker's own bitmap, shared by its 16 segment lanes (global memory)
   const bool active = w < a.walkers;
+  uint32_t *wb = nullptr;
+  if (PW && active) {
+    wb = a.walker_bitmaps + (r * a.walkers + w) * WORDS;
+    for (int i = (int)sgi; i < WORDS; i += 16) wb[i] = 0u;
+  }
+  __syncthreads();
   const uint32_t t0 = min(a.steps, sgi * seg), t1 = min(a.steps, t0 + seg);
 
   // pass 1: the segment's net displacement (seg is a multiple of 64 steps)
   Taus ts;
   if (RNG == RNG_TAUS88) {
-    ts = taus_seed(TAG_RW, 0u, (uint32_t)r, k0, k1);
+    ts = taus_seed(TAG_RW, 0u, (uint32_t)(a.rep0 + r), k0, k1);
     taus_skip(ts, (uint64_t)w * ((a.steps + 15) / 16) + t0 / 16, a.taus);
   }
   const Taus ts0 = ts;
@@ -193,7 +241,7 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) wd[j] = g + 16u * j < t1 ? taus_next(ts) : 0u;
     } else {
-      const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
+      const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
       wd[0] = b.x;
       wd[1] = b.y;
       wd[2] = b.z;
@@ -215,7 +263,10 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
   int ux = sx - dx, uy = sy - dy;  // unwrapped offset at the segment's start
   int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
   int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
-  if (active && sgi == 0) mark(bm, y * GRID + x);
+  if (active && sgi == 0) {
+    mark(bm, y * GRID + x);
+    mark_walker<WB>(wb, y * GRID + x, true);
+  }
   x = (x + ux) & (GRID - 1);
   y = (y + uy) & (GRID - 1);
 
@@ -227,7 +278,7 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) wd[j] = g + 16u * j < t1 ? taus_next(ts) : 0u;
     } else {
-      const Block4 b = philox(g >> 6, w, (uint32_t)r, TAG_RW, k0, k1);
+      const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
       wd[0] = b.x;
       wd[1] = b.y;
       wd[2] = b.z;
@@ -235,7 +286,7 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      walk16<GRID, true>(wd[j], g + 16u * j, t1, active, x, y, ux, uy, bm);
+      walk16<GRID, true, WB>(wd[j], g + 16u * j, t1, active, x, y, ux, uy, bm, wb);
   }
   __syncthreads();
 
@@ -246,19 +297,30 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
   for (int i = tid; i < WORDS; i += blockDim.x) cnt += __popc(bm[i]);
   sd = group_sum_i(sd, 64);
   cnt = group_sum_i(cnt, 64);
+  int mine = 0;
+  if (PW) {
+    // read the walker's words back through the atomic unit (where the other
+    // segment lanes' ors were performed)
+    if (active)
+      for (int i = (int)sgi; i < WORDS; i += 16) mine += __popc(atomicOr(&wb[i], 0u));
+    mine = group_sum_i(mine, 64);
+  }
   if (lane == 0) {
     sh_ssd[wave] = sd;
     sh_cnt[wave] = cnt;
+    sh_mine[wave] = mine;
   }
   __syncthreads();
   if (tid == 0) {
-    int s1 = 0, s2 = 0;
+    int s1 = 0, s2 = 0, s3 = 0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
       s1 += sh_ssd[i];
       s2 += sh_cnt[i];
+      s3 += sh_mine[i];
     }
     a.ssd[r] = s1;
     a.distinct[r] = s2;
+    if (PW) a.walker_sites[r] = s3;
   }
 }
 
@@ -274,21 +336,29 @@ hipError_t wave_launch(const RwArgs &a, uint32_t wg, hipStream_t s) {
     // 16 lanes per walker; segments of whole Philox blocks (64 moves)
     const uint32_t threads = (16u * a.walkers + 63u) / 64u * 64u;
     const uint32_t seg = (a.steps + 16u * 64u - 1u) / (16u * 64u) * 64u;
-    if (a.rng == RNG_TAUS88)
-      hipLaunchKernelGGL((rw_seg_kernel<GRID, RNG_TAUS88>), dim3((uint32_t)a.n_reps),
-                         dim3(threads), 0, s, a, seg);
-    else
-      hipLaunchKernelGGL((rw_seg_kernel<GRID, RNG_PHILOX>), dim3((uint32_t)a.n_reps),
-                         dim3(threads), 0, s, a, seg);
+    const dim3 g((uint32_t)a.n_reps), b(threads);
+    const bool pw = a.walker_sites != nullptr;
+    if (a.rng == RNG_TAUS88) {
+      if (pw) hipLaunchKernelGGL((rw_seg_kernel<GRID, RNG_TAUS88, true>), g, b, 0, s, a, seg);
+      else hipLaunchKernelGGL((rw_seg_kernel<GRID, RNG_TAUS88, false>), g, b, 0, s, a, seg);
+    } else {
+      if (pw) hipLaunchKernelGGL((rw_seg_kernel<GRID, RNG_PHILOX, true>), g, b, 0, s, a, seg);
+      else hipLaunchKernelGGL((rw_seg_kernel<GRID, RNG_PHILOX, false>), g, b, 0, s, a, seg);
+    }
     return hipGetLastError();
   }
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (a.n_reps + wpb - 1) / wpb;
   const size_t lds = (size_t)wpb * (GRID * GRID / 32) * sizeof(uint32_t);
-  if (a.rng == RNG_TAUS88)
-    hipLaunchKernelGGL((rw_wave_kernel<GRID, RNG_TAUS88>), dim3((uint32_t)blocks), dim3(wg), lds, s, a);
-  else
-    hipLaunchKernelGGL((rw_wave_kernel<GRID, RNG_PHILOX>), dim3((uint32_t)blocks), dim3(wg), lds, s, a);
+  const dim3 g((uint32_t)blocks), b(wg);
+  const bool pw = a.walker_sites != nullptr;
+  if (a.rng == RNG_TAUS88) {
+    if (pw) hipLaunchKernelGGL((rw_wave_kernel<GRID, RNG_TAUS88, true>), g, b, lds, s, a);
+    else hipLaunchKernelGGL((rw_wave_kernel<GRID, RNG_TAUS88, false>), g, b, lds, s, a);
+  } else {
+    if (pw) hipLaunchKernelGGL((rw_wave_kernel<GRID, RNG_PHILOX, true>), g, b, lds, s, a);
+    else hipLaunchKernelGGL((rw_wave_kernel<GRID, RNG_PHILOX, false>), g, b, lds, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -298,13 +368,16 @@ hipError_t simt_launch(const RwArgs &a, bool one_lane, hipStream_t s) {
   const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
   const uint64_t blocks = (threads + wg - 1) / wg;
   const dim3 g((uint32_t)blocks), b(wg);
+#define MRIP_SIMT(ST, RN, PW) hipLaunchKernelGGL((rw_simt_kernel<GRID, ST, RN, PW>), g, b, 0, s, a)
+  const bool pw = a.walker_sites != nullptr;
   if (a.rng == RNG_TAUS88) {
-    if (one_lane) hipLaunchKernelGGL((rw_simt_kernel<GRID, 64, RNG_TAUS88>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((rw_simt_kernel<GRID, 1, RNG_TAUS88>), g, b, 0, s, a);
+    if (one_lane) { if (pw) MRIP_SIMT(64, RNG_TAUS88, true); else MRIP_SIMT(64, RNG_TAUS88, false); }
+    else { if (pw) MRIP_SIMT(1, RNG_TAUS88, true); else MRIP_SIMT(1, RNG_TAUS88, false); }
   } else {
-    if (one_lane) hipLaunchKernelGGL((rw_simt_kernel<GRID, 64, RNG_PHILOX>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((rw_simt_kernel<GRID, 1, RNG_PHILOX>), g, b, 0, s, a);
+    if (one_lane) { if (pw) MRIP_SIMT(64, RNG_PHILOX, true); else MRIP_SIMT(64, RNG_PHILOX, false); }
+    else { if (pw) MRIP_SIMT(1, RNG_PHILOX, true); else MRIP_SIMT(1, RNG_PHILOX, false); }
   }
+#undef MRIP_SIMT
   return hipGetLastError();
 }
 

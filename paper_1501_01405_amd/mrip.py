@@ -24,7 +24,7 @@ MRIP_CV_BETA_BINS = 16
 
 class mrip_rw_params(C.Structure):
     _fields_ = [("size", C.c_uint32), ("walkers", C.c_uint32), ("grid", C.c_uint32),
-                ("steps", C.c_uint32)]
+                ("steps", C.c_uint32), ("walker_sites", C.c_uint32)]
 
 
 class mrip_mm1_params(C.Structure):
@@ -369,8 +369,8 @@ def mrip_t_quantile(p, dof):
 
 
 # ------------------------------------------------------------ convenience
-def rw_params(walkers=64, grid=64, steps=1000):
-    return mrip_rw_params(C.sizeof(mrip_rw_params), walkers, grid, steps)
+def rw_params(walkers=64, grid=64, steps=1000, walker_sites=False):
+    return mrip_rw_params(C.sizeof(mrip_rw_params), walkers, grid, steps, int(walker_sites))
 
 
 def mm1_params(lam=0.9, mu=1.0, customers=100000, feature_prefix=0):
@@ -389,7 +389,7 @@ def cv_hparams(epochs=20, batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
     return mrip_cv_hparams(C.sizeof(mrip_cv_hparams), epochs, batch, lr, beta1, beta2, eps)
 
 
-_OUT_DTYPES = {MRIP_RW: ("int32", "int32"), MRIP_MM1: ("float32",) * 3,
+_OUT_DTYPES = {MRIP_RW: ("int32", "int32", "int32"), MRIP_MM1: ("float32",) * 3,
                MRIP_FF: ("int32",), MRIP_PI: ("int32", "float32")}
 
 

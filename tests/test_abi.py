@@ -67,6 +67,10 @@ def test_parameter_validation():
     assert _create(mrip.MRIP_RW, mrip.rw_params(walkers=65)) == bad
     assert _create(mrip.MRIP_RW, mrip.rw_params(grid=48)) == bad
     assert _create(mrip.MRIP_RW, mrip.rw_params(steps=10**5)) == bad
+    assert _create(mrip.MRIP_RW, mrip.rw_params(walker_sites=True)) == ok
+    p = mrip.rw_params()
+    p.walker_sites = 2
+    assert _create(mrip.MRIP_RW, p) == bad
     assert _create(mrip.MRIP_MM1, mrip.mm1_params()) == ok
     assert _create(mrip.MRIP_MM1, mrip.mm1_params(lam=0.0)) == bad
     assert _create(mrip.MRIP_MM1, mrip.mm1_params(customers=0)) == bad

@@ -122,3 +122,50 @@ def test_rw_segmented_and_sequential_forms_agree(gpu, rng):
         for o in range(2):
             assert np.array_equal(small.output(o).cpu().numpy(),
                                   big.output(o).cpu().numpy()[:2048])
+
+
+@pytest.mark.parametrize("rng", ["philox", "taus88"])
+@pytest.mark.parametrize("mapping", [SIMT, WAVE, LANE0])
+@pytest.mark.parametrize("W,G,T,R", [(64, 64, 1000, 12), (5, 16, 37, 9), (33, 128, 300, 5)])
+def test_rw_walker_sites_bit_exact(gpu, rng, mapping, W, G, T, R):
+    announce("rw walker sites", rng, mapping, W, G, T, R)
+    ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T, walker_sites=True), mapping)
+    ctx.set_rng(mrip.MRIP_RNG_PHILOX if rng == "philox" else mrip.MRIP_RNG_TAUS88)
+    ctx.run(R, seed=13)
+    ref = core.rw_many(13, R, W, G, T, threads=core.default_threads(), rng=rng,
+                       walker_sites=True)
+    for o in range(3):
+        assert np.array_equal(ctx.output(o).cpu().numpy(), ref[o])
+    s = ctx.stats(2)
+    assert abs(s["mean"] - ref[2].mean()) <= 1e-12 * ref[2].mean()
+
+
+@pytest.mark.parametrize("rng", ["philox", "taus88"])
+def test_rw_walker_sites_one_wave_per_replication(gpu, rng):
+    # beyond 2048 replications each walker is one lane that owns its bitmap
+    announce("rw walker sites, sequential form", rng)
+    R, W, G, T = 2100, 64, 64, 200
+    ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T, walker_sites=True), WAVE)
+    ctx.set_rng(mrip.MRIP_RNG_PHILOX if rng == "philox" else mrip.MRIP_RNG_TAUS88)
+    ctx.run(R, seed=14)
+    ids = [0, 1, 1050, R - 1]
+    ref = core.rw_many(14, ids, W, G, T, threads=4, rng=rng, walker_sites=True)
+    got = [ctx.output(o).cpu().numpy()[ids] for o in range(3)]
+    for o in range(3):
+        assert np.array_equal(got[o], ref[o])
+
+
+def test_rw_walker_sites_in_several_launches(gpu):
+    # 64 walkers on a 128 x 128 torus keep 128 KiB of walker bitmaps per
+    # replication: 9000 replications go in two launches (8192, then 808)
+    announce("rw walker sites, two launches")
+    R, W, G, T = 9000, 64, 128, 64
+    ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T, walker_sites=True), WAVE)
+    ctx.run(R, seed=15)
+    plain = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T), WAVE)
+    plain.run(R, seed=15)
+    for o in range(2):
+        assert np.array_equal(ctx.output(o).cpu().numpy(), plain.output(o).cpu().numpy())
+    ids = [0, 8191, 8192, 8193, R - 1]
+    ref = core.rw_many(15, ids, W, G, T, threads=4, walker_sites=True)
+    assert np.array_equal(ctx.output(2).cpu().numpy()[ids], ref[2])
