@@ -62,8 +62,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary configs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target wall time of the CPU-oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="target thread time (CPU seconds) of the CPU-oracle sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with a 256 MiB device-to-device copy (calibrates HBM counters)")
     ap.add_argument("--mapping-counters", action="store_true",
@@ -122,17 +122,19 @@ def timed_steps(ctx, steps, warmup, torch, mrip):
 
 
 def cpu_baseline(seconds):
-    """The CPU oracle, unchanged, on a bounded sample of the same workload:
-    whole replications of 1e5 customers run one per host thread."""
+    """The CPU oracle, unchanged, on the same workload: the whole 1024 x 1e5
+    run (replication ids 0..1023, one per host thread at a time), repeated
+    with new seeds until about `seconds` of thread time (CPU seconds) are spent."""
     from oracle import core
     threads = min(core.default_threads(), 16)
     core.mm1_many(7, 1, N, LAM, MU)  # load and warm up
     t0 = time.perf_counter()
     core.mm1_many(7, 4, N, LAM, MU)  # calibrate on four replications
     one = (time.perf_counter() - t0) / 4
-    reps = int(min(max(threads, seconds * threads / max(one, 1e-4)), 20000))
+    passes = int(min(max(1, round(seconds / max(one * R, 1e-4))), 32))
     t0 = time.perf_counter()
-    core.mm1_many(7, reps, N, LAM, MU, threads=threads)
+    for k in range(passes):
+        core.mm1_many(42 + k, R, N, LAM, MU, threads=threads)
     dt = time.perf_counter() - t0
     model = ""
     try:
@@ -143,9 +145,10 @@ def cpu_baseline(seconds):
                     break
     except OSError:
         pass
-    return {"value": reps * N / dt, "unit": "customers/s", "cores": threads, "kind": "oracle",
-            "sample": "%d replications x %d customers (of 1024 x 1e5), %.1f s wall" %
-                      (reps, N, dt),
+    return {"value": passes * R * N / dt, "unit": "customers/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "the whole workload (%d replications x %d customers), %d passes "
+                      "(seeds 42..%d), %.1f s wall" % (R, N, passes, 41 + passes, dt),
             "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
