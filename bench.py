@@ -55,6 +55,37 @@ def mm1_slots_per_customer(c=SLOT_COST):
     return philox + variates + lindley + sums
 
 
+def philox_block_slots(c=SLOT_COST):
+    """One Philox4x32-10 block: 20 32x32->64 multiplies, 20 three-input xors
+    (the key schedule runs on the scalar unit)."""
+    return 20 * c["mad_u64_u32"] + 20 * c["simple"]
+
+
+def pi_slots_per_point(c=SLOT_COST):
+    """Half a block, each coordinate's odd 25-bit integer (shift, or), the two
+    squares summed on v_mad_u64_u32, one 64-bit compare, one add into the
+    count."""
+    return philox_block_slots(c) / 2 + 4 * c["simple"] + 2 * c["mad_u64_u32"] + 2 * c["simple"]
+
+
+def ff_slots_per_cell(c=SLOT_COST):
+    """A quarter block, the two threshold tests, and the rule on 32-cell
+    bit-plane words (about 8 word operations per 32 cells)."""
+    return philox_block_slots(c) / 4 + 2 * c["simple"] + 8 / 32 * c["simple"]
+
+
+def rw_slots_per_step(c=SLOT_COST):
+    """1/64 block and about 8 move, unwrapped-offset and wrap operations (the
+    LDS or that marks the site is not a VALU op)."""
+    return philox_block_slots(c) / 64 + 8 * c["simple"]
+
+
+def alu_roofline(events_per_s, slots):
+    achieved = events_per_s * slots
+    return {"bound": "alu", "slots_per_event": round(slots, 2), "achieved": achieved / 1e12,
+            "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +241,7 @@ def extras(torch, mrip, inputs):
         v, ms = rate(ctx, 32, 32 * 64 * 1000)
         out.setdefault("rw_32x64x1000", {})[name] = {"walker_steps_per_s": v, "kernel_ms": ms}
     rw = out["rw_32x64x1000"]
+    rw["wave"]["roofline"] = alu_roofline(rw["wave"]["walker_steps_per_s"], rw_slots_per_step())
     rw["wave_over_simt"] = rw["wave"]["walker_steps_per_s"] / rw["simt"]["walker_steps_per_s"]
     rw["lane0_over_simt"] = rw["lane0"]["walker_steps_per_s"] / rw["simt"]["walker_steps_per_s"]
     # the paper's replication sweep (its random-walk figure): kernel ms per mapping
@@ -219,6 +251,9 @@ def extras(torch, mrip, inputs):
         for n in (1, 8, 32, 64, 256, 1024, 4096, 16384):
             sweep.setdefault(str(n), {})[name] = rate(ctx, n, n * 64 * 1000, runs=2)[1]
     rw["sweep_kernel_ms"] = sweep
+    # the chip filled: 16384 replications in the wavefront mapping
+    rw["wave_16384_roofline"] = alu_roofline(16384 * 64 * 1000 / (sweep["16384"]["wave"] * 1e-3),
+                                             rw_slots_per_step())
 
     # Monte Carlo pi, 1e7 draws per replication (the paper's first model):
     # kernel ms against replications per mapping, and the oracle's single-core
@@ -239,7 +274,8 @@ def extras(torch, mrip, inputs):
     s_pi = ctx.stats(1)
     out["pi_1e7"] = {"wave_points_per_s_1024reps": v, "sweep_kernel_ms": psweep,
                      "cpu_oracle_s_per_rep_one_core": cpu_rep_s,
-                     "pi_estimate_1024reps": s_pi["mean"], "half_width": s_pi["half_width"]}
+                     "pi_estimate_1024reps": s_pi["mean"], "half_width": s_pi["half_width"],
+                     "roofline": alu_roofline(v, pi_slots_per_point())}
 
     # M/M/1 with the paper's one-working-lane WLP form
     ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_LANE0)
@@ -252,7 +288,7 @@ def extras(torch, mrip, inputs):
     v, ms = rate(ctx, 4096, ev, runs=2)
     s = ctx.stats(0)
     ff = {"wave": {"cell_updates_per_s": v, "kernel_ms": ms, "mean_burnt": s["mean"],
-                   "half_width": s["half_width"]}}
+                   "half_width": s["half_width"], "roofline": alu_roofline(v, ff_slots_per_cell())}}
     ctx = mrip.Context(mrip.MRIP_FF, mrip.ff_params(128, 2000, 0.01, 1e-5), mrip.MRIP_MAP_SIMT)
     v, ms = rate(ctx, 4096, ev, runs=1)
     ff["simt"] = {"cell_updates_per_s": v, "kernel_ms": ms}
@@ -299,6 +335,8 @@ def extras(torch, mrip, inputs):
     total = float(items["customers"].sum())
     out["plan_64x32"] = {"customers": total, "kernel_ms": min(ms),
                          "customers_per_s": total / (min(ms) * 1e-3),
+                         "roofline": alu_roofline(total / (min(ms) * 1e-3),
+                                                  mm1_slots_per_customer()),
                          "tuned_shape": {"reps_per_wave": rpw, "workgroup": wg},
                          "longest_item": int(items["customers"].max())}
     return out

@@ -22,7 +22,9 @@
  *    mrip_last_error(ctx).
  *  - `hip_stream` is a caller-owned hipStream_t (NULL = the null stream).
  *    Run calls only enqueue work and return; calls that hand results back
- *    to the host synchronise that stream first.
+ *    to the host synchronise that stream first. A run enqueued on another
+ *    stream than the context's previous run waits on the device for that
+ *    run's simulation (the context's scratch buffers serve one at a time).
  *  - Pointers named *_dev are device pointers the caller owns (for example
  *    torch tensors); pointers without the suffix are host pointers, read
  *    during the call only. The context owns every buffer it allocates and

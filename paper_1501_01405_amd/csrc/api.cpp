@@ -107,7 +107,13 @@ mrip_status commit_stats_slot(mrip_ctx c, hipStream_t s) {
 
 // Events bracketing one simulation-kernel launch: the next slot of the
 // run-history ring (the last run's pair is the slot before `launches`).
+// A launch on another stream than the last one first waits for the last
+// launch: the context's scratch buffers serve one launch at a time.
 mrip_status record_begin(mrip_ctx c, hipStream_t s) {
+  if (c->launches > 0 && s != c->last_stream) {
+    const uint32_t prev = (uint32_t)((c->launches - 1) % mrip_ctx_s::RING);
+    HIP_TRY(c, hipStreamWaitEvent(s, c->ring1[prev], 0));
+  }
   const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
   if (!c->ring0[slot]) HIP_TRY(c, hipEventCreate(&c->ring0[slot]));
   if (!c->ring1[slot]) HIP_TRY(c, hipEventCreate(&c->ring1[slot]));

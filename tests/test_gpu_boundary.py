@@ -1,12 +1,14 @@
 """GPU tests of the boundary's caller-owned outputs and plan resume: a bound
 torch buffer receives exactly the outputs (and statistics) of an unbound
 run, and a plan resumed from saved outputs of its finished items gives the
-outputs and per-design-point statistics of an uninterrupted run."""
+outputs and per-design-point statistics of an uninterrupted run; runs of one
+context on two streams are ordered on the device."""
 import numpy as np
 import pytest
 import torch
 
 from gpu_util import SIMT, WAVE, announce
+from oracle import core
 from paper_1501_01405_amd import inputs, mrip
 
 pytestmark = pytest.mark.gpu
@@ -99,3 +101,23 @@ def test_resumed_plan_equals_uninterrupted_plan(gpu):
     # nothing done: the whole plan
     ctx.run_plan_resume(np.zeros(n, np.uint8), seed=9)
     assert np.array_equal(bufs[0].cpu().numpy(), want[0])
+
+
+def test_runs_on_two_streams_share_scratch_in_order(gpu):
+    # SIMT walk bitmaps live in the context's scratch buffer: a run enqueued
+    # on a second stream waits for the first run's launch
+    announce("rw simt on two streams")
+    W, G, T, R = 64, 64, 1000, 4096
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T), SIMT)
+    ctx.run(R, seed=1, stream=s1.cuda_stream)
+    ctx.run(R, seed=2, stream=s2.cuda_stream)
+    got = [ctx.output(o).cpu().numpy() for o in range(2)]
+    ref = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T), SIMT)
+    ref.run(R, seed=2)
+    for o in range(2):
+        assert np.array_equal(got[o], ref.output(o).cpu().numpy())
+    ids = [0, 4095]
+    ssd, distinct = core.rw_many(2, ids, W, G, T, threads=2)
+    assert np.array_equal(got[0][ids], ssd)
+    assert np.array_equal(got[1][ids], distinct)
