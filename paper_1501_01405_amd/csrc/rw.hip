@@ -34,9 +34,11 @@ namespace mrip {
 
 namespace {
 
+// Move d (0:+x 1:-x 2:+y 3:-y) as two sign-extended 2-bit fields of small
+// tables: dx = field d of 0b00'00'11'01, dy = field d of 0b11'01'00'00.
 __device__ __forceinline__ void step_delta(uint32_t d, int &dx, int &dy) {
-  dx = (d == 0u) - (d == 1u);
-  dy = (d == 2u) - (d == 3u);
+  dx = __builtin_amdgcn_sbfe(0x0D, d << 1, 2);
+  dy = __builtin_amdgcn_sbfe(0xD0, d << 1, 2);
 }
 
 // Set the visited bit of lattice site c (row-major) in an LDS bitmap.
@@ -52,18 +54,19 @@ __device__ __forceinline__ void mark_walker(uint32_t *wb, int c, bool active) {
   if (WB == WB_SHARED && active) atomicOr(&wb[c >> 5], 1u << (c & 31));
 }
 
+// One move of a walker at unwrapped position (X, Y); marks the wrapped site.
+// LDS: inactive lanes or into `spare` (a word past the bitmaps), so the
+// mark needs no branch.
 template <int GRID, bool LDS, int WB>
-__device__ __forceinline__ void move1(uint32_t d, bool active, int &x, int &y, int &ux, int &uy,
-                                      uint32_t *bm, uint32_t *wb) {
+__device__ __forceinline__ void move1(uint32_t d, bool active, int &X, int &Y, uint32_t *bm,
+                                      uint32_t *spare, uint32_t *wb) {
   int dx, dy;
   step_delta(d, dx, dy);
-  ux += dx;
-  uy += dy;
-  x = (x + dx) & (GRID - 1);
-  y = (y + dy) & (GRID - 1);
-  const int c = y * GRID + x;
+  X += dx;
+  Y += dy;
+  const int c = (Y & (GRID - 1)) * GRID + (X & (GRID - 1));
   if (LDS) {
-    if (active) mark(bm, c);
+    atomicOr(active ? &bm[c >> 5] : spare, 1u << (c & 31));
   } else {
     bm[c >> 5] |= 1u << (c & 31);
   }
@@ -74,15 +77,15 @@ __device__ __forceinline__ void move1(uint32_t d, bool active, int &x, int &y, i
 // g .. min(g + 16, steps) - 1.
 template <int GRID, bool LDS, int WB = WB_NONE>
 __device__ __forceinline__ void walk16(uint32_t word, uint32_t g, uint32_t steps, bool active,
-                                       int &x, int &y, int &ux, int &uy, uint32_t *bm,
+                                       int &X, int &Y, uint32_t *bm, uint32_t *spare,
                                        uint32_t *wb = nullptr) {
   if (g + 16u <= steps) {
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-      move1<GRID, LDS, WB>((word >> (2 * i)) & 3u, active, x, y, ux, uy, bm, wb);
+      move1<GRID, LDS, WB>((word >> (2 * i)) & 3u, active, X, Y, bm, spare, wb);
   } else {
     for (uint32_t i = 0; g + i < steps; ++i)
-      move1<GRID, LDS, WB>((word >> (2 * i)) & 3u, active, x, y, ux, uy, bm, wb);
+      move1<GRID, LDS, WB>((word >> (2 * i)) & 3u, active, X, Y, bm, spare, wb);
   }
 }
 
@@ -100,36 +103,38 @@ __global__ void rw_wave_kernel(RwArgs a) {
 
   const bool active = r < a.n_reps && (uint32_t)lane < a.walkers;
   const uint32_t w = (uint32_t)lane;
-  int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
-  int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
-  int ux = 0, uy = 0;
-  if (active) mark(bm, y * GRID + x);
+  const int x0 = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
+  const int y0 = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
+  int X = x0, Y = y0;
+  uint32_t *spare = lds + (blockDim.x >> 6) * WORDS;
+  if (active) mark(bm, y0 * GRID + x0);
   // this walker's own bitmap (global memory, owned by this lane)
   uint32_t *wb = nullptr;
   if (PW && active) {
     wb = a.walker_bitmaps + (r * a.walkers + w) * WORDS;
     for (int i = 0; i < WORDS; ++i) wb[i] = 0u;
-    mark_walker<WB>(wb, y * GRID + x, true);
+    mark_walker<WB>(wb, y0 * GRID + x0, true);
   }
 
   if (RNG == RNG_TAUS88) {
     Taus t = taus_seed(TAG_RW, 0u, (uint32_t)(a.rep0 + r), k0, k1);
     taus_skip(t, (uint64_t)w * ((a.steps + 15) / 16), a.taus);
     for (uint32_t g = 0; g < a.steps; g += 16)
-      walk16<GRID, true, WB>(taus_next(t), g, a.steps, active, x, y, ux, uy, bm, wb);
+      walk16<GRID, true, WB>(taus_next(t), g, a.steps, active, X, Y, bm, spare, wb);
   } else {
     for (uint32_t g = 0; g < a.steps; g += 64) {
       const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
-      walk16<GRID, true, WB>(b.x, g, a.steps, active, x, y, ux, uy, bm, wb);
-      walk16<GRID, true, WB>(b.y, g + 16, a.steps, active, x, y, ux, uy, bm, wb);
-      walk16<GRID, true, WB>(b.z, g + 32, a.steps, active, x, y, ux, uy, bm, wb);
-      walk16<GRID, true, WB>(b.w, g + 48, a.steps, active, x, y, ux, uy, bm, wb);
+      walk16<GRID, true, WB>(b.x, g, a.steps, active, X, Y, bm, spare, wb);
+      walk16<GRID, true, WB>(b.y, g + 16, a.steps, active, X, Y, bm, spare, wb);
+      walk16<GRID, true, WB>(b.z, g + 32, a.steps, active, X, Y, bm, spare, wb);
+      walk16<GRID, true, WB>(b.w, g + 48, a.steps, active, X, Y, bm, spare, wb);
     }
   }
   __syncthreads();
   int cnt = 0;
   for (int i = lane; i < WORDS; i += 64) cnt += __popc(bm[i]);
   cnt = group_sum_i(cnt, 64);
+  const int ux = X - x0, uy = Y - y0;
   const int sd = active ? ux * ux + uy * uy : 0;
   const int ssd = group_sum_i(sd, 64);
   int mine = 0;
@@ -164,26 +169,27 @@ __global__ void rw_simt_kernel(RwArgs a) {
   Taus t;
   if (RNG == RNG_TAUS88) t = taus_seed(TAG_RW, 0u, (uint32_t)(a.rep0 + r), k0, k1);
   for (uint32_t w = 0; w < a.walkers; ++w) {
-    int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
-    int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
-    int ux = 0, uy = 0;
-    bm[(y * GRID + x) >> 5] |= 1u << ((y * GRID + x) & 31);
+    const int x0 = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
+    const int y0 = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
+    int X = x0, Y = y0;
+    bm[(y0 * GRID + x0) >> 5] |= 1u << ((y0 * GRID + x0) & 31);
     if (PW) {
       for (int i = 0; i < WORDS; ++i) wb[i] = 0u;
-      mark_walker<WB>(wb, y * GRID + x, true);
+      mark_walker<WB>(wb, y0 * GRID + x0, true);
     }
     if (RNG == RNG_TAUS88) {
       for (uint32_t g = 0; g < a.steps; g += 16)
-        walk16<GRID, false, WB>(taus_next(t), g, a.steps, true, x, y, ux, uy, bm, wb);
+        walk16<GRID, false, WB>(taus_next(t), g, a.steps, true, X, Y, bm, nullptr, wb);
     } else {
       for (uint32_t g = 0; g < a.steps; g += 64) {
         const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
-        walk16<GRID, false, WB>(b.x, g, a.steps, true, x, y, ux, uy, bm, wb);
-        walk16<GRID, false, WB>(b.y, g + 16, a.steps, true, x, y, ux, uy, bm, wb);
-        walk16<GRID, false, WB>(b.z, g + 32, a.steps, true, x, y, ux, uy, bm, wb);
-        walk16<GRID, false, WB>(b.w, g + 48, a.steps, true, x, y, ux, uy, bm, wb);
+        walk16<GRID, false, WB>(b.x, g, a.steps, true, X, Y, bm, nullptr, wb);
+        walk16<GRID, false, WB>(b.y, g + 16, a.steps, true, X, Y, bm, nullptr, wb);
+        walk16<GRID, false, WB>(b.z, g + 32, a.steps, true, X, Y, bm, nullptr, wb);
+        walk16<GRID, false, WB>(b.w, g + 48, a.steps, true, X, Y, bm, nullptr, wb);
       }
     }
+    const int ux = X - x0, uy = Y - y0;
     ssd += ux * ux + uy * uy;
     if (PW)
       for (int i = 0; i < WORDS; ++i) mine += __popc(wb[i]);
@@ -206,13 +212,27 @@ __device__ __forceinline__ void word_displacement(uint32_t word, uint32_t g, uin
   dy += __popc(hi & ~lo) - __popc(hi & lo);
 }
 
+// Sum of v over the workgroup (every thread gets it); `sh` holds one int per
+// wavefront.
+__device__ __forceinline__ int block_sum_i(int v, int *sh) {
+  v = group_sum_i(v, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  int t = 0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+// One workgroup per replication, 16 lanes per walker.
 template <int GRID, int RNG, bool PW>
 __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
   constexpr int WORDS = GRID * GRID / 32;
   constexpr int WB = PW ? WB_SHARED : WB_NONE;
-  __shared__ uint32_t bm[WORDS];
-  __shared__ int sh_ssd[16], sh_cnt[16], sh_mine[16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ uint32_t bm[WORDS + 1];  // + the inactive lanes' spare word
+  __shared__ int sh_red[16];
+  const int tid = threadIdx.x;
   const uint32_t w = (uint32_t)tid >> 4, sgi = (uint32_t)tid & 15u;
   const uint64_t r = blockIdx.x;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -260,15 +280,14 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
       sy += py;
     }
   }
-  int ux = sx - dx, uy = sy - dy;  // unwrapped offset at the segment's start
-  int x = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
-  int y = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
+  const int x0 = (int)(((w % 8u) * (GRID / 8) + GRID / 16) % GRID);
+  const int y0 = (int)(((w / 8u) * (GRID / 8) + GRID / 16) % GRID);
   if (active && sgi == 0) {
-    mark(bm, y * GRID + x);
-    mark_walker<WB>(wb, y * GRID + x, true);
+    mark(bm, y0 * GRID + x0);
+    mark_walker<WB>(wb, y0 * GRID + x0, true);
   }
-  x = (x + ux) & (GRID - 1);
-  y = (y + uy) & (GRID - 1);
+  // unwrapped position at the segment's start
+  int X = x0 + (sx - dx), Y = y0 + (sy - dy);
 
   // pass 2: replay the segment's moves from its start
   ts = ts0;
@@ -286,41 +305,27 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      walk16<GRID, true, WB>(wd[j], g + 16u * j, t1, active, x, y, ux, uy, bm, wb);
+      walk16<GRID, true, WB>(wd[j], g + 16u * j, t1, active, X, Y, bm, &bm[WORDS], wb);
   }
   __syncthreads();
 
   // outputs: the walkers' squared end displacements (last segment's lane
   // holds the walker's total) and the popcount of the union bitmap
-  int sd = (active && sgi == 15) ? sx * sx + sy * sy : 0;
-  int cnt = 0;
-  for (int i = tid; i < WORDS; i += blockDim.x) cnt += __popc(bm[i]);
-  sd = group_sum_i(sd, 64);
-  cnt = group_sum_i(cnt, 64);
   int mine = 0;
-  if (PW) {
+  if (PW && active) {
     // read the walker's words back through the atomic unit (where the other
     // segment lanes' ors were performed)
-    if (active)
-      for (int i = (int)sgi; i < WORDS; i += 16) mine += __popc(atomicOr(&wb[i], 0u));
-    mine = group_sum_i(mine, 64);
+    for (int i = (int)sgi; i < WORDS; i += 16) mine += __popc(atomicOr(&wb[i], 0u));
   }
-  if (lane == 0) {
-    sh_ssd[wave] = sd;
-    sh_cnt[wave] = cnt;
-    sh_mine[wave] = mine;
-  }
-  __syncthreads();
+  const int sd = block_sum_i((active && sgi == 15) ? sx * sx + sy * sy : 0, sh_red);
+  if (PW) mine = block_sum_i(mine, sh_red);
+  int cnt = 0;
+  for (int i = tid; i < WORDS; i += blockDim.x) cnt += __popc(bm[i]);
+  cnt = block_sum_i(cnt, sh_red);
   if (tid == 0) {
-    int s1 = 0, s2 = 0, s3 = 0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-      s1 += sh_ssd[i];
-      s2 += sh_cnt[i];
-      s3 += sh_mine[i];
-    }
-    a.ssd[r] = s1;
-    a.distinct[r] = s2;
-    if (PW) a.walker_sites[r] = s3;
+    a.ssd[r] = sd;
+    a.distinct[r] = cnt;
+    if (PW) a.walker_sites[r] = mine;
   }
 }
 
@@ -349,7 +354,7 @@ hipError_t wave_launch(const RwArgs &a, uint32_t wg, hipStream_t s) {
   }
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (a.n_reps + wpb - 1) / wpb;
-  const size_t lds = (size_t)wpb * (GRID * GRID / 32) * sizeof(uint32_t);
+  const size_t lds = ((size_t)wpb * (GRID * GRID / 32) + 1) * sizeof(uint32_t);  // + spare
   const dim3 g((uint32_t)blocks), b(wg);
   const bool pw = a.walker_sites != nullptr;
   if (a.rng == RNG_TAUS88) {

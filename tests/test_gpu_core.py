@@ -169,3 +169,19 @@ def test_rw_walker_sites_in_several_launches(gpu):
     ids = [0, 8191, 8192, 8193, R - 1]
     ref = core.rw_many(15, ids, W, G, T, threads=4, walker_sites=True)
     assert np.array_equal(ctx.output(2).cpu().numpy()[ids], ref[2])
+
+
+@pytest.mark.parametrize("rng", ["philox", "taus88"])
+def test_rw_consecutive_runs_of_different_sizes(gpu, rng):
+    # one context, runs alternating between the segmented (<= 2048
+    # replications) and sequential forms, with per-walker counts
+    announce("rw consecutive runs", rng)
+    W, G, T = 64, 64, 300
+    ctx = mrip.Context(mrip.MRIP_RW, mrip.rw_params(W, G, T, walker_sites=True), WAVE)
+    ctx.set_rng(mrip.MRIP_RNG_PHILOX if rng == "philox" else mrip.MRIP_RNG_TAUS88)
+    for R, seed in ((1, 3), (32, 4), (2100, 5), (7, 6), (32, 7)):
+        ctx.run(R, seed=seed)
+        ids = sorted({0, R // 2, R - 1})
+        ref = core.rw_many(seed, ids, W, G, T, threads=4, rng=rng, walker_sites=True)
+        for o in range(3):
+            assert np.array_equal(ctx.output(o).cpu().numpy()[ids], ref[o]), (R, o)
