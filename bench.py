@@ -26,7 +26,7 @@ SPLIT = 4  # wavefronts per replication (four per SIMD at 1024 replications)
 # WRITE_SIZE, each scaled by the same counter on a 256 MiB copy
 # (profiles/mm1_split_hbm_counters.md); to be re-measured (or set to None)
 # whenever the kernel changes.
-TRAFFIC_BYTES = (149.0 * 2.00 + 96.0 * 1.00) * 1024
+TRAFFIC_BYTES = (149.125 * 2.00 + 96.0 * 1.00) * 1024
 # Peak vector issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, the rate
 # behind the published fp32 vector figure (157.3 TFLOP/s counts an FMA as 2).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
@@ -152,10 +152,13 @@ def timed_steps(ctx, steps, warmup, torch, mrip):
     return elapsed, kernel_ms, half
 
 
-def cpu_baseline(seconds):
+def cpu_baseline(seconds, per_workload=True):
     """The CPU oracle, unchanged, on the same workload: the whole 1024 x 1e5
     run (replication ids 0..1023, one per host thread at a time), repeated
-    with new seeds until about `seconds` of thread time (CPU seconds) are spent."""
+    with new seeds until about `seconds` of thread time (CPU seconds) are spent.
+    With per_workload, also the oracle on bounded samples of the secondary
+    workloads (each a few hundred ms of wall time), in events per second on
+    the same threads, for the GPU/CPU ratios beside each extras row."""
     from oracle import core
     threads = min(core.default_threads(), 16)
     core.mm1_many(7, 1, N, LAM, MU)  # load and warm up
@@ -176,11 +179,47 @@ def cpu_baseline(seconds):
                     break
     except OSError:
         pass
-    return {"value": passes * R * N / dt, "unit": "customers/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "the whole workload (%d replications x %d customers), %d passes "
-                      "(seeds 42..%d), %.1f s wall" % (R, N, passes, 41 + passes, dt),
-            "cpu_model": model, "host_cpus": os.cpu_count()}
+    out = {"value": passes * R * N / dt, "unit": "customers/s", "cores": threads,
+           "kind": "oracle",
+           "sample": "the whole workload (%d replications x %d customers), %d passes "
+                     "(seeds 42..%d), %.1f s wall" % (R, N, passes, 41 + passes, dt),
+           "cpu_model": model, "host_cpus": os.cpu_count()}
+    if per_workload:
+        out["per_workload"] = oracle_workloads(core, threads)
+    return out
+
+
+def oracle_workloads(core, threads):
+    """The oracle on the secondary workloads: events/s on `threads` threads."""
+    from paper_1501_01405_amd import inputs
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    res = {}
+    dt = timed(lambda: core.rw_many(42, 32, 64, 64, 1000, threads=threads))
+    res["rw_32x64x1000"] = {"walker_steps_per_s": 32 * 64 * 1000 / dt,
+                            "sample": "the whole workload (32 replications)"}
+    # pi: one replication of 1e7 points on one core (the paper's CPU-vs-GPU
+    # crossover), then one replication per thread
+    one = timed(lambda: core.pi_hits(7, 0, 10_000_000))
+    dt = timed(lambda: core.pi_many(42, threads, 10_000_000, threads=threads))
+    res["pi_1e7"] = {"points_per_s": threads * 1e7 / dt, "s_per_rep_one_core": one,
+                     "sample": "%d replications of 1e7 points (of 1024)" % threads}
+    n_ff = 2 * threads
+    dt = timed(lambda: core.ff_many(42, n_ff, 128, 2000, 0.01, 1e-5, threads=threads))
+    res["ff_4096x128x128x2000"] = {
+        "cell_updates_per_s": n_ff * 128 * 128 * 2000 / dt,
+        "sample": "%d whole replications (of 4096)" % n_ff}
+    items = inputs.plan_table()
+    rows = [(int(i["dp"]), int(i["rep"]), int(i["customers"]), float(i["lambda_"]),
+             float(i["mu"])) for i in items]
+    dt = timed(lambda: core.mm1_items(42, rows, threads=threads))
+    res["plan_64x32"] = {"customers_per_s": float(items["customers"].sum()) / dt,
+                         "sample": "the whole plan (2048 items)"}
+    return res
 
 
 def cv_experiment(mrip, inputs, customers, K=1000):
@@ -256,12 +295,9 @@ def extras(torch, mrip, inputs):
                                              rw_slots_per_step())
 
     # Monte Carlo pi, 1e7 draws per replication (the paper's first model):
-    # kernel ms against replications per mapping, and the oracle's single-core
-    # time per replication (the paper's CPU-vs-GPU crossover)
-    from oracle import core as ocore
-    t0 = time.perf_counter()
-    ocore.pi_hits(7, 0, 10_000_000)
-    cpu_rep_s = time.perf_counter() - t0
+    # kernel ms against replications per mapping (the oracle's single-core
+    # time per replication, for the paper's CPU-vs-GPU crossover, is in
+    # cpu_baseline.per_workload)
     psweep = {}
     for name, mp in maps:
         ctx = mrip.Context(mrip.MRIP_PI, mrip.pi_params(10_000_000), mp)
@@ -273,7 +309,6 @@ def extras(torch, mrip, inputs):
     v, ms = rate(ctx, 1024, 1024 * 10_000_000, runs=2)
     s_pi = ctx.stats(1)
     out["pi_1e7"] = {"wave_points_per_s_1024reps": v, "sweep_kernel_ms": psweep,
-                     "cpu_oracle_s_per_rep_one_core": cpu_rep_s,
                      "pi_estimate_1024reps": s_pi["mean"], "half_width": s_pi["half_width"],
                      "roofline": alu_roofline(v, pi_slots_per_point())}
 
@@ -424,7 +459,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, per_workload=not args.no_extras)
+        if "extras" in line:
+            # GPU (WAVE, kernel events) over the oracle on the host threads
+            ex, cpu = line["extras"], line["cpu_baseline"]["per_workload"]
+            gpu = {"rw_32x64x1000": ex["rw_32x64x1000"]["wave"]["walker_steps_per_s"],
+                   "pi_1e7": ex["pi_1e7"]["wave_points_per_s_1024reps"],
+                   "ff_4096x128x128x2000": ex["ff_4096x128x128x2000"]["wave"]["cell_updates_per_s"],
+                   "plan_64x32": ex["plan_64x32"]["customers_per_s"]}
+            for k, v in gpu.items():
+                rate = [x for key, x in cpu[k].items() if key.endswith("_per_s")][0]
+                cpu[k]["gpu_over_oracle"] = v / rate
     print(json.dumps(line), flush=True)
 
 
