@@ -101,8 +101,11 @@ typedef enum {
  *          2 = when walker_sites != 0, int32 sum over walkers of the
  *              number of sites each one visited (its start included): the
  *              union count nearly fills the torus, this one does not.
- *              Costs a bitmap per walker in device memory (WAVE: walkers *
- *              grid^2 / 8 bytes per replication) and its updates.
+ *              Costs a bitmap per walker in device memory and its
+ *              updates: WAVE keeps walkers * grid^2 / 8 bytes per
+ *              replication and runs at most 1 GiB of them per launch (a
+ *              larger run is launched in slices, same outputs); SIMT and
+ *              LANE0 keep grid^2 / 8 bytes per replication.
  * Requires walkers * steps^2 < 2^31. */
 typedef struct {
   uint32_t size;
