@@ -146,3 +146,14 @@ def test_bind_output_and_resume_checks():
     assert L.mrip_bind_output(ctx, 3, None, 0) == mrip.MRIP_OK  # features are output 3
     assert L.mrip_run_plan_resume(ctx, 42, None, None) == mrip.MRIP_E_STATE  # no plan
     L.mrip_destroy(ctx)
+
+
+def test_c_example_is_built_and_checks_its_arguments():
+    # the plain-C client of the library (built by build()); these calls
+    # return before any HIP call
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1501_01405_amd", "examples", "mrip_from_c")
+    assert os.access(exe, os.X_OK), "the C example is not built"
+    assert subprocess.run([exe], capture_output=True, timeout=60).returncode == 2
+    r = subprocess.run([exe, "pi", "100", "4", "42", "warp"], capture_output=True, timeout=60)
+    assert r.returncode == 2 and b"unknown mapping" in r.stderr
