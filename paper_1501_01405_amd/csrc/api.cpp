@@ -42,6 +42,10 @@ mrip_status inval(mrip_ctx c, const char *why) {
     if (_e != hipSuccess) return hip_fail((ctx), _e, #expr); \
   } while (0)
 
+// Let single-kernel runs record their timing events from the kernel's own
+// dispatch (hipExtLaunchKernelGGL) instead of separate stream markers.
+constexpr bool kSelfTimedLaunch = true;
+
 uint32_t scalar_outputs(mrip_ctx c) {
   const mrip_model m = c->model;
   return m == MRIP_RW ? (c->rw.walker_sites ? 3 : 2) : m == MRIP_MM1 ? 3 : m == MRIP_PI ? 2 : 1;
@@ -93,7 +97,16 @@ double *next_stats_slot(mrip_ctx c) {
 // Before a run on stream s writes output set `set`: wait for the reduction
 // that may still be reading it.
 mrip_status claim_set(mrip_ctx c, uint32_t set, hipStream_t s) {
-  if (c->set_pending[set]) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_set_free[set], 0));
+  if (!c->set_pending[set]) return MRIP_OK;
+  // a reduction already finished needs no wait packet on the run's stream
+  const hipError_t q = hipEventQuery(c->ev_set_free[set]);
+  if (q == hipSuccess) {
+    c->set_pending[set] = false;
+    return MRIP_OK;
+  }
+  if (q != hipErrorNotReady) return hip_fail(c, q, "hipEventQuery(ev_set_free)");
+  (void)hipGetLastError();  // "not ready" is an answer, not a failure to keep
+  HIP_TRY(c, hipStreamWaitEvent(s, c->ev_set_free[set], 0));
   return MRIP_OK;
 }
 
@@ -109,7 +122,10 @@ mrip_status commit_stats_slot(mrip_ctx c, hipStream_t s) {
 // run-history ring (the last run's pair is the slot before `launches`).
 // A launch on another stream than the last one first waits for the last
 // launch: the context's scratch buffers serve one launch at a time.
-mrip_status record_begin(mrip_ctx c, hipStream_t s) {
+// `markers`: record the pair as separate stream markers; otherwise the one
+// kernel of the launch records them itself (KernelEvents), which saves two
+// packets between consecutive runs.
+mrip_status record_begin(mrip_ctx c, hipStream_t s, bool markers = true) {
   if (c->launches > 0 && s != c->last_stream) {
     const uint32_t prev = (uint32_t)((c->launches - 1) % mrip_ctx_s::RING);
     HIP_TRY(c, hipStreamWaitEvent(s, c->ring1[prev], 0));
@@ -117,13 +133,19 @@ mrip_status record_begin(mrip_ctx c, hipStream_t s) {
   const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
   if (!c->ring0[slot]) HIP_TRY(c, hipEventCreate(&c->ring0[slot]));
   if (!c->ring1[slot]) HIP_TRY(c, hipEventCreate(&c->ring1[slot]));
-  HIP_TRY(c, hipEventRecord(c->ring0[slot], s));
+  if (markers) HIP_TRY(c, hipEventRecord(c->ring0[slot], s));
   return MRIP_OK;
 }
 
-mrip_status record_end(mrip_ctx c, hipStream_t s) {
+// The events the next launch's kernel records around itself.
+KernelEvents kernel_events(mrip_ctx c) {
   const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
-  HIP_TRY(c, hipEventRecord(c->ring1[slot], s));
+  return KernelEvents{c->ring0[slot], c->ring1[slot]};
+}
+
+mrip_status record_end(mrip_ctx c, hipStream_t s, bool markers = true) {
+  const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
+  if (markers) HIP_TRY(c, hipEventRecord(c->ring1[slot], s));
   ++c->launches;
   return MRIP_OK;
 }
@@ -361,8 +383,11 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     if (st != MRIP_OK) return st;
   }
   const bool wave = ctx->mapping == MRIP_MAP_WAVE;
+  // the headline form, one kernel per run, times itself
+  const bool self_timed = kSelfTimedLaunch && ctx->model == MRIP_MM1 && wave && ctx->split > 1 &&
+                          ctx->rng == MRIP_RNG_PHILOX;
 
-  st = record_begin(ctx, s);
+  st = record_begin(ctx, s, !self_timed);
   if (st != MRIP_OK) return st;
   if (ctx->model == MRIP_RW) {
     RwArgs a{};
@@ -419,7 +444,10 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
       if (st != MRIP_OK) return st;
       a.features = (float *)outp[3];
     }
-    if (wave && ctx->split > 1) HIP_TRY(ctx, launch_mm1_split(a, ctx->split, s));
+    if (self_timed) {
+      const KernelEvents ev = kernel_events(ctx);
+      HIP_TRY(ctx, launch_mm1_split(a, ctx->split, s, &ev));
+    } else if (wave && ctx->split > 1) HIP_TRY(ctx, launch_mm1_split(a, ctx->split, s));
     else if (wave) HIP_TRY(ctx, launch_mm1_wave(a, ctx->rpw, ctx->wg, s));
     else HIP_TRY(ctx, launch_mm1_simt(a, ctx->mapping == MRIP_MAP_LANE0, s));
   } else if (ctx->model == MRIP_PI) {
@@ -450,7 +478,7 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
       HIP_TRY(ctx, launch_ff_simt(a, ctx->mapping == MRIP_MAP_LANE0, s));
     }
   }
-  st = record_end(ctx, s);
+  st = record_end(ctx, s, !self_timed);
   if (st != MRIP_OK) return st;
   // all scalar outputs in one reduction launch, written straight into
   // pinned host memory, so mrip_stats only waits for an event

@@ -70,7 +70,13 @@ hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s);
 hipError_t launch_mm1_taus(const Mm1Args &a, uint32_t lanes_per_rep, hipStream_t s);
 // WAVE mapping with each replication split over 2 or 4 wavefronts of a
 // 256-thread workgroup (speculate from carry 0, then correct in order).
-hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s);
+// Events a kernel launch records around the kernel itself (start, stop).
+struct KernelEvents {
+  hipEvent_t start, stop;
+};
+// ev (nullable, Philox only): the kernel records ev->start and ev->stop
+hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s,
+                            const KernelEvents *ev = nullptr);
 // Persistent plan kernel: grid sized to full residency, waves pop work.
 hipError_t launch_mm1_plan(const Mm1Args &a, uint64_t n_items, uint32_t reps_per_wave,
                            uint32_t workgroup, hipStream_t s);

@@ -25,6 +25,8 @@
 // every lane a contiguous run of customers instead (mm1_taus_kernel: one
 // jump per lane, two passes over its run); a SIMT lane reads the stream in
 // order.
+#include <hip/hip_ext.h>
+
 #include "device.hpp"
 #include "kernels.hpp"
 #include "taus.hpp"
@@ -874,19 +876,27 @@ hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t rpw, uint32_t wg, hipStrea
 }
 
 template <int X>
-hipError_t split_launch(const Mm1Args &a, float ca, float cs, hipStream_t s) {
+hipError_t split_launch(const Mm1Args &a, float ca, float cs, hipStream_t s,
+                        const KernelEvents *ev) {
   const uint64_t blocks = (a.n_reps + split_slots<X>() - 1) / split_slots<X>();
-  hipLaunchKernelGGL(mm1_split_kernel<X>, dim3((uint32_t)blocks), dim3(split_wg<X>()), 0, s, a,
-                     ca, cs);
+  const dim3 g((uint32_t)blocks), b(split_wg<X>());
+  if (ev)
+    hipExtLaunchKernelGGL(mm1_split_kernel<X>, g, b, 0, s, ev->start, ev->stop, 0, a, ca, cs);
+  else
+    hipLaunchKernelGGL(mm1_split_kernel<X>, g, b, 0, s, a, ca, cs);
   return hipGetLastError();
 }
 
-hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s) {
-  if (a.rng == RNG_TAUS88) return launch_mm1_taus(a, 64 * waves_per_rep, s);
+hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s,
+                            const KernelEvents *ev) {
+  if (a.rng == RNG_TAUS88) {
+    if (ev) return hipErrorInvalidValue;  // the taus88 form is not self-timed
+    return launch_mm1_taus(a, 64 * waves_per_rep, s);
+  }
   const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
-  if (waves_per_rep == 2) return split_launch<2>(a, ca, cs, s);
-  if (waves_per_rep == 4) return split_launch<4>(a, ca, cs, s);
-  if (waves_per_rep == 8) return split_launch<8>(a, ca, cs, s);
+  if (waves_per_rep == 2) return split_launch<2>(a, ca, cs, s, ev);
+  if (waves_per_rep == 4) return split_launch<4>(a, ca, cs, s, ev);
+  if (waves_per_rep == 8) return split_launch<8>(a, ca, cs, s, ev);
   return hipErrorInvalidValue;
 }
 
