@@ -80,6 +80,22 @@ def rw_slots_per_step(c=SLOT_COST):
     return philox_block_slots(c) / 64 + 8 * c["simple"]
 
 
+def taus88_output_slots(c=SLOT_COST):
+    """One taus88 output: three components of shift, xor, shift, and, shift,
+    xor each, combined by one three-input xor."""
+    return 3 * 6 * c["simple"] + c["simple"]
+
+
+def taus88_slots(model, c=SLOT_COST):
+    """Algorithmic slots per event on taus88 streams: the Philox share of
+    each model's count replaced by its taus88 outputs."""
+    if model == "mm1":  # two outputs per customer
+        return mm1_slots_per_customer(c) - philox_block_slots(c) / 2 + 2 * taus88_output_slots(c)
+    if model == "pi":  # two outputs per point
+        return pi_slots_per_point(c) - philox_block_slots(c) / 2 + 2 * taus88_output_slots(c)
+    return rw_slots_per_step(c) - philox_block_slots(c) / 64 + taus88_output_slots(c) / 16
+
+
 def alu_roofline(events_per_s, slots):
     achieved = events_per_s * slots
     return {"bound": "alu", "slots_per_event": round(slots, 2), "achieved": achieved / 1e12,
@@ -351,8 +367,13 @@ def extras(torch, mrip, inputs):
             ctx.set_split(split)
             v, ms = rate(ctx, 1024, events, runs=2)
             st = ctx.stats(o)
+            slots = {"mm1": mm1_slots_per_customer(), "pi": pi_slots_per_point(),
+                     "rw": rw_slots_per_step()}[name.split("_")[0]]
+            if gname == "taus88":
+                slots = taus88_slots(name.split("_")[0])
             row[gname] = {"kernel_ms": ms, "events_per_s": v, "mean": st["mean"],
-                          "half_width": st["half_width"], "var": st["var"]}
+                          "half_width": st["half_width"], "var": st["var"],
+                          "roofline": alu_roofline(v, slots)}
         a, b = row["philox"], row["taus88"]
         row["z_difference"] = (a["mean"] - b["mean"]) / math.sqrt((a["var"] + b["var"]) / 1024)
         tau[name] = row
