@@ -113,6 +113,8 @@ def parse():
                     help="target thread time (CPU seconds) of the CPU-oracle sample")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with a 256 MiB device-to-device copy (calibrates HBM counters)")
+    ap.add_argument("--full-size-counters", action="store_true",
+                    help="only run each WAVE workload once at its bench size (for counter runs)")
     ap.add_argument("--mapping-counters", action="store_true",
                     help="only run the walk and the forest fire once per mapping (for "
                          "rocprofv3 memory counters, the paper's TLP vs WLP table)")
@@ -144,6 +146,25 @@ def mapping_counters(mrip):
         ctx.run(R, seed=42)
         out["mm1_" + name] = ctx.last_ms()
     print(json.dumps({"mapping_counters_kernel_ms": out}), flush=True)
+
+
+def full_size_counters(mrip):
+    """One WAVE launch of each workload at the size bench.py times it (the
+    walk also at 16384 replications), so that a counter run sees how busy
+    each kernel keeps the vector ALUs at full size."""
+    out = {}
+    runs = (("mm1_1024x1e5", mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), R),
+            ("ff_4096x128x128x2000", mrip.MRIP_FF, mrip.ff_params(128, 2000, 0.01, 1e-5), 4096),
+            ("pi_1024x1e7", mrip.MRIP_PI, mrip.pi_params(10_000_000), 1024),
+            ("rw_32x64x1000", mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), 32),
+            ("rw_16384x64x1000", mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), 16384))
+    for name, model, params, n in runs:
+        ctx = mrip.Context(model, params, mrip.MRIP_MAP_WAVE)
+        if model == mrip.MRIP_MM1:
+            ctx.set_split(SPLIT)
+        ctx.run(n, seed=42)
+        out[name] = ctx.last_ms()
+    print(json.dumps({"full_size_counters_kernel_ms": out}), flush=True)
 
 
 def timed_steps(ctx, steps, warmup, torch, mrip):
@@ -414,6 +435,9 @@ def main():
     mrip.load()
     if args.mapping_counters:
         mapping_counters(mrip)
+        return
+    if args.full_size_counters:
+        full_size_counters(mrip)
         return
 
     ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_WAVE)
