@@ -264,7 +264,9 @@ MRIP_API mrip_status mrip_run_history_ms(mrip_ctx ctx, float *ms, uint32_t max_n
  * different factor levels; here all of them in one persistent launch) */
 
 /* Upload a plan (M/M/1 contexts only). Items keep their index for outputs;
- * the device queue serves them longest-first. Host pointer, n >= 1. */
+ * the device queue serves them longest-first. Host pointer, n >= 1.
+ * Synchronises the context's last stream first (an earlier plan run may
+ * still be reading the items it replaces). */
 MRIP_API mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n);
 
 /* Run every item of the plan in one persistent-kernel launch whose waves

@@ -613,6 +613,8 @@ mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n)
     }
   }
   offsets.push_back(n);
+  // an earlier plan run may still read the item buffers
+  if (ctx->launches > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
   HIP_TRY(ctx, ctx->it_dp.ensure(4 * n));
   HIP_TRY(ctx, ctx->it_rep.ensure(4 * n));
   HIP_TRY(ctx, ctx->it_n.ensure(8 * n));

@@ -24,6 +24,9 @@ struct DevBuf {
   hipError_t ensure(size_t n) {
     if (n <= bytes && p) return hipSuccess;
     if (p) {
+      // work queued earlier may still use the old buffer
+      const hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return e;
       (void)hipFree(p);
       p = nullptr;
       bytes = 0;
