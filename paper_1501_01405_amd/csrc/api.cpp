@@ -196,12 +196,21 @@ mrip_status philox_only(mrip_ctx c) {
 }
 
 mrip_status upload_taus_tables(mrip_ctx c) {
-  if (c->taus_tables.p) return MRIP_OK;
-  std::vector<uint32_t> host((size_t)TAUS_TABLES * TAUS_COLS);
-  taus_build_tables(host.data());
-  HIP_TRY(c, c->taus_tables.ensure(host.size() * sizeof(uint32_t)));
-  HIP_TRY(c, hipMemcpy(c->taus_tables.p, host.data(), host.size() * sizeof(uint32_t),
-                       hipMemcpyHostToDevice));
+  if (!c->taus_tables.p) {
+    std::vector<uint32_t> host((size_t)TAUS_TABLES * TAUS_COLS);
+    taus_build_tables(host.data());
+    HIP_TRY(c, c->taus_tables.ensure(host.size() * sizeof(uint32_t)));
+    HIP_TRY(c, hipMemcpy(c->taus_tables.p, host.data(), host.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice));
+  }
+  if (c->model == MRIP_RW && !c->taus_walk.p) {
+    // the walk's lanes reach their place with one table per level
+    std::vector<uint32_t> host((size_t)TAUS_WALK_TABLES * TAUS_COLS);
+    taus_build_walk_tables(c->rw.steps, host.data());
+    HIP_TRY(c, c->taus_walk.ensure(host.size() * sizeof(uint32_t)));
+    HIP_TRY(c, hipMemcpy(c->taus_walk.p, host.data(), host.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice));
+  }
   return MRIP_OK;
 }
 
@@ -400,6 +409,7 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.distinct = (int32_t *)outp[1];
     a.rng = ctx->rng;
     a.taus = ctx->taus_tables.as<uint32_t>();
+    a.taus_walk = ctx->taus_walk.as<uint32_t>();
     uint64_t chunk = n_reps;  // replications per launch
     if (ctx->rw.walker_sites) {
       const uint64_t bytes = (uint64_t)a.grid * a.grid / 8;  // one bitmap

@@ -112,6 +112,7 @@ struct mrip_ctx_s {
   void *cur[4] = {};
   mrip::DevBuf scratch;
   mrip::DevBuf walker_scratch;  // the walk's per-walker bitmaps
+  mrip::DevBuf taus_walk;       // the walk's taus88 jump tables (its steps are fixed)
   // (n, mean, var) per scalar output: pinned host memory written by the
   // reduction kernel through its device view
   // A ring of STATS_RING slots, one per run, so a caller may read run k's

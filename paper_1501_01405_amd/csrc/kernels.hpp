@@ -26,6 +26,7 @@ struct RwArgs {
   uint32_t *scratch_bitmaps;  // SIMT only: n_reps * grid*grid/32 words
   int rng;
   const uint32_t *taus;
+  const uint32_t *taus_walk;  // taus88: the walk's jump tables (taus_build_walk_tables)
   // per-walker site counts (nullptr = off): output and the walkers' own
   // bitmaps (WAVE: n_reps * walkers * grid*grid/32 words, SIMT: n_reps *
   // grid*grid/32)

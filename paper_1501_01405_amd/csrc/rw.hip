@@ -118,7 +118,7 @@ __global__ void rw_wave_kernel(RwArgs a) {
 
   if (RNG == RNG_TAUS88) {
     Taus t = taus_seed(TAG_RW, 0u, (uint32_t)(a.rep0 + r), k0, k1);
-    taus_skip(t, (uint64_t)w * ((a.steps + 15) / 16), a.taus);
+    taus_jump(t, a.taus_walk + (uint64_t)w * TAUS_COLS);  // to walker w's run
     for (uint32_t g = 0; g < a.steps; g += 16)
       walk16<GRID, true, WB>(taus_next(t), g, a.steps, active, X, Y, bm, spare, wb);
   } else {
@@ -251,7 +251,9 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
   Taus ts;
   if (RNG == RNG_TAUS88) {
     ts = taus_seed(TAG_RW, 0u, (uint32_t)(a.rep0 + r), k0, k1);
-    taus_skip(ts, (uint64_t)w * ((a.steps + 15) / 16) + t0 / 16, a.taus);
+    // to walker w's run, then to this segment's start within it (w <= 63)
+    taus_jump(ts, a.taus_walk + (uint64_t)w * TAUS_COLS);
+    taus_jump(ts, a.taus_walk + (uint64_t)(TAUS_WALK_WALKERS + sgi) * TAUS_COLS);
   }
   const Taus ts0 = ts;
   int dx = 0, dy = 0;

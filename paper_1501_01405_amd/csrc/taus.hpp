@@ -36,6 +36,14 @@ constexpr uint32_t TAG_TAUS_SEED = 5;
 
 // Host: fill `out` (TAUS_TABLES x TAUS_COLS words) with the jump tables.
 void taus_build_tables(uint32_t *out);
+// Host: the walk's jump tables for walks of `steps` moves, so that a lane
+// reaches its place with one table per level instead of one per bit of the
+// distance: table w (w < 64) advances to walker w's run (w ceil(steps/16)
+// outputs), table 64 + s (s < 16) from a walker's run to its segment s
+// (min(steps, s seg) / 16 outputs, seg the segmented form's moves per lane).
+constexpr uint32_t TAUS_WALK_WALKERS = 64, TAUS_WALK_SEGMENTS = 16;
+constexpr uint32_t TAUS_WALK_TABLES = TAUS_WALK_WALKERS + TAUS_WALK_SEGMENTS;
+void taus_build_walk_tables(uint32_t steps, uint32_t *out);
 
 #if defined(__HIPCC__)
 struct Taus {

@@ -5,6 +5,7 @@
 // square of one step).
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "taus.hpp"
@@ -58,14 +59,50 @@ void store(const Mat (&m)[3], uint32_t *table) {
     for (int b = 0; b < m[c].k; ++b) table[o++] = m[c].col[b];
 }
 
+struct Pow2 {
+  Mat m[TAUS_POW2][3];
+  Pow2() {
+    for (int c = 0; c < 3; ++c) m[0][c] = one_step(kComp[c]);
+    for (int j = 1; j < TAUS_POW2; ++j)
+      for (int c = 0; c < 3; ++c) m[j][c] = compose(m[j - 1][c], m[j - 1][c]);
+  }
+};
+
+const Pow2 &pow2() {
+  static const Pow2 p;
+  return p;
+}
+
+// the table that advances d outputs (the product of the powers of two in d)
+void store_jump(uint64_t d, uint32_t *out) {
+  const Pow2 &p = pow2();
+  Mat r[3];
+  for (int c = 0; c < 3; ++c) {
+    r[c].k = kComp[c].k;
+    for (int b = 0; b < r[c].k; ++b) r[c].col[b] = 1u << (32 - r[c].k + b);  // identity
+  }
+  for (int j = 0; d != 0; ++j, d >>= 1)
+    if (d & 1u)
+      for (int c = 0; c < 3; ++c) r[c] = compose(p.m[j][c], r[c]);
+  store(r, out);
+}
+
 }  // namespace
 
 void taus_build_tables(uint32_t *out) {
-  Mat pow2[TAUS_POW2][3];
-  for (int c = 0; c < 3; ++c) pow2[0][c] = one_step(kComp[c]);
-  for (int j = 1; j < TAUS_POW2; ++j)
-    for (int c = 0; c < 3; ++c) pow2[j][c] = compose(pow2[j - 1][c], pow2[j - 1][c]);
-  for (int j = 0; j < TAUS_POW2; ++j) store(pow2[j], out + (size_t)j * TAUS_COLS);
+  const Pow2 &p = pow2();
+  for (int j = 0; j < TAUS_POW2; ++j) store(p.m[j], out + (size_t)j * TAUS_COLS);
+}
+
+void taus_build_walk_tables(uint32_t steps, uint32_t *out) {
+  const uint64_t per_walker = (steps + 15u) / 16u;                    // outputs of one walker
+  const uint64_t seg = (steps + 16u * 64u - 1u) / (16u * 64u) * 64u;  // moves per segment
+  for (uint32_t w = 0; w < TAUS_WALK_WALKERS; ++w)
+    store_jump(w * per_walker, out + (size_t)w * TAUS_COLS);
+  for (uint32_t s = 0; s < TAUS_WALK_SEGMENTS; ++s) {
+    const uint64_t t0 = std::min<uint64_t>(steps, s * seg);
+    store_jump(t0 / 16, out + (size_t)(TAUS_WALK_WALKERS + s) * TAUS_COLS);
+  }
 }
 
 }  // namespace mrip

@@ -169,3 +169,18 @@ def test_philox_only_paths_refuse_taus88(gpu):
         ctx.set_split(8)
     ctx.set_rng(mrip.MRIP_RNG_PHILOX)
     ctx.set_split(8)  # back on Philox, splitting over 8 is allowed again
+
+
+@pytest.mark.parametrize("steps", [1024, 1025, 2000])
+@pytest.mark.parametrize("R", [7, 2100])
+def test_rw_long_walks_in_both_wave_forms(gpu, steps, R):
+    # segments of 128 moves (steps > 1024), trailing segments that start at
+    # or past the last move, and the one-lane-per-walker form above 2048
+    # replications: each lane reaches its place with one jump per level
+    announce("rw taus88 long walks", steps, R)
+    ctx = _ctx(mrip.MRIP_RW, mrip.rw_params(64, 64, steps), WAVE)
+    ctx.run(R, seed=9)
+    ids = sorted({0, R // 2, R - 1})
+    ref = core.rw_many(9, ids, 64, 64, steps, threads=core.default_threads(), rng="taus88")
+    assert np.array_equal(ctx.output(0).cpu().numpy()[ids], ref[0])
+    assert np.array_equal(ctx.output(1).cpu().numpy()[ids], ref[1])
