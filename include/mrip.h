@@ -206,7 +206,8 @@ MRIP_API mrip_status mrip_set_split(mrip_ctx ctx, uint32_t waves_per_rep);
  * or 4 wavefronts with mrip_set_split) a contiguous run of customers.
  * MRIP_E_UNSUPPORTED for the forest fire, for splits over 8 wavefronts, and
  * for later plan or control-variate calls on the context (those use
- * Philox). Builds and uploads the generator's jump tables (22.5 KB) once,
+ * Philox). Builds and uploads the generator's jump tables (22.5 KB; for a
+ * walk context also 28 KB of per-walker and per-segment tables) once,
  * synchronously. Default PHILOX. */
 MRIP_API mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng);
 
