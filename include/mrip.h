@@ -215,7 +215,11 @@ MRIP_API mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng);
 
 /* Run replications 0..n_reps-1 with key `seed` (paper section 1: MRIP),
  * then reduce every scalar output over replications in fp64 on the device.
- * Asynchronous on hip_stream. */
+ * Asynchronous on hip_stream. One launch holds fewer than 2^32 lanes:
+ * n_reps times the lanes of a replication (1 in SIMT; 64 in LANE0 and
+ * WAVE, 64 / reps_per_wave with mrip_set_shape, 64 x waves_per_rep with
+ * mrip_set_split) must stay below 2^32 - 1024, else MRIP_E_INVAL (about
+ * 67 million replications per call in WAVE). */
 MRIP_API mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_stream);
 
 /* Mean, unbiased variance and Student-t interval of output `output` of the

@@ -370,10 +370,22 @@ mrip_status mrip_get_shape(mrip_ctx ctx, uint32_t *rpw, uint32_t *wg, uint32_t *
   return MRIP_OK;
 }
 
+// Lanes one replication occupies in its launch (a launch holds < 2^32).
+uint64_t lanes_per_rep(mrip_ctx c) {
+  if (c->mapping == MRIP_MAP_SIMT) return 1;
+  if (c->mapping == MRIP_MAP_LANE0) return 64;
+  if (c->model == MRIP_MM1 && c->split > 1) return 64ull * c->split;
+  if (c->model == MRIP_MM1 && c->rpw > 1) return 64ull / c->rpw;
+  return 64;
+}
+
 mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_stream) {
   if (!ctx) return MRIP_E_INVAL;
   if (n_reps == 0) return inval(ctx, "n_reps must be >= 1");
   if (n_reps > 0xFFFFFFFFull) return inval(ctx, "n_reps must be < 2^32");
+  if (n_reps * lanes_per_rep(ctx) > 0xFFFFFFFFull - 1024)
+    return inval(ctx, "too many replications for one launch of this mapping "
+                      "(replications x lanes per replication must stay below 2^32 - 1024)");
   hipStream_t s = (hipStream_t)hip_stream;
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;

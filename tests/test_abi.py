@@ -106,6 +106,11 @@ def test_calls_out_of_order_and_bad_shapes():
     assert L.mrip_set_split(ctx, 8) == mrip.MRIP_OK
     assert L.mrip_set_split(ctx, 16) == mrip.MRIP_E_INVAL
     assert L.mrip_set_split(ctx, 4) == mrip.MRIP_OK
+    # a launch holds < 2^32 lanes: 2^24 replications x 256 lanes is refused
+    # before any device call
+    assert L.mrip_run(ctx, 1 << 24, 42, None) == mrip.MRIP_E_INVAL
+    assert b"lanes" in L.mrip_last_error(ctx)
+    assert L.mrip_run(ctx, 1 << 32, 42, None) == mrip.MRIP_E_INVAL
     assert L.mrip_set_shape(ctx, 2, 256) == mrip.MRIP_E_INVAL
     assert L.mrip_run_plan(ctx, 42, None) == mrip.MRIP_E_STATE
     assert L.mrip_plan_stats(ctx, 0, 0.95, C.byref(s)) == mrip.MRIP_E_STATE
