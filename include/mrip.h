@@ -406,15 +406,15 @@ MRIP_API mrip_status mrip_cv_times(mrip_ctx ctx, float *full_ms, float *prefix_m
 /* ------------------------------------------------------------ utilities */
 
 /* Raw Philox4x32-10 blocks: out_dev[4i..4i+3] = Philox(ctr_dev[4i..4i+3],
- * key = seed). Device pointers, n blocks. */
+ * key = seed). Device pointers, n blocks, n <= 2^32 - 256. */
 MRIP_API mrip_status mrip_philox(uint64_t seed, const uint32_t *ctr_dev, uint64_t n, uint32_t *out_dev,
                         void *hip_stream);
 
 /* Raw taus88 outputs: out_dev[i] = output skip + i of the Random Spacing
  * stream of (model tag, dp, rep) under `seed` (see mrip_rng), each reached by
  * jumping from the stream's start with the generator's power-of-two jump
- * tables. Device pointer, n values. Allocates the tables for the call and
- * synchronises the stream before freeing them. */
+ * tables. Device pointer, n values, n <= 2^32 - 256. Allocates the tables
+ * for the call and synchronises the stream before freeing them. */
 MRIP_API mrip_status mrip_taus88(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep,
                                  uint64_t skip, uint64_t n, uint32_t *out_dev, void *hip_stream);
 

@@ -875,10 +875,13 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
 
 // ------------------------------------------------------------- utilities
 
+// one lane per value: a dump launch holds fewer than 2^32 lanes
+constexpr uint64_t kDumpMax = 0xFFFFFF00ull;
+
 mrip_status mrip_taus88(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep, uint64_t skip,
                         uint64_t n, uint32_t *out_dev, void *hip_stream) {
   if (n == 0) return MRIP_OK;
-  if (!out_dev || n > 0xFFFFFFFFull * 256) return MRIP_E_INVAL;
+  if (!out_dev || n > kDumpMax) return MRIP_E_INVAL;
   std::vector<uint32_t> host((size_t)TAUS_TABLES * TAUS_COLS);
   taus_build_tables(host.data());
   DevBuf tables;
@@ -897,6 +900,7 @@ mrip_status mrip_taus88(uint64_t seed, uint32_t model, uint32_t dp, uint32_t rep
 mrip_status mrip_philox(uint64_t seed, const uint32_t *ctr_dev, uint64_t n, uint32_t *out_dev,
                         void *hip_stream) {
   if (n > 0 && (!ctr_dev || !out_dev)) return MRIP_E_INVAL;
+  if (n > kDumpMax) return MRIP_E_INVAL;
   hipError_t e = launch_philox_dump(seed, ctr_dev, n, out_dev, (hipStream_t)hip_stream);
   return e == hipSuccess ? MRIP_OK : MRIP_E_HIP;
 }

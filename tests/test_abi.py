@@ -135,6 +135,10 @@ def test_generator_choice_checks():
     L.mrip_destroy(ctx)
     assert L.mrip_taus88(1, 4, 0, 0, 0, 0, None, None) == mrip.MRIP_OK  # n = 0: nothing to do
     assert L.mrip_taus88(1, 4, 0, 0, 0, 5, None, None) == mrip.MRIP_E_INVAL
+    # one lane per value: 2^32 - 255 values would not fit one launch
+    fake = C.cast(C.c_void_p(256), C.POINTER(C.c_uint32))
+    assert L.mrip_taus88(1, 4, 0, 0, 0, 2**32 - 255, fake, None) == mrip.MRIP_E_INVAL
+    assert L.mrip_philox(1, fake, 2**32 - 255, fake, None) == mrip.MRIP_E_INVAL
 
 
 def test_bind_output_and_resume_checks():
