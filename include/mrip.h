@@ -328,7 +328,7 @@ MRIP_API mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_i
 
 /* Forward pass of the 10-128-128-1 ReLU network, bf16 operands with fp32
  * accumulation. theta_dev: MRIP_MLP_PARAMS fp32; x_dev: n x 10 fp32
- * (normalised features); y_dev: n fp32. */
+ * (normalised features); y_dev: n fp32; n < 2^30. */
 MRIP_API mrip_status mrip_mlp_forward(const float *theta_dev, const float *x_dev, uint64_t n,
                              float *y_dev, void *hip_stream);
 
@@ -338,7 +338,7 @@ MRIP_API mrip_status mrip_mlp_grad(const float *theta_dev, const float *x_dev, c
                           uint64_t n, float *grad_dev, float *loss_dev, void *hip_stream);
 
 /* One Adam step (Kingma and Ba 2015, Algorithm 1) on fp32 weights;
- * `step` counts from 1. */
+ * `step` counts from 1; n_params <= 2^32 - 256. */
 MRIP_API mrip_status mrip_adam_step(float *theta_dev, float *m_dev, float *v_dev, const float *grad_dev,
                            uint64_t n_params, uint64_t step, float lr, float beta1, float beta2,
                            float eps, void *hip_stream);

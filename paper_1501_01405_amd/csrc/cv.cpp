@@ -157,6 +157,7 @@ extern "C" {
 mrip_status mrip_mlp_forward(const float *theta_dev, const float *x_dev, uint64_t n, float *y_dev,
                              void *hip_stream) {
   if (n > 0 && (!theta_dev || !x_dev || !y_dev)) return MRIP_E_INVAL;
+  if (n >= (1ull << 30)) return MRIP_E_INVAL;  // 4 lanes per row: one launch < 2^32 lanes
   hipError_t e = launch_mlp_forward(theta_dev, x_dev, n, y_dev, 1.0f, 0.0f, (hipStream_t)hip_stream);
   return e == hipSuccess ? MRIP_OK : MRIP_E_HIP;
 }
@@ -183,6 +184,7 @@ mrip_status mrip_adam_step(float *theta_dev, float *m_dev, float *v_dev, const f
                            float eps, void *hip_stream) {
   if (step == 0 || (n_params > 0 && (!theta_dev || !m_dev || !v_dev || !grad_dev)))
     return MRIP_E_INVAL;
+  if (n_params > 0xFFFFFF00ull) return MRIP_E_INVAL;  // one lane per parameter
   hipError_t e = launch_adam(theta_dev, m_dev, v_dev, grad_dev, n_params,
                              adam_args(lr, beta1, beta2, eps, step), (hipStream_t)hip_stream);
   return e == hipSuccess ? MRIP_OK : MRIP_E_HIP;

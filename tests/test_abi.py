@@ -139,6 +139,9 @@ def test_generator_choice_checks():
     fake = C.cast(C.c_void_p(256), C.POINTER(C.c_uint32))
     assert L.mrip_taus88(1, 4, 0, 0, 0, 2**32 - 255, fake, None) == mrip.MRIP_E_INVAL
     assert L.mrip_philox(1, fake, 2**32 - 255, fake, None) == mrip.MRIP_E_INVAL
+    assert L.mrip_mlp_forward(fake, fake, 2**30, fake, None) == mrip.MRIP_E_INVAL
+    assert L.mrip_adam_step(fake, fake, fake, fake, 2**32, 1, 1e-3, 0.9, 0.999, 1e-8,
+                            None) == mrip.MRIP_E_INVAL
 
 
 def test_bind_output_and_resume_checks():
