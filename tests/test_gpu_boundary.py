@@ -121,3 +121,22 @@ def test_runs_on_two_streams_share_scratch_in_order(gpu):
     ssd, distinct = core.rw_many(2, ids, W, G, T, threads=2)
     assert np.array_equal(got[0][ids], ssd)
     assert np.array_equal(got[1][ids], distinct)
+
+
+def test_kernel_times_of_self_timed_and_marked_launches(gpu):
+    # the split M/M/1 launch records its timing events from its own
+    # dispatch, the other launches between stream markers; a context that
+    # alternates them keeps one history, oldest first, and its statistics
+    announce("kernel timing history")
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 50000), WAVE)
+    expect = []
+    for k, split in enumerate((4, 1, 4, 2, 1)):
+        ctx.set_split(split)
+        ctx.run(64 + k, seed=k)
+        ms = ctx.last_ms()
+        assert 0.0 < ms < 1000.0
+        expect.append(ms)
+        assert ctx.stats(0)["n"] == 64 + k
+    hist = ctx.history_ms(16)
+    assert len(hist) == 5
+    assert np.allclose(hist, expect)
