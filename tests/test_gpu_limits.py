@@ -61,3 +61,26 @@ def test_pi_at_the_largest_point_count(gpu):
     assert np.array_equal(est, (4.0 * hits / N).astype(np.float32))
     with pytest.raises(mrip.MripError):
         mrip.Context(mrip.MRIP_PI, mrip.pi_params(N + 1), WAVE)
+
+
+def test_mm1_beyond_2_32_customers(gpu):
+    # the largest runs the parameters allow are < 2^33 customers: here
+    # 2^32 + 4097 (customer indices past 32 bits, draw blocks up to 2^31),
+    # two replications split over 8 and over 4 wavefronts. The oracle would
+    # need minutes, so: the two splits agree (same per-customer values) and
+    # the means match the closed forms at rho = 0.5 (Wq = 1, idle per
+    # arrival (1 - rho) / lambda = 1), far inside the sampling error at
+    # this length
+    announce("mm1 2^32 + 4097 customers")
+    N = (1 << 32) + 4097
+    outs = {}
+    for split in (8, 4):
+        ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.5, 1.0, N), WAVE)
+        ctx.set_split(split)
+        ctx.run(2, seed=31)
+        outs[split] = np.stack([ctx.output(o).cpu().numpy() for o in range(3)], axis=1)
+    assert np.all(np.abs(outs[8] - outs[4]) <= 1e-6 * np.abs(outs[4]))
+    wq, t, idle = outs[8][:, 0], outs[8][:, 1], outs[8][:, 2]
+    assert np.all(np.abs(wq - 1.0) < 0.01)
+    assert np.all(np.abs(t - 2.0) < 0.01)
+    assert np.all(np.abs(idle - 1.0) < 0.01)
