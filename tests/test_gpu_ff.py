@@ -54,3 +54,19 @@ def test_ff_simt_matches_wave(gpu):
     _, a = _run(WAVE, 128, 300, 200, 0.01, 1e-4)
     _, b = _run(SIMT, 128, 300, 200, 0.01, 1e-4)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("grid,p,f", [(256, 0.05, 1e-3), (224, 1.0, 0.0), (32, 0.0, 1.0),
+                                      (64, 1.0, 1.0)])
+def test_ff_edges(gpu, grid, p, f):
+    # the largest SIMT grid, and probabilities at their ends: p = 1 grows a
+    # full forest every other step, f = 1 lights every tree, p = 0 never
+    # grows (burnt = 0); both mappings where the grid allows
+    announce("ff edges", grid, p, f)
+    R, T = 6, 40
+    ref = core.ff_many(7, R, grid, T, p, f, threads=core.default_threads())
+    for mapping in ((SIMT, WAVE) if grid in (64, 128) else (SIMT,)):
+        _, got = _run(mapping, grid, T, R, p, f, seed=7)
+        assert np.array_equal(got, ref), mapping
+    if p == 0.0:
+        assert np.all(ref == 0)
