@@ -410,11 +410,22 @@ def extras(torch, mrip, inputs):
         ctx.run_plan(42 + i)
         ms.append(ctx.last_ms())
     total = float(items["customers"].sum())
+    # the same plan in the thread-per-replication forms (every working lane
+    # pops its own items)
+    thread_forms = {}
+    for name, mp in (("simt", mrip.MRIP_MAP_SIMT), ("lane0", mrip.MRIP_MAP_LANE0)):
+        c = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), mp)
+        c.plan_set(items)
+        c.run_plan(42)
+        t_ms = c.last_ms()
+        thread_forms[name] = {"kernel_ms": t_ms, "customers_per_s": total / (t_ms * 1e-3)}
     out["plan_64x32"] = {"customers": total, "kernel_ms": min(ms),
                          "customers_per_s": total / (min(ms) * 1e-3),
                          "roofline": alu_roofline(total / (min(ms) * 1e-3),
                                                   mm1_slots_per_customer()),
                          "tuned_shape": {"reps_per_wave": rpw, "workgroup": wg},
+                         "thread_forms": thread_forms,
+                         "wave_over_simt": thread_forms["simt"]["kernel_ms"] / min(ms),
                          "longest_item": int(items["customers"].max())}
     return out
 

@@ -276,7 +276,10 @@ MRIP_API mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, ui
 
 /* Run every item of the plan in one persistent-kernel launch whose waves
  * pop work from a device queue, then reduce per design point. Outputs are
- * indexed like the uploaded items. Asynchronous. */
+ * indexed like the uploaded items. Asynchronous. In the SIMT and LANE0
+ * mappings every working lane pops its own items (the thread-per-
+ * replication form, where a wavefront runs as long as its longest item);
+ * an item's values equal those of a standalone run in the same mapping. */
 MRIP_API mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream);
 
 /* Resume a plan (section 1: an experimental plan is a set of replication

@@ -705,6 +705,8 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
   if (st != MRIP_OK) return st;
   if (n == 0) {
     // nothing left to simulate (a resumed plan): only the reductions run
+  } else if (ctx->mapping != MRIP_MAP_WAVE) {
+    HIP_TRY(ctx, launch_mm1_plan_simt(a, n, ctx->mapping == MRIP_MAP_LANE0, s));
   } else if (split > 1 && n_long > 0) {
     HIP_TRY(ctx, launch_mm1_plan_split(a, n, n_long, split, rpw, s));
   } else {
@@ -733,8 +735,6 @@ mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
   if (!ctx) return MRIP_E_INVAL;
   if (philox_only(ctx) != MRIP_OK) return MRIP_E_UNSUPPORTED;
   if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
-  if (ctx->mapping != MRIP_MAP_WAVE)
-    return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
   const uint64_t n_long = count_long(ctx->lpt_customers, ctx->n_items, ctx->long_min);
   mrip_status st = run_plan_impl(ctx, seed, (hipStream_t)hip_stream, ctx->it_order.as<uint32_t>(),
                                  ctx->n_items, n_long, ctx->rpw, ctx->wg, ctx->plan_split, true);
@@ -749,8 +749,6 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
   if (!ctx) return MRIP_E_INVAL;
   if (philox_only(ctx) != MRIP_OK) return MRIP_E_UNSUPPORTED;
   if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
-  if (ctx->mapping != MRIP_MAP_WAVE)
-    return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
   if (!skip_done) return mrip_run_plan(ctx, seed, hip_stream);
   hipStream_t s = (hipStream_t)hip_stream;
   // the remaining items, still longest first

@@ -79,6 +79,8 @@ struct KernelEvents {
 hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s,
                             const KernelEvents *ev = nullptr);
 // Persistent plan kernel: grid sized to full residency, waves pop work.
+// plan in the SIMT (one_lane = false) or one-working-lane form
+hipError_t launch_mm1_plan_simt(const Mm1Args &a, uint64_t n_items, bool one_lane, hipStream_t s);
 hipError_t launch_mm1_plan(const Mm1Args &a, uint64_t n_items, uint32_t reps_per_wave,
                            uint32_t workgroup, hipStream_t s);
 // Plan kernel whose first n_long items (longest first) are each split over

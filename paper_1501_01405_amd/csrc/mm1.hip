@@ -27,6 +27,8 @@
 // order.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "kernels.hpp"
 #include "taus.hpp"
@@ -765,18 +767,17 @@ __global__ __launch_bounds__(256) void mm1_plan_split_kernel(Mm1Args a, uint64_t
 
 // STRIDE = 1: one replication per lane; 64: one working lane per wavefront
 // (the paper's WLP form).
-template <int STRIDE, int RNG>
-__global__ void mm1_simt_kernel(Mm1Args a, float ca, float cs) {
-  if (threadIdx.x % STRIDE) return;
-  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
-  if (r >= a.n_reps) return;
-  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-  const uint64_t N = a.customers, K = a.feature_prefix;
+// One replication by Lindley's recursion, customer after customer, in one
+// lane (the thread-per-replication form).
+template <int RNG>
+__device__ void simt_replication(const Rep &d, uint64_t K, uint32_t k0, uint32_t k1,
+                                 const Mm1Args &a) {
+  const uint64_t N = d.n;
   float tprev = 0.0f;
   Kahan sw, st, si;
   Feat ft;
   Taus ts;
-  if (RNG == RNG_TAUS88) ts = taus_seed(TAG_MM1, 0u, (uint32_t)r, k0, k1);
+  if (RNG == RNG_TAUS88) ts = taus_seed(TAG_MM1, d.dp, d.rep, k0, k1);
   for (uint64_t k = 0; 2 * k < N; ++k) {
     Block4 b;
     if (RNG == RNG_TAUS88) {
@@ -785,14 +786,14 @@ __global__ void mm1_simt_kernel(Mm1Args a, float ca, float cs) {
       b.z = taus_next(ts);
       b.w = taus_next(ts);
     } else {
-      b = philox((uint32_t)k, 0u, (uint32_t)r, TAG_MM1, k0, k1);
+      b = philox((uint32_t)k, d.dp, d.rep, TAG_MM1, k0, k1);
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const uint64_t n = 2 * k + h;
       if (n >= N) break;
-      const float A = exp_variate(h ? b.z : b.x, ca);
-      const float Sv = exp_variate(h ? b.w : b.y, cs);
+      const float A = exp_variate(h ? b.z : b.x, d.ca);
+      const float Sv = exp_variate(h ? b.w : b.y, d.cs);
       const float W = fmaxf(0.0f, tprev - A);
       const float I = fmaxf(0.0f, A - tprev);
       const float T = W + Sv;
@@ -813,14 +814,14 @@ __global__ void mm1_simt_kernel(Mm1Args a, float ca, float cs) {
     }
   }
   const float nf = (float)N;
-  a.mean_w[r] = sw.value() / nf;
-  a.mean_t[r] = st.value() / nf;
-  a.mean_i[r] = si.value() / nf;
+  a.mean_w[d.out] = sw.value() / nf;
+  a.mean_t[d.out] = st.value() / nf;
+  a.mean_i[d.out] = si.value() / nf;
   if (K > 0) {
     const float kf = (float)K;
-    float *f = a.features + r * 10;
-    f[0] = a.lambda / a.mu;
-    f[1] = a.mu;
+    float *f = a.features + d.out * 10;
+    f[0] = d.lambda / d.mu;
+    f[1] = d.mu;
     f[2] = ft.sa / kf;
     f[3] = ft.ss / kf;
     f[4] = ft.sw / kf;
@@ -829,6 +830,32 @@ __global__ void mm1_simt_kernel(Mm1Args a, float ca, float cs) {
     f[7] = ft.wmax;
     f[8] = ft.si / kf;
     f[9] = ft.tlast;
+  }
+}
+
+// STRIDE = 1: one replication per lane. STRIDE = 64: one per wavefront with
+// only its first lane working (the paper's WLP form).
+template <int STRIDE, int RNG>
+__global__ void mm1_simt_kernel(Mm1Args a, float ca, float cs) {
+  if (threadIdx.x % STRIDE) return;
+  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / STRIDE;
+  if (r >= a.n_reps) return;
+  simt_replication<RNG>(uniform_rep(a, r, ca, cs), a.feature_prefix, (uint32_t)a.seed,
+                        (uint32_t)(a.seed >> 32), a);
+}
+
+// A plan in the thread-per-replication form: every working lane pops the
+// next item of the longest-first order from the device queue and runs it
+// alone, until the queue is empty (each lane's exit is its own; the grid
+// drains once every lane has seen the queue exhausted).
+template <int STRIDE>
+__global__ void mm1_plan_simt_kernel(Mm1Args a, uint64_t n_items) {
+  if (threadIdx.x % STRIDE) return;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  for (;;) {
+    const uint32_t slot = atomicAdd(a.queue_head, 1u);
+    if (slot >= n_items) break;
+    simt_replication<RNG_PHILOX>(item_rep(a, slot, n_items), a.feature_prefix, k0, k1, a);
   }
 }
 
@@ -913,6 +940,22 @@ hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s) {
     if (one_lane) hipLaunchKernelGGL((mm1_simt_kernel<64, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
     else hipLaunchKernelGGL((mm1_simt_kernel<1, RNG_PHILOX>), g, b, 0, s, a, ca, cs);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_mm1_plan_simt(const Mm1Args &a, uint64_t n_items, bool one_lane,
+                                hipStream_t s) {
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  // working lanes: at most one per item, at most a wavefront per SIMD's worth
+  const uint64_t lanes = std::min<uint64_t>(n_items, (uint64_t)cus * 4 * 64);
+  const uint64_t threads = lanes * (one_lane ? 64 : 1);
+  const dim3 g((uint32_t)((threads + 63) / 64)), b(64);
+  if (one_lane) hipLaunchKernelGGL(mm1_plan_simt_kernel<64>, g, b, 0, s, a, n_items);
+  else hipLaunchKernelGGL(mm1_plan_simt_kernel<1>, g, b, 0, s, a, n_items);
   return hipGetLastError();
 }
 

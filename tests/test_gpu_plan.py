@@ -1,10 +1,11 @@
-"""The persistent plan kernel against the oracle: every item within 1e-5 of
+"""The persistent plan kernels against the oracle: every item within 1e-5 of
 its standalone oracle run, per-design-point statistics, item == standalone
-GPU run, and invariance over the autotuner's shapes."""
+GPU run, invariance over the autotuner's shapes, and the thread-per-
+replication forms (SIMT, one working lane) of the same plans."""
 import numpy as np
 import pytest
 
-from gpu_util import WAVE, announce, rel_err
+from gpu_util import LANE0, SIMT, WAVE, announce, rel_err
 from oracle import core
 from oracle import stats as ostats
 from paper_1501_01405_amd import inputs, mrip
@@ -104,3 +105,38 @@ def test_plan_shape_invariance_and_autotune(gpu):
     assert ctx.shape()["plan_split"] in (1, 2, 4)
     ctx.run_plan(42)
     assert rel_err(ctx.output(0, n=len(items)).cpu().numpy(), base).max() <= 1e-6
+
+
+@pytest.mark.parametrize("mapping", [SIMT, LANE0])
+def test_plan_thread_forms_match_oracle(gpu, mapping):
+    # every working lane pops its own items; K > 0 also checks the features
+    items = inputs.plan_table(n_dp=8, reps=8, n_lo=1000, n_hi=20000, seed=3)
+    announce("plan thread form", mapping, len(items))
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 100000, 500), mapping)
+    ctx.plan_set(items)
+    ctx.run_plan(42)
+    got = np.stack([ctx.output(o, n=len(items)).cpu().numpy() for o in range(3)], axis=1)
+    ref, rfeat = core.mm1_items(42, _items_tuple(items), features=500,
+                                threads=core.default_threads())
+    assert rel_err(got, ref).max() <= 1e-5
+    feat = ctx.output(3, n=len(items)).cpu().numpy()
+    cont = [0, 1, 2, 3, 4, 5, 7, 8, 9]
+    assert rel_err(feat[:, cont], rfeat[:, cont]).max() <= 1e-5
+    assert np.abs(feat[:, 6] - rfeat[:, 6]).max() <= 2.0 / 500
+    for dp in range(8):
+        st = ctx.plan_stats(dp)
+        e = ostats.summarize(got[items["dp"] == dp, 0])
+        assert st["n"] == 8 and abs(st["mean"] - e["mean"]) <= 1e-12 * e["mean"]
+
+
+@pytest.mark.parametrize("mapping", [SIMT, LANE0])
+def test_plan_thread_form_item_equals_standalone_run(gpu, mapping):
+    announce("plan thread form item == standalone", mapping)
+    items = inputs.uniform_items(1, 40, 5000, [0.9])
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), mapping)
+    ctx.plan_set(items)
+    ctx.run_plan(42)
+    got = ctx.output(0, n=40).cpu().numpy()
+    solo = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 5000), mapping)
+    solo.run(40, seed=42)
+    assert np.array_equal(got, solo.output(0).cpu().numpy())
