@@ -316,7 +316,7 @@ MRIP_API mrip_status mrip_get_shape(mrip_ctx ctx, uint32_t *reps_per_wave, uint3
  * evenly strided slice of `calib_items` items of its longest-first order,
  * 0 = all); keep the fastest as the context's plan shape and report its
  * reps_per_wave, workgroup and time (mrip_get_shape gives the split).
- * Synchronises. */
+ * WAVE contexts only (MRIP_E_UNSUPPORTED otherwise). Synchronises. */
 MRIP_API mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, void *hip_stream,
                           uint32_t *best_rpw, uint32_t *best_workgroup, float *best_ms);
 

@@ -810,7 +810,7 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
   if (philox_only(ctx) != MRIP_OK) return MRIP_E_UNSUPPORTED;
   if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
   if (ctx->mapping != MRIP_MAP_WAVE)
-    return (ctx->err = "the plan kernel uses the WAVE mapping"), MRIP_E_UNSUPPORTED;
+    return (ctx->err = "the autotuner times the WAVE plan shapes"), MRIP_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)hip_stream;
   const uint32_t *order = ctx->it_order.as<uint32_t>();
   uint64_t n = ctx->n_items;
