@@ -353,6 +353,13 @@ def extras(torch, mrip, inputs):
     ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), mrip.MRIP_MAP_LANE0)
     v, ms = rate(ctx, R, R * N, runs=2)
     out["mm1_lane0"] = {"customers_per_s": v, "kernel_ms": ms}
+    # the M/M/1 replication sweep (10^4 customers each) in the three mappings
+    msweep = {}
+    for name, mp in maps:
+        ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, 10_000), mp)
+        for n in (1, 8, 32, 64, 256, 1024, 4096, 16384):
+            msweep.setdefault(str(n), {})[name] = rate(ctx, n, n * 10_000, runs=2)[1]
+    out["mm1_sweep_1e4_kernel_ms"] = msweep
 
     # forest fire: 4096 reps x 128^2 x 2000 steps
     ev = 4096 * 128 * 128 * 2000
