@@ -16,7 +16,9 @@
  *   philox   -- two independent Philox4x32-10 implementations (PyTorch's and
  *               rocRAND's engines) on >=1e4 random (key, counter) pairs.
  *   rw       -- E[ssd] = W*T (unbiased lattice walk, MSD = t), parity of ssd,
- *               exact distinct-site distribution by 4^T enumeration.
+ *               exact distinct-site distribution by 4^T enumeration; the
+ *               per-walker site counts hand-traced and equal to the sum of
+ *               one-walker runs.
  *   mm1      -- M/M/1 closed form Wq = rho/(mu-lambda), a hand-traced case,
  *               an independent absolute-clock event simulation, degenerate
  *               inputs (S == 0, A == 0).
