@@ -22,11 +22,11 @@ sys.path.insert(0, ROOT)
 
 R, N, LAM, MU = 1024, 100000, 0.9, 1.0
 SPLIT = 4  # wavefronts per replication (four per SIMD at 1024 replications)
-# HBM bytes per launch of mm1_split_kernel<SPLIT> from rocprofv3 FETCH_SIZE and
+# HBM bytes per launch of mm1_split_kernel<4, false> from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by the same counter on a 256 MiB copy
 # (profiles/mm1_split_hbm_counters.md); to be re-measured (or set to None)
 # whenever the kernel changes.
-TRAFFIC_BYTES = (149.0 * 2.00 + 96.0 * 1.00) * 1024
+TRAFFIC_BYTES = (122.5 * 2.00 + 96.0 * 1.00) * 1024  # taken at SPLIT = 4
 # Peak vector issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, the rate
 # behind the published fp32 vector figure (157.3 TFLOP/s counts an FMA as 2).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
@@ -105,8 +105,10 @@ def alu_roofline(events_per_s, slots):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=300,
+                    help="untimed steps first, back to back like the timed ones: the GPU "
+                         "reaches its sustained clock after ~20 ms of continuous work")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary configs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
@@ -115,6 +117,8 @@ def parse():
                     help="end with a 256 MiB device-to-device copy (calibrates HBM counters)")
     ap.add_argument("--full-size-counters", action="store_true",
                     help="only run each WAVE workload once at its bench size (for counter runs)")
+    ap.add_argument("--split", type=int, default=SPLIT, choices=(2, 4, 8),
+                    help="wavefronts per replication of the headline M/M/1 kernel")
     ap.add_argument("--mapping-counters", action="store_true",
                     help="only run the walk and the forest fire once per mapping (for "
                          "rocprofv3 memory counters, the paper's TLP vs WLP table)")
@@ -173,8 +177,14 @@ def timed_steps(ctx, steps, warmup, torch, mrip):
     run's statistics in its own slot), so the device does not wait for the
     host between steps; every step's interval is still read."""
     stream = torch.cuda.current_stream().cuda_stream
+    # warm-up in the same pipelined form: under continuous work the kernel
+    # settles within ~20 ms (about 130 runs) at its sustained speed, 5-10 %
+    # faster than in the first milliseconds
     for i in range(warmup):
         ctx.run(R, seed=1000 + i, stream=stream)
+        if i > 0:
+            ctx.stats_back(1, 0)
+    if warmup > 0:
         ctx.stats(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -382,7 +392,8 @@ def extras(torch, mrip, inputs):
     # on both generators, their kernel times and the z-score of the difference
     # of the two estimates (section 5.3: a second generator checks that the
     # streams do not bias the results)
-    cases = (("mm1_1024x1e5_wait", mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), 0, R * N, SPLIT),
+    cases = (("mm1_1024x1e5_wait", mrip.MRIP_MM1, mrip.mm1_params(LAM, MU, N), 0, R * N,
+              min(SPLIT, 4)),  # taus88 replications split over at most 4 wavefronts
              ("pi_1024x1e6", mrip.MRIP_PI, mrip.pi_params(1_000_000), 1, 1024 * 10**6, 1),
              ("rw_1024x64x1000_ssd", mrip.MRIP_RW, mrip.rw_params(64, 64, 1000), 0,
               1024 * 64 * 1000, 1))
@@ -438,7 +449,9 @@ def extras(torch, mrip, inputs):
 
 
 def main():
+    global SPLIT
     args = parse()
+    SPLIT = args.split
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (replications "
               "would shard by id ranges, with one all-gather of outputs)", file=sys.stderr)
@@ -498,8 +511,9 @@ def main():
                    "waves_per_replication": SPLIT},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": TRAFFIC_BYTES,
-                     "kernel": "mm1_split_kernel<%d>" % SPLIT, "avg_kernel_ms": avg_kernel_ms,
+                     "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": TRAFFIC_BYTES if SPLIT == 4 else None,
+                     "kernel": "mm1_split_kernel<%d, false>" % SPLIT, "avg_kernel_ms": avg_kernel_ms,
                      "slots_per_customer": slots,
                      "frac_of_sustained_simple_op_rate": achieved / SUSTAINED_LANE_OPS},
         "kernel_only": {"median_kernel_ms": kernel_med,
