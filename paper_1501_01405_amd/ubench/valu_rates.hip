@@ -2,7 +2,10 @@
 // made of (gfx950). Each lane runs 8 independent dependency chains of one
 // instruction for many iterations over a grid that fills every SIMD several
 // times; the rate is lane-instructions per second, reported beside the
-// full-rate figure 256 CU x 4 SIMD x 16 lanes x clock.
+// full-rate figure 256 CU x 4 SIMD x 16 lanes x clock. Two timings per
+// instruction: the best of 5 isolated launches (each after a host
+// synchronisation), and the average of 20 back-to-back launches after
+// 50 ms of continuous launches (the clock state a long run settles in).
 //
 // Usage: valu_rates [waves_per_simd ...]   (default: 4 8 16)
 #include <hip/hip_runtime.h>
@@ -81,8 +84,13 @@ __global__ void rate_kernel(uint32_t *out, uint32_t seed) {
   out[t] = acc;
 }
 
+struct Rate {
+  double isolated, sustained;        // lane-ops/s
+  double isolated_ms, sustained_ms;  // per launch
+};
+
 template <int OP>
-double measure(uint32_t *out, int blocks, int threads, double *ms_out) {
+Rate measure(uint32_t *out, int blocks, int threads) {
   hipEvent_t a, b;
   CHECK(hipEventCreate(&a));
   CHECK(hipEventCreate(&b));
@@ -99,11 +107,34 @@ double measure(uint32_t *out, int blocks, int threads, double *ms_out) {
     CHECK(hipEventElapsedTime(&ms, a, b));
     if (ms < best) best = ms;
   }
+  // continuous launches for at least 50 ms (at most 4096), then 20 timed
+  float warm = 0.0f;
+  for (int k = 0; k < 64 && warm < 50.0f; ++k) {
+    CHECK(hipEventRecord(a, 0));
+    for (int r = 0; r < 64; ++r)
+      hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(threads), 0, 0, out, (uint32_t)r);
+    CHECK(hipEventRecord(b, 0));
+    CHECK(hipEventSynchronize(b));
+    float ms;
+    CHECK(hipEventElapsedTime(&ms, a, b));
+    warm += ms;
+  }
+  CHECK(hipEventRecord(a, 0));
+  for (int r = 0; r < 20; ++r)
+    hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(threads), 0, 0, out, (uint32_t)r);
+  CHECK(hipEventRecord(b, 0));
+  CHECK(hipEventSynchronize(b));
+  float sus;
+  CHECK(hipEventElapsedTime(&sus, a, b));
   CHECK(hipEventDestroy(a));
   CHECK(hipEventDestroy(b));
-  *ms_out = best;
   const double lane_ops = (double)blocks * threads * ITERS * CHAINS;
-  return lane_ops / (best * 1e-3);
+  Rate r;
+  r.isolated_ms = best;
+  r.sustained_ms = sus / 20.0;
+  r.isolated = lane_ops / (best * 1e-3);
+  r.sustained = lane_ops / (r.sustained_ms * 1e-3);
+  return r;
 }
 
 int main(int argc, char **argv) {
@@ -128,7 +159,7 @@ int main(int argc, char **argv) {
               cus, clock_khz / 1e3, waves_per_simd, full);
   struct Row {
     const char *name;
-    double (*fn)(uint32_t *, int, int, double *);
+    Rate (*fn)(uint32_t *, int, int);
   } rows[] = {
       {"v_mad_u64_u32", measure<MAD_U64>}, {"v_mul_hi_u32", measure<MUL_HI>},
       {"v_mul_lo_u32", measure<MUL_LO>},   {"v_log_f32", measure<LOG>},
@@ -138,10 +169,11 @@ int main(int argc, char **argv) {
       {"v_fma_f64", measure<FMA_F64>},
   };
   for (const Row &r : rows) {
-    double ms;
-    const double rate = r.fn(out, blocks, threads, &ms);
-    std::printf("%-22s %.4e lane-ops/s  %.3f of full rate  (%.3f ms)\n", r.name, rate,
-                rate / full, ms);
+    const Rate m = r.fn(out, blocks, threads);
+    std::printf("%-22s isolated %.4e lane-ops/s %.3f of full rate (%.3f ms)  "
+                "sustained %.4e lane-ops/s %.3f of full rate (%.3f ms)\n",
+                r.name, m.isolated, m.isolated / full, m.isolated_ms, m.sustained,
+                m.sustained / full, m.sustained_ms);
   }
   CHECK(hipFree(out));
   }

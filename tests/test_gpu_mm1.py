@@ -141,6 +141,24 @@ def test_mm1_split_features(gpu):
     assert rel_err(ctx.output(0).cpu().numpy(), base[1][:, 0]).max() <= 1e-6
 
 
+@pytest.mark.parametrize("split", [2, 4, 8])
+@pytest.mark.parametrize("N,lam", [(100000, 0.9), (20000, 1.3), (3000, 0.5)])
+def test_mm1_split_feature_free_form(gpu, split, N, lam):
+    # a run without a feature prefix takes the split kernel's feature-free
+    # form; with a short prefix (one chunk, so the parts are the same) the
+    # feature form runs the same customers in the same order: the means
+    # must agree bit for bit
+    announce("mm1 split feature-free form", split, N, lam)
+    R = 24
+    outs = []
+    for K in (0, 100):
+        ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(lam, 1.0, N, K), WAVE)
+        ctx.set_split(split)
+        ctx.run(R, seed=7)
+        outs.append(np.stack([ctx.output(o).cpu().numpy() for o in range(3)], axis=1))
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("mapping,rpw", [(WAVE, 1), (WAVE, 4), (SIMT, 1)])
 @pytest.mark.parametrize("N,K", [(1, 1), (5000, 5000), (777, 512), (2048, 1)])
 def test_mm1_feature_edges(gpu, mapping, rpw, N, K):
