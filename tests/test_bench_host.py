@@ -1,5 +1,6 @@
 """Host-side parts of bench.py that need no GPU: the refusal of more than
-one GPU, and the algorithmic slot counts its rooflines divide by."""
+one GPU, the algorithmic slot counts its rooflines divide by, and its
+command-line defaults."""
 import os
 import subprocess
 import sys
@@ -29,3 +30,17 @@ def test_slot_counts():
     assert bench.taus88_output_slots() == 19.0
     r = bench.alu_roofline(1e12, 10.0)
     assert r["bound"] == "alu" and abs(r["frac"] - 1e13 / bench.PEAK_LANE_OPS) < 1e-12
+
+
+def test_defaults_and_split_choice(monkeypatch):
+    # the default run warms up in the pipelined form before timing; the
+    # headline's wavefronts per replication are one of the split kernels'
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert (a.gpus, a.steps, a.warmup, a.split) == (1, 200, 300, bench.SPLIT)
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--split", "8", "--steps", "5"])
+    a = bench.parse()
+    assert (a.split, a.steps) == (8, 5)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--split", "3"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "invalid choice" in r.stderr
