@@ -352,8 +352,8 @@ mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng) {
 
 mrip_status mrip_set_plan_split(mrip_ctx ctx, uint32_t waves_per_item, uint64_t long_min) {
   if (!ctx) return MRIP_E_INVAL;
-  if (waves_per_item != 1 && waves_per_item != 2 && waves_per_item != 4)
-    return inval(ctx, "waves_per_item must be 1, 2 or 4");
+  if (waves_per_item != 1 && waves_per_item != 2 && waves_per_item != 4 && waves_per_item != 8)
+    return inval(ctx, "waves_per_item must be 1, 2, 4 or 8");
   if (ctx->model != MRIP_MM1) return inval(ctx, "plans are defined for the M/M/1 engine");
   ctx->plan_split = waves_per_item;
   ctx->long_min = long_min > 0 ? long_min : 65536;
@@ -841,7 +841,7 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
     for (uint32_t w : {64u, 256u, 1024u}) shapes.push_back({r, w, 1});
   if (n_long > 0)
     for (uint32_t r : {1u, 2u, 4u})
-      for (uint32_t x : {2u, 4u}) shapes.push_back({r, 256u, x});
+      for (uint32_t x : {2u, 4u, 8u}) shapes.push_back({r, 256u, x});
   float best = 1e30f;
   uint32_t br = ctx->rpw, bw = ctx->wg, bx = ctx->plan_split;
   for (const Shape &sh : shapes) {

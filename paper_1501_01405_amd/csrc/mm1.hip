@@ -730,15 +730,17 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_split_kernel(Mm1Args a, flo
 
 // Persistent plan kernel with the long items split: the first n_long items
 // of the longest-first order are served one per X wavefronts of a workgroup
+// (X = 2 or 4: 256-thread workgroups of 4 / X items; X = 8: one item per
+// 512-thread workgroup)
 // (queue_head[0]), at raised wave priority so that the critical path keeps
 // its issue slots when it shares a SIMD; then every wavefront serves the
 // rest RPW items at a time (queue_head[1]). Both exits are uniform (the
 // first per workgroup, the second per wavefront), so the grid drains.
 template <int X, int RPW>
-__global__ __launch_bounds__(256) void mm1_plan_split_kernel(Mm1Args a, uint64_t n_items,
-                                                             uint64_t n_long) {
+__global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a, uint64_t n_items,
+                                                                       uint64_t n_long) {
   constexpr int SLOTS = split_slots<X>();
-  static_assert(split_wg<X>() == 256, "plans split over 2 or 4 wavefronts");
+  static_assert(X == 2 || X == 4 || X == 8, "plans split over 2, 4 or 8 wavefronts");
   constexpr int S = 4 / RPW;
   __shared__ SplitShared<X> sh;
   __shared__ uint32_t sh_pop;
@@ -1006,15 +1008,19 @@ hipError_t launch_mm1_plan_split(const Mm1Args &a, uint64_t n_items, uint64_t n_
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
 #define MRIP_PICK(X, R) (const void *)mm1_plan_split_kernel<X, R>
-  const void *fn = waves_per_rep == 2 ? (rpw == 1 ? MRIP_PICK(2, 1) : rpw == 2 ? MRIP_PICK(2, 2) : MRIP_PICK(2, 4))
-                                      : (rpw == 1 ? MRIP_PICK(4, 1) : rpw == 2 ? MRIP_PICK(4, 2) : MRIP_PICK(4, 4));
+#define MRIP_PICK_X(X) (rpw == 1 ? MRIP_PICK(X, 1) : rpw == 2 ? MRIP_PICK(X, 2) : MRIP_PICK(X, 4))
+  const void *fn = waves_per_rep == 2   ? MRIP_PICK_X(2)
+                   : waves_per_rep == 4 ? MRIP_PICK_X(4)
+                                        : MRIP_PICK_X(8);
+#undef MRIP_PICK_X
 #undef MRIP_PICK
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+  const int wg = waves_per_rep == 8 ? split_wg<8>() : 256;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, wg, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   const uint64_t blocks = (uint64_t)cus * (uint64_t)per_cu;
   void *args[] = {(void *)&a, (void *)&n_items, (void *)&n_long};
-  e = hipLaunchKernel(fn, dim3((uint32_t)blocks), dim3(256), args, 0, s);
+  e = hipLaunchKernel(fn, dim3((uint32_t)blocks), dim3(wg), args, 0, s);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }

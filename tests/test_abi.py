@@ -106,6 +106,9 @@ def test_calls_out_of_order_and_bad_shapes():
     assert L.mrip_set_split(ctx, 8) == mrip.MRIP_OK
     assert L.mrip_set_split(ctx, 16) == mrip.MRIP_E_INVAL
     assert L.mrip_set_split(ctx, 4) == mrip.MRIP_OK
+    for x, want in ((1, 0), (2, 0), (3, mrip.MRIP_E_INVAL), (8, 0), (16, mrip.MRIP_E_INVAL),
+                    (4, 0)):
+        assert L.mrip_set_plan_split(ctx, x, 0) == want, x
     # a launch holds < 2^32 lanes: 2^24 replications x 256 lanes is refused
     # before any device call
     assert L.mrip_run(ctx, 1 << 24, 42, None) == mrip.MRIP_E_INVAL

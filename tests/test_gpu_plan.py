@@ -42,7 +42,7 @@ def test_plan_matches_oracle(gpu):
         assert abs(s["var"] - e["var"]) <= 1e-10 * e["var"]
 
 
-@pytest.mark.parametrize("split", [1, 4])
+@pytest.mark.parametrize("split", [1, 4, 8])
 def test_plan_full_config_sampled(gpu, split):
     items = inputs.plan_table()  # 64 dp x 32 reps, N log-uniform in [1e4, 1e6]
     announce("plan full", len(items), split)
@@ -93,7 +93,7 @@ def test_plan_shape_invariance_and_autotune(gpu):
             tol = 0.0 if rpw == 1 else 1e-6
             assert rel_err(got, base).max() <= tol
     for rpw in (1, 2, 4):
-        for split in (2, 4):
+        for split in (2, 4, 8):
             # long_min 1000: most items take the split path here
             ctx = _plan_ctx(items, rpw, 256, split, long_min=1000)
             ctx.run_plan(42)
@@ -102,7 +102,7 @@ def test_plan_shape_invariance_and_autotune(gpu):
     ctx = _plan_ctx(items, long_min=1000)
     rpw, wg, ms = ctx.autotune(42)
     assert rpw in (1, 2, 4) and wg in (64, 256, 1024) and ms > 0
-    assert ctx.shape()["plan_split"] in (1, 2, 4)
+    assert ctx.shape()["plan_split"] in (1, 2, 4, 8)
     ctx.run_plan(42)
     assert rel_err(ctx.output(0, n=len(items)).cpu().numpy(), base).max() <= 1e-6
 
