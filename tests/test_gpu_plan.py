@@ -68,6 +68,26 @@ def test_plan_split_long_items_match_oracle(gpu):
     assert rel_err(got, ref).max() <= 1e-5
 
 
+@pytest.mark.parametrize("split", [2, 4, 8])
+def test_plan_split_features_match_unsplit(gpu, split):
+    # a plan with prefix features: the split kernel's feature form keeps the
+    # prefix on the item's first part, so features match the unsplit plan's
+    # bit for bit and the means to the summation order
+    items = inputs.plan_table(n_dp=4, reps=8, n_lo=2000, n_hi=40000, seed=5)
+    announce("plan split features", split, len(items))
+    K = 1000
+    outs = []
+    for x, long_min in ((1, 0), (split, 1000)):
+        ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 1000, K), WAVE)
+        ctx.set_plan_split(x, long_min)
+        ctx.plan_set(items)
+        ctx.run_plan(42)
+        outs.append((ctx.output(0, n=len(items)).cpu().numpy(),
+                     ctx.output(3, n=len(items)).cpu().numpy()))
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert rel_err(outs[1][0], outs[0][0]).max() <= 1e-6
+
+
 def test_plan_item_equals_standalone_run(gpu):
     announce("plan item == standalone")
     items = inputs.uniform_items(1, 40, 5000, [0.9])
