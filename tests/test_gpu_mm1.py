@@ -52,10 +52,19 @@ def test_mm1_features(gpu, mapping, rpw, wg):
     assert np.abs(feat[:, 6] - rfeat[:, 6]).max() <= 2.0 / K
 
 
-def test_mm1_full_config_sampled(gpu):
-    # 1024 replications x 1e5 customers, lambda 0.9, mu 1 (WAVE, default shape)
-    announce("mm1 full config")
-    ctx, outs, _ = _run(WAVE, 1, 256, 0.9, 100000, 1024)
+@pytest.mark.parametrize("split", [1, 4])
+def test_mm1_full_config_sampled(gpu, split):
+    # 1024 replications x 1e5 customers, lambda 0.9, mu 1: WAVE in the
+    # default shape, and split over 4 wavefronts per replication (the launch
+    # bench.py times: the split kernel's feature-free form)
+    announce("mm1 full config", split)
+    if split == 1:
+        ctx, outs, _ = _run(WAVE, 1, 256, 0.9, 100000, 1024)
+    else:
+        ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 100000), WAVE)
+        ctx.set_split(split)
+        ctx.run(1024, seed=42)
+        outs = np.stack([ctx.output(o).cpu().numpy() for o in range(3)], axis=1)
     rng = np.random.default_rng(5)
     ids = sorted(set([0, 1, 511, 1023] + list(rng.integers(0, 1024, 28))))
     ref = core.mm1_many(42, ids, 100000, 0.9, 1.0, threads=core.default_threads())
