@@ -46,6 +46,16 @@ def test_pi_paper_configuration(gpu):
     assert abs(s["mean"] - math.pi) < 5 * s["half_width"]
 
 
+def test_pi_bench_configuration_sampled(gpu):
+    # 1024 replications x 1e7 draws, the launch bench.py times (four
+    # wavefronts per replication): sampled replications bit-exact
+    announce("pi 1024 x 1e7")
+    _, hits, _ = _run(WAVE, 10_000_000, 1024)
+    ids = [0, 511, 1023]
+    ref = core.pi_many(42, ids, 10_000_000, threads=3)
+    assert np.array_equal(hits[ids], ref)
+
+
 @pytest.mark.parametrize("R", [2049, 1500, 700, 300, 100])
 @pytest.mark.parametrize("rng", ["philox", "taus88"])
 def test_pi_shared_out_over_wavefronts(gpu, R, rng):
