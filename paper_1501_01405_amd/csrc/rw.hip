@@ -255,7 +255,10 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
     taus_jump(ts, a.taus_walk + (uint64_t)w * TAUS_COLS);
     taus_jump(ts, a.taus_walk + (uint64_t)(TAUS_WALK_WALKERS + sgi) * TAUS_COLS);
   }
-  const Taus ts0 = ts;
+  // the first 64 moves' words are kept for pass 2 (for up to 1024 steps
+  // that is the whole segment, and pass 2 draws nothing)
+  uint32_t first[4] = {0u, 0u, 0u, 0u};
+  Taus ts1 = ts;  // taus88: the state after those words
   int dx = 0, dy = 0;
   for (uint32_t g = t0; g < t1; g += 64) {
     uint32_t wd[4];
@@ -268,6 +271,11 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
       wd[1] = b.y;
       wd[2] = b.z;
       wd[3] = b.w;
+    }
+    if (g == t0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) first[j] = wd[j];
+      ts1 = ts;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) word_displacement(wd[j], g + 16u * j, t1, dx, dy);
@@ -292,8 +300,13 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
   int X = x0 + (sx - dx), Y = y0 + (sy - dy);
 
   // pass 2: replay the segment's moves from its start
-  ts = ts0;
-  for (uint32_t g = t0; g < t1; g += 64) {
+  if (t0 < t1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      walk16<GRID, true, WB>(first[j], t0 + 16u * j, t1, active, X, Y, bm, &bm[WORDS], wb);
+  }
+  ts = ts1;
+  for (uint32_t g = t0 + 64; g < t1; g += 64) {
     uint32_t wd[4];
     if (RNG == RNG_TAUS88) {
 #pragma unroll
