@@ -301,7 +301,7 @@ MRIP_API mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidenc
 /* Plans: items of at least long_min customers (0 = 65536) are each split
  * over waves_per_item (1, 2, 4 or 8) wavefronts of a workgroup, served first
  * (longest first) at raised wavefront priority, since the longest items set
- * the plan's makespan; the rest go reps_per_wave per wavefront. Default 4. */
+ * the plan's makespan; the rest go reps_per_wave per wavefront. Default 8. */
 MRIP_API mrip_status mrip_set_plan_split(mrip_ctx ctx, uint32_t waves_per_item,
                                          uint64_t long_min);
 

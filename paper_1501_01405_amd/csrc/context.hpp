@@ -90,7 +90,7 @@ struct mrip_ctx_s {
   uint32_t rpw = 1, wg = 256;
   uint32_t split = 1;  // wavefronts per M/M/1 replication in mrip_run
   // plans: wavefronts per long item (1 = none) and what counts as long
-  uint32_t plan_split = 4;
+  uint32_t plan_split = 8;
   uint64_t long_min = 65536;
   // stream source of mrip_run (MRIP_RNG_*) and, for taus88, its jump tables
   int rng = MRIP_RNG_PHILOX;
