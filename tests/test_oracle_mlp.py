@@ -89,3 +89,71 @@ def test_training_reduces_loss():
         g, _ = mlp.backward(theta, X, y)
         theta, m, v = mlp.adam_step(theta, m, v, g, step, lr=3e-3)
     assert mlp.loss(theta, X, y) < 0.05 * l0
+
+
+# The rounding points of the bf16 reading: both operands of every matrix
+# product are rounded to bfloat16 (X, W1, H1, W2, H2, W3 forward; dy, dZ2,
+# dZ1 backward); biases, ReLU masks and sums stay unrounded.
+_POINTS = ("X", "W1", "H1", "W2", "H2", "W3", "dy", "dZ2", "dZ1")
+
+
+def _layerwise(theta, X, y, points):
+    """The network written out layer by layer in fp64, rounding to bfloat16
+    with torch's own conversion (an implementation independent of the
+    oracle's bit arithmetic) exactly at `points`."""
+    import torch
+
+    def r(name, v):
+        v = np.asarray(v, np.float64)
+        if name not in points:
+            return v
+        t = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16)
+        return t.to(torch.float64).numpy()
+
+    f32 = lambda v: np.asarray(v, np.float32).astype(np.float64)  # noqa: E731
+    W1 = theta[:1280].reshape(128, 10)
+    b1 = theta[1280:1408]
+    W2 = theta[1408:17792].reshape(128, 128)
+    b2 = theta[17792:17920]
+    W3 = theta[17920:18048].reshape(1, 128)
+    b3 = theta[18048]
+    Xr = r("X", X)
+    z1 = Xr @ r("W1", W1).T + b1
+    h1 = r("H1", f32(np.maximum(z1, 0.0)))
+    z2 = h1 @ r("W2", W2).T + b2
+    h2 = r("H2", f32(np.maximum(z2, 0.0)))
+    out = (h2 @ r("W3", W3).T)[:, 0] + b3
+    n = X.shape[0]
+    dy = f32(2.0 * (out - y) / n)
+    dyr = r("dy", dy)
+    gW3 = dyr[None, :] @ h2
+    gb3 = np.array([dy.sum()])
+    dz2 = f32((dyr[:, None] @ r("W3", W3)) * (z2 > 0))
+    dz2r = r("dZ2", dz2)
+    gW2 = dz2r.T @ h1
+    gb2 = dz2.sum(0)
+    dz1 = f32((dz2r @ r("W2", W2)) * (z1 > 0))
+    gW1 = r("dZ1", dz1).T @ Xr
+    gb1 = dz1.sum(0)
+    grad = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
+    return out, grad
+
+
+def test_bf16_path_rounds_exactly_at_the_stated_points():
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(48, 10)).astype(np.float32)
+    y = rng.normal(size=48).astype(np.float32)
+    theta = _theta(12, 0.25).astype(np.float32).astype(np.float64)
+    got_y, _ = mlp.forward(theta, X, bf16=True)
+    got_g, _ = mlp.backward(theta, X, y, bf16=True)
+    want_y, want_g = _layerwise(theta, X, y, set(_POINTS))
+    scale = np.max(np.abs(want_g))
+    assert np.allclose(got_y, want_y, rtol=1e-9, atol=1e-12)
+    assert np.max(np.abs(got_g - want_g)) <= 1e-9 * scale
+    # the comparison sees each rounding point: leaving any one out moves the
+    # prediction or some gradient far beyond the tolerance above
+    for p in _POINTS:
+        y2, g2 = _layerwise(theta, X, y, set(_POINTS) - {p})
+        moved = max(np.max(np.abs(y2 - want_y)) / np.max(np.abs(want_y)),
+                    np.max(np.abs(g2 - want_g)) / scale)
+        assert moved > 1e-6, p
