@@ -152,3 +152,49 @@ def pooled_slope_table(Y, G, dp, rho, lo, hi, bins=16):
                 break
         beta[k] = 0.0 if src is None else max(0.0, sxy[src] / sxx[src])
     return beta
+
+
+# ------------------------------------------------- the input control variate
+# A control whose mean is known: the net input sum over the customers after
+# the feature prefix, post = sum_{n >= K} (S_n - A_n). Its expectation
+# follows from the variates' definition, and it draws on other customers'
+# variates than the features X, so it is independent of X: for any fixed
+# network g, h = g(X) z has mean 0 and Y - beta h is unbiased for E[Y]
+# without a second sample.
+
+# E[-ln u] for u = (k + 1) 2^-24, k uniform on [0, 2^24): the mean of the
+# exponential variate's inversion on its 24-bit grid, in closed form
+# 24 ln 2 - ln((2^24)!) / 2^24 (slightly below 1: the tail beyond u = 2^-24
+# is cut).
+LOG_GRID_MEAN = 24.0 * math.log(2.0) - math.lgamma(2.0 ** 24 + 1.0) / 2.0 ** 24
+
+
+def variate_mean(rate):
+    """Mean of the exponential variate of the given rate as drawn: the fp32
+    mean m = (float)(1 / rate) times the grid mean of -ln u."""
+    m = float(np.float32(1.0 / float(np.float32(rate))))
+    return m * LOG_GRID_MEAN
+
+
+def input_control(post, customers, K, lam, mu):
+    """Standardised input control of one replication: (post / (N - K) minus
+    its mean E[S] - E[A]) over its standard deviation sqrt((1/mu^2 +
+    1/lambda^2) / (N - K)); 0 when no customer follows the prefix."""
+    n_after = int(customers) - int(K)
+    if n_after <= 0:
+        return 0.0
+    mean = variate_mean(mu) - variate_mean(lam)
+    ms = float(np.float32(1.0 / float(np.float32(mu))))
+    ma = float(np.float32(1.0 / float(np.float32(lam))))
+    sd = math.sqrt((ms * ms + ma * ma) / n_after)
+    return (float(post) / n_after - mean) / sd
+
+
+def known_mean_control_variate(Y, H, beta, confidence=0.95):
+    """mean(Y - beta H) for a control H of known mean 0, with the variance
+    s^2(Y - beta H) / n and a t_{n-1} interval (beta fixed beforehand)."""
+    Y, H = (np.asarray(a, np.float64) for a in (Y, H))
+    n = Y.shape[0]
+    m, v = _mean_var(Y - beta * H)
+    tq = t_quantile(0.5 + confidence / 2.0, n - 1)
+    return dict(mean=m, var=v / n, half_width=tq * math.sqrt(v / n), dof=float(n - 1))

@@ -7,7 +7,9 @@ the method's statement of work adds. What is computed:
   operands  every matrix product rounds both of its operands to bfloat16
             (round to nearest, ties to even) and accumulates exactly here
             (fp64); biases and the ReLU masks stay in fp32/fp64.
-  loss      mean squared error over the batch.
+  loss      mean squared error over the batch of the prediction g(x), or,
+            with a per-sample multiplier z (the input control variate, whose
+            coefficient the network predicts), of g(x) z.
   optimizer Adam (Kingma and Ba, 2015, Algorithm 1) on fp32 master weights.
 
 Parameters are the flat fp32 vector [W1 (128x10), b1 (128), W2 (128x128),
@@ -69,18 +71,26 @@ def forward(theta, X, bf16=True):
     return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2)
 
 
-def loss(theta, X, y, bf16=True):
+def _mult(z, n):
+    return np.ones(n) if z is None else np.asarray(z, np.float32).astype(np.float64)
+
+
+def loss(theta, X, y, bf16=True, z=None):
     yh, _ = forward(theta, X, bf16)
-    return float(np.mean((yh - np.asarray(y, np.float64)) ** 2))
+    zz = _mult(z, yh.shape[0])
+    return float(np.mean((yh * zz - np.asarray(y, np.float64)) ** 2))
 
 
-def backward(theta, X, y, bf16=True):
-    """Gradient of the mean squared error, flat like theta, and the loss."""
+def backward(theta, X, y, bf16=True, z=None):
+    """Gradient of the mean squared error of g(x) z (z = 1 by default), flat
+    like theta, and the loss."""
     p = unpack(theta)
     yh, c = forward(theta, X, bf16)
     n = yh.shape[0]
     y = np.asarray(y, np.float64)
-    dy = 2.0 * (yh - y) / n
+    zz = _mult(z, n)
+    err = yh * zz - y
+    dy = 2.0 * err * zz / n
     if bf16:
         dy = dy.astype(np.float32)
     g = {}
@@ -98,7 +108,7 @@ def backward(theta, X, y, bf16=True):
         dz1 = dz1.astype(np.float32)
     g["W1"] = _op(dz1, bf16).T @ _op(c["X"], bf16)
     g["b1"] = np.sum(np.asarray(dz1, np.float64), axis=0)
-    return pack(g), float(np.mean((yh - y) ** 2))
+    return pack(g), float(np.mean(err ** 2))
 
 
 def adam_step(theta, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

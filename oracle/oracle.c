@@ -193,10 +193,14 @@ EXPORT int oracle_rw_injected(const uint8_t *dirs, uint32_t walkers, uint32_t gr
 /* Features over the first K customers (K = 0: none):                       */
 /*   [rho, mu, mean A, mean S, mean W, mean T, frac(W == 0), max W,         */
 /*    mean I, T_{K-1}]                                                      */
+/* and the net input after them, post = sum over n >= K of (S_n - A_n),     */
+/* exact in fp64: the raw material of a zero-mean control independent of    */
+/* the features (it draws on other customers' variates).                    */
 /* ------------------------------------------------------------------------ */
 typedef struct {
   double sum_w, sum_t, sum_i;
   double f_sum_a, f_sum_s, f_sum_w, f_sum_t, f_sum_i, f_zero, f_max_w, f_last_t;
+  double post;
 } mm1_acc;
 
 static void mm1_customer(float a, float s, float *t_prev, uint64_t n, uint64_t K,
@@ -216,6 +220,8 @@ static void mm1_customer(float a, float s, float *t_prev, uint64_t n, uint64_t K
     acc->f_zero += (w == 0.0f) ? 1.0 : 0.0;
     if ((double)w > acc->f_max_w) acc->f_max_w = (double)w;
     if (n == K - 1) acc->f_last_t = (double)t;
+  } else {
+    acc->post += (double)s - (double)a;
   }
   if (w_out) *w_out = w;
   if (i_out) *i_out = idle;
@@ -243,9 +249,10 @@ static void mm1_finish(const mm1_acc *acc, uint64_t N, uint64_t K, float lambda,
   }
 }
 
-/* out[3] = {mean W, mean T, mean I}; feat[10] written when K > 0. */
+/* out[3] = {mean W, mean T, mean I}; feat[10] written when K > 0, and
+ * *post (nullable) = sum over n >= K of (S_n - A_n). */
 EXPORT int oracle_mm1(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, float lambda,
-                      float mu, uint64_t K, float out[3], float *feat) {
+                      float mu, uint64_t K, float out[3], float *feat, double *post) {
   if (N == 0 || K > N) return -1;
   mm1_acc acc;
   memset(&acc, 0, sizeof(acc));
@@ -259,21 +266,24 @@ EXPORT int oracle_mm1(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, floa
     mm1_customer(a, s, &t_prev, n, K, &acc, NULL, NULL, NULL);
   }
   mm1_finish(&acc, N, K, lambda, mu, out, feat);
+  if (post) *post = acc.post;
   return 0;
 }
 
 /* Test seam: explicit interarrival/service arrays; per-customer W, I, T
- * (any of them may be NULL) and the three means. */
-EXPORT int oracle_mm1_injected(const float *A, const float *S, uint64_t N, float *W, float *I,
-                               float *T, float out[3]) {
-  if (N == 0) return -1;
+ * (any of them may be NULL), the three means and, after a prefix of K
+ * customers, the net input *post (nullable). */
+EXPORT int oracle_mm1_injected(const float *A, const float *S, uint64_t N, uint64_t K, float *W,
+                               float *I, float *T, float out[3], double *post) {
+  if (N == 0 || K > N) return -1;
   mm1_acc acc;
   memset(&acc, 0, sizeof(acc));
   float t_prev = 0.0f;
   for (uint64_t n = 0; n < N; ++n)
-    mm1_customer(A[n], S[n], &t_prev, n, 0, &acc, W ? W + n : NULL, I ? I + n : NULL,
+    mm1_customer(A[n], S[n], &t_prev, n, K, &acc, W ? W + n : NULL, I ? I + n : NULL,
                  T ? T + n : NULL);
   mm1_finish(&acc, N, 0, 1.0f, 1.0f, out, NULL);
+  if (post) *post = acc.post;
   return 0;
 }
 
@@ -474,7 +484,7 @@ EXPORT int oracle_rw_taus(uint64_t seed, uint32_t rep, uint32_t walkers, uint32_
 }
 
 EXPORT int oracle_mm1_taus(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, float lambda,
-                           float mu, uint64_t K, float out[3], float *feat) {
+                           float mu, uint64_t K, float out[3], float *feat, double *post) {
   if (N == 0 || K > N) return -1;
   mm1_acc acc;
   memset(&acc, 0, sizeof(acc));
@@ -487,5 +497,6 @@ EXPORT int oracle_mm1_taus(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N,
     mm1_customer(a, s, &t_prev, n, K, &acc, NULL, NULL, NULL);
   }
   mm1_finish(&acc, N, K, lambda, mu, out, feat);
+  if (post) *post = acc.post;
   return 0;
 }

@@ -162,3 +162,52 @@ def test_pooled_slope_constant_network_negative_slope_and_neighbour_fill():
     Y = np.where(k_of == 3, 1.5, 4.0) * G
     beta = cv.pooled_slope_table(Y, G, dp, rho, 0.5, 0.95)
     assert np.allclose(beta[:7], 1.5) and np.allclose(beta[7:], 4.0)
+
+
+# ------------------------------------------------- the input control variate
+
+def test_log_grid_mean_equals_exhaustive_average():
+    k = np.arange(1, 2 ** 24 + 1, dtype=np.float64)
+    exact = -np.mean(np.log(k * 2.0 ** -24))
+    assert abs(cv.LOG_GRID_MEAN - exact) < 1e-12
+    assert 1.0 - 1e-6 < cv.LOG_GRID_MEAN < 1.0  # the cut tail: about 5.5e-7
+
+
+def test_input_control_is_standard_and_independent_of_the_features():
+    from oracle import core
+    N, K, R = 900, 300, 4000
+    for lam in (0.6, 0.95):
+        _, feat, post = core.mm1_many(11, R, N, lam, 1.0, features=K, threads=8, post=True)
+        z = np.array([cv.input_control(p, N, K, lam, 1.0) for p in post])
+        assert abs(z.mean()) < 4 / np.sqrt(R)
+        assert abs(z.var(ddof=1) - 1.0) < 4 * np.sqrt(2.0 / R)
+        for j in range(2, 10):  # the prefix statistics
+            c = np.corrcoef(feat[:, j], z)[0, 1]
+            assert abs(c) < 4 / np.sqrt(R), (lam, j, c)
+        # any fixed function of the features times z has mean 0
+        h = np.tanh(feat[:, 9] / 5.0 - 1.0) * z
+        assert abs(h.mean()) < 4 * h.std(ddof=1) / np.sqrt(R)
+    assert cv.input_control(123.0, 500, 500, 0.9, 1.0) == 0.0
+
+
+def test_known_mean_estimator_reduces_unbiased_and_matches_variance():
+    rng = np.random.default_rng(8)
+    Y = rng.normal(3.0, 2.0, 64)
+    zero = cv.known_mean_control_variate(Y, np.zeros(64), beta=2.0)
+    pl = cv.plain(Y)
+    assert abs(zero["mean"] - pl["mean"]) < 1e-12 and abs(zero["var"] - pl["var"]) < 1e-12
+    # Y = 1 + 2 H + e with E[H] = 0: unbiased, variance 0.25 / n
+    n, K = 64, 2000
+    ests, vs = [], []
+    for _ in range(K):
+        H = rng.normal(size=n)
+        Yk = 1.0 + 2.0 * H + 0.5 * rng.normal(size=n)
+        r = cv.known_mean_control_variate(Yk, H, beta=2.0)
+        ests.append(r["mean"])
+        vs.append(r["var"])
+    ests = np.array(ests)
+    assert abs(ests.mean() - 1.0) < 4 * ests.std() / np.sqrt(K)
+    assert abs(ests.var() / (0.25 / n) - 1) < 4 * np.sqrt(2.0 / K)
+    assert abs(np.mean(vs) / (0.25 / n) - 1) < 0.05
+    H = rng.normal(size=n)
+    assert cv.known_mean_control_variate(5.0 + 3.0 * H, H, beta=3.0)["var"] < 1e-28

@@ -157,3 +157,25 @@ def test_bf16_path_rounds_exactly_at_the_stated_points():
         moved = max(np.max(np.abs(y2 - want_y)) / np.max(np.abs(want_y)),
                     np.max(np.abs(g2 - want_g)) / scale)
         assert moved > 1e-6, p
+
+
+def test_gradient_with_a_per_sample_multiplier():
+    # loss mean((g(x) z - y)^2): the network predicts the coefficient of z
+    rng = np.random.default_rng(13)
+    X = rng.normal(size=(9, 10))
+    y = rng.normal(size=9)
+    z = rng.normal(size=9).astype(np.float32)
+    theta = _theta(14)
+    g, l0 = mlp.backward(theta, X, y, bf16=False, z=z)
+    assert abs(l0 - mlp.loss(theta, X, y, bf16=False, z=z)) < 1e-12
+    h = 1e-6
+    for i in list(rng.choice(18049, 80, replace=False)) + [18048, 17925, 1281]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (mlp.loss(tp, X, y, bf16=False, z=z) - mlp.loss(tm, X, y, bf16=False, z=z)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, i
+    # z = 1 is the plain regression
+    g1, _ = mlp.backward(theta, X, y, bf16=True, z=np.ones(9, np.float32))
+    g0, _ = mlp.backward(theta, X, y, bf16=True)
+    assert np.array_equal(g0, g1)

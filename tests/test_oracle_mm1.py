@@ -107,3 +107,31 @@ def test_closed_form_light_load():
     out = core.mm1_many(9, R, N, 0.5, 1.0, threads=core.default_threads()).astype(np.float64)
     m, se = out[:, 0].mean(), out[:, 0].std(ddof=1) / math.sqrt(R)
     assert abs(m - 1.0) < 4 * se + 1e-3
+
+
+def test_post_prefix_net_input_obeys_flow_balance():
+    # T_n - T_{n-1} = S_n - A_n + I_n, so the net input after customer K-1 is
+    # T_{N-1} - T_{K-1} - sum_{n >= K} I_n (up to the fp32 rounding of T)
+    rng = np.random.default_rng(21)
+    N = 1500
+    for K, lam in ((0, 0.9), (200, 0.9), (700, 0.6), (N, 0.8), (N - 1, 1.2)):
+        A = rng.exponential(1 / lam, N).astype(np.float32)
+        S = rng.exponential(1.0, N).astype(np.float32)
+        W, I, T, _, post = core.mm1_injected(A, S, post_after=K)
+        T64, I64 = T.astype(np.float64), I.astype(np.float64)
+        tk = T64[K - 1] if K > 0 else 0.0
+        want = T64[-1] - tk - I64[K:].sum()
+        tol = 2.0 ** -23 * np.abs(T64).sum() + 1e-9
+        assert abs(post - want) <= tol, (K, post, want)
+
+
+def test_post_prefix_net_input_has_the_variates_mean():
+    # E[post] = (N - K)(E[S] - E[A]) with the variates' exact means
+    from oracle import cv
+    N, K, lam, mu, R = 1200, 200, 0.8, 1.0, 3000
+    _, _, post = core.mm1_many(7, R, N, lam, mu, features=K, threads=8, post=True)
+    per = post / (N - K)
+    mean = cv.variate_mean(mu) - cv.variate_mean(lam)
+    se = np.sqrt((1.0 + 1.0 / lam ** 2) / (N - K) / R)
+    assert abs(per.mean() - mean) < 4 * se
+    assert abs(per.var(ddof=1) / ((1.0 + 1.0 / lam ** 2) / (N - K)) - 1) < 0.1
