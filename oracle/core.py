@@ -41,8 +41,11 @@ def lib():
                                          C.POINTER(C.c_int64)]
         L.oracle_mm1.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_float,
                                  C.c_float, C.c_uint64, f32p, C.c_void_p, C.c_void_p]
-        L.oracle_mm1_injected.argtypes = [f32p, f32p, C.c_uint64, C.c_uint64, C.c_void_p,
-                                          C.c_void_p, C.c_void_p, f32p, C.c_void_p]
+        L.oracle_mm1_injected.argtypes = [f32p, f32p, C.c_uint64, C.c_uint64, C.c_double,
+                                          C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, f32p,
+                                          C.c_void_p]
+        L.oracle_variate_mean.argtypes = [C.c_float]
+        L.oracle_variate_mean.restype = C.c_double
         L.oracle_pi_inside.argtypes = [C.c_uint32, C.c_uint32]
         L.oracle_pi_inside.restype = C.c_int
         L.oracle_pi.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64]
@@ -147,25 +150,31 @@ def rw_many(seed, reps, walkers=64, grid=64, steps=1000, threads=1, rng="philox"
 
 
 # ---------------------------------------------------------------- M/M/1
-def _mm1_call(fn, name, seed, rep, customers, lam, mu, dp, features, post):
+def _mm1_call(fn, name, seed, rep, customers, lam, mu, dp, features, ctl):
     out = np.zeros(3, dtype=np.float32)
     feat = np.zeros(10, dtype=np.float32)
-    pn = C.c_double(0.0)
+    c4 = np.zeros(4, dtype=np.float64)
     _check(fn(seed, dp, rep, customers, lam, mu, features, out,
-              feat.ctypes.data if features else None, C.addressof(pn) if post else None), name)
-    res = (out,) + ((feat,) if features else ()) + ((pn.value,) if post else ())
+              feat.ctypes.data if features else None, c4.ctypes.data if ctl else None), name)
+    res = (out,) + ((feat,) if features else ()) + ((c4,) if ctl else ())
     return res if len(res) > 1 else out
 
 
-def mm1(seed, rep, customers, lam, mu, dp=0, features=0, post=False):
+def variate_mean(rate):
+    """Exact mean of the exponential variate of `rate` as drawn (fp64)."""
+    return lib().oracle_variate_mean(rate)
+
+
+def mm1(seed, rep, customers, lam, mu, dp=0, features=0, ctl=False):
     """(mean_wq, mean_T, mean_idle); when features > 0 also the 10 features;
-    with post, also the net input sum over n >= features of (S_n - A_n)."""
-    return _mm1_call(lib().oracle_mm1, "mm1", seed, rep, customers, lam, mu, dp, features, post)
+    with ctl, also the four controls over customers n >= features:
+    sum (S - E S), sum (A - E A), sum T_{n-1} (S - E S), sum T_{n-1} (A - E A)."""
+    return _mm1_call(lib().oracle_mm1, "mm1", seed, rep, customers, lam, mu, dp, features, ctl)
 
 
-def mm1_injected(A, S, post_after=None):
+def mm1_injected(A, S, ctl_after=None, es=1.0, ea=1.0):
     """Per-customer W, I, T and the means on explicit arrays; with
-    post_after = K, also the net input sum over n >= K of (S_n - A_n)."""
+    ctl_after = K, also the four controls over n >= K with means es, ea."""
     A = np.ascontiguousarray(A, dtype=np.float32)
     S = np.ascontiguousarray(S, dtype=np.float32)
     n = A.shape[0]
@@ -173,47 +182,47 @@ def mm1_injected(A, S, post_after=None):
     I = np.zeros(n, np.float32)
     T = np.zeros(n, np.float32)
     out = np.zeros(3, np.float32)
-    pn = C.c_double(0.0)
-    K = 0 if post_after is None else int(post_after)
-    _check(lib().oracle_mm1_injected(A, S, n, K, W.ctypes.data, I.ctypes.data, T.ctypes.data,
-                                     out, C.addressof(pn)), "mm1_injected")
-    return (W, I, T, out) if post_after is None else (W, I, T, out, pn.value)
+    c4 = np.zeros(4, np.float64)
+    K = 0 if ctl_after is None else int(ctl_after)
+    _check(lib().oracle_mm1_injected(A, S, n, K, es, ea, W.ctypes.data, I.ctypes.data,
+                                     T.ctypes.data, out, c4.ctypes.data), "mm1_injected")
+    return (W, I, T, out) if ctl_after is None else (W, I, T, out, c4)
 
 
-def mm1_taus(seed, rep, customers, lam, mu, dp=0, features=0, post=False):
+def mm1_taus(seed, rep, customers, lam, mu, dp=0, features=0, ctl=False):
     """mm1() on the replication's taus88 stream."""
     return _mm1_call(lib().oracle_mm1_taus, "mm1_taus", seed, rep, customers, lam, mu, dp,
-                     features, post)
+                     features, ctl)
 
 
-def _stack(res, features, post):
-    if not (features or post):
+def _stack(res, features, ctl):
+    if not (features or ctl):
         return np.stack(res)
     cols = list(zip(*res))
     out = [np.stack(cols[0])]
     if features:
         out.append(np.stack(cols[1]))
-    if post:
-        out.append(np.array(cols[-1], dtype=np.float64))
+    if ctl:
+        out.append(np.stack(cols[-1]))
     return tuple(out)
 
 
 def mm1_many(seed, reps, customers, lam, mu, dp=0, features=0, threads=1, rng="philox",
-             post=False):
-    """Outputs (R,3) float32, (R,10) features when requested, and the (R,)
-    fp64 post-prefix net inputs with post."""
+             ctl=False):
+    """Outputs (R,3) float32, (R,10) features when requested, and the (R,4)
+    fp64 controls with ctl."""
     ids = list(range(reps)) if isinstance(reps, int) else list(reps)
     one = mm1 if rng == "philox" else mm1_taus
-    res = _map(lambda r: one(seed, r, customers, lam, mu, dp, features, post), ids, threads)
-    return _stack(res, features, post)
+    res = _map(lambda r: one(seed, r, customers, lam, mu, dp, features, ctl), ids, threads)
+    return _stack(res, features, ctl)
 
 
-def mm1_items(seed, items, features=0, threads=1, post=False):
+def mm1_items(seed, items, features=0, threads=1, ctl=False):
     """Run plan items: an iterable of (dp, rep, customers, lambda, mu)."""
     items = list(items)
     res = _map(lambda it: mm1(seed, int(it[1]), int(it[2]), float(it[3]), float(it[4]),
-                              int(it[0]), features, post), items, threads)
-    return _stack(res, features, post)
+                              int(it[0]), features, ctl), items, threads)
+    return _stack(res, features, ctl)
 
 
 # ---------------------------------------------------------------- forest fire

@@ -1,23 +1,25 @@
 """Control-variate estimator, oracle side -- TEST INFRASTRUCTURE ONLY.
 
-Two-phase control variate for one design point (a control variate whose mean
-is estimated from a second, independent sample):
+For one design point with n replications (Y_i, h_i), where h is a control of
+known mean zero fixed before the replications are drawn (up to the
+replication's own prefix, see below), and a coefficient beta fixed
+beforehand,
 
-  n full replications give (Y_i, g_i = g(X_i)); M prefix-only replications,
-  with stream ids disjoint from the full ones, give g'_j = g(X'_j). With a
-  fixed coefficient beta,
+    Y_cv = mean_i(Y_i - beta h_i)
 
-      Y_cv = mean_i(Y_i - beta g_i) + beta mean_j(g'_j)
+is unbiased for E[Y]; its variance estimate is s^2(Y - beta h)/n with a
+t_{n-1} interval. The plain estimate mean(Y) with its t_{n-1} interval is
+the fallback and the judge of the control's error.
 
-  is unbiased for E[Y] for any fixed g, because E[g(X)] = E[g(X')]. Its
-  variance estimate is s^2(Y - beta g)/n + beta^2 s^2(g')/M, and the interval
-  uses the Welch-Satterthwaite degrees of freedom. The plain estimate
-  mean(Y) with a t_{n-1} interval is the fallback.
+The control is h = sum_k g_k(X) z_k: four martingale controls z of the run
+after its first K customers (below), with coefficients g(X) the network
+predicts from the design's factor levels and summary statistics of those K
+customers.
 
 Training's host steps (feature z-scores, the standardised within-design-
-point target, the held-out design points, and the per-bin pooled slope of Y
-on the control with its clamp at zero and nearest-bin fill) follow below,
-one function each.
+point target and its multipliers, the held-out design points, and the
+per-bin pooled slope of Y on the control with its clamp at zero and
+nearest-bin fill) follow, one function each.
 """
 import math
 
@@ -44,20 +46,6 @@ def plain(Y, confidence=0.95):
     n = len(Y)
     tq = t_quantile(0.5 + confidence / 2.0, n - 1)
     return dict(mean=m, var=v / n, half_width=tq * math.sqrt(v / n), dof=float(n - 1))
-
-
-def control_variate(Y, G, Gp, beta, confidence=0.95):
-    Y, G, Gp = (np.asarray(a, np.float64) for a in (Y, G, Gp))
-    n, M = Y.shape[0], Gp.shape[0]
-    m1, v1 = _mean_var(Y - beta * G)
-    m2, v2 = _mean_var(Gp)
-    est = m1 + beta * m2
-    a, b = v1 / n, beta * beta * v2 / M
-    var = a + b
-    denom = a * a / (n - 1) + b * b / (M - 1)
-    dof = var * var / denom if denom > 0 else float(n - 1)
-    tq = t_quantile(0.5 + confidence / 2.0, dof)
-    return dict(mean=est, var=var, half_width=tq * math.sqrt(var), dof=dof)
 
 
 # ----------------------------------------------------------------- training
@@ -154,13 +142,15 @@ def pooled_slope_table(Y, G, dp, rho, lo, hi, bins=16):
     return beta
 
 
-# ------------------------------------------------- the input control variate
-# A control whose mean is known: the net input sum over the customers after
-# the feature prefix, post = sum_{n >= K} (S_n - A_n). Its expectation
-# follows from the variates' definition, and it draws on other customers'
-# variates than the features X, so it is independent of X: for any fixed
-# network g, h = g(X) z has mean 0 and Y - beta h is unbiased for E[Y]
-# without a second sample.
+# ------------------------------------------------- the martingale controls
+# Four controls over the customers after the feature prefix (n >= K):
+#   c0 = sum (S_n - E S), c1 = sum (A_n - E A),
+#   c2 = sum T_{n-1} (S_n - E S), c3 = sum T_{n-1} (A_n - E A).
+# A_n and S_n are drawn independently of everything before customer n, so
+# each term has mean zero given the past (martingale differences). Any
+# function of the first K customers, the network's coefficients included,
+# times any c_k therefore has mean zero, and Y - h stays unbiased for E[Y]
+# with no second sample. The means are the variates' exact ones.
 
 # E[-ln u] for u = (k + 1) 2^-24, k uniform on [0, 2^24): the mean of the
 # exponential variate's inversion on its 24-bit grid, in closed form
@@ -176,18 +166,49 @@ def variate_mean(rate):
     return m * LOG_GRID_MEAN
 
 
-def input_control(post, customers, K, lam, mu):
-    """Standardised input control of one replication: (post / (N - K) minus
-    its mean E[S] - E[A]) over its standard deviation sqrt((1/mu^2 +
-    1/lambda^2) / (N - K)); 0 when no customer follows the prefix."""
-    n_after = int(customers) - int(K)
-    if n_after <= 0:
-        return 0.0
-    mean = variate_mean(mu) - variate_mean(lam)
+def control_multipliers(ctl, customers, mu):
+    """The network's per-sample multipliers z from the four controls of a
+    replication of N customers: c / N, the two T-weighted controls also
+    divided by the service scale (float)(1 / mu), so that all four are in
+    time units per customer and the coefficients are plain numbers. A fixed
+    rescaling per design point keeps every mean zero."""
+    ctl = np.asarray(ctl, np.float64)
     ms = float(np.float32(1.0 / float(np.float32(mu))))
-    ma = float(np.float32(1.0 / float(np.float32(lam))))
-    sd = math.sqrt((ms * ms + ma * ma) / n_after)
-    return (float(post) / n_after - mean) / sd
+    scale = np.array([1.0, 1.0, 1.0 / ms, 1.0 / ms]) / float(customers)
+    return ctl * scale
+
+
+def design_point_sd(Y, dp):
+    """Per row: the unbiased standard deviation of Y over the row's design
+    point (the scale of the standardised training target)."""
+    Y = np.asarray(Y, np.float64)
+    dp = np.asarray(dp)
+    sd = np.zeros(Y.shape[0])
+    for d in sorted(set(dp.tolist())):
+        idx = np.flatnonzero(dp == d)
+        _, v = _mean_var(Y[idx])
+        sd[idx] = math.sqrt(v)
+    return sd
+
+
+def training_multipliers(Z, sd):
+    """The multipliers of the standardised target: z / sd of the row's
+    design point (0 where that deviation is 0), so that sum_k g_k z_k / sd
+    fits (Y - mean_dp Y) / sd and g_k stays a coefficient of Y itself."""
+    Z = np.asarray(Z, np.float64)
+    sd = np.asarray(sd, np.float64)
+    out = np.zeros_like(Z)
+    for i in range(Z.shape[0]):
+        if sd[i] > 0:
+            out[i] = Z[i] / sd[i]
+    return out
+
+
+def control_value(G, Z):
+    """h = sum_k g_k z_k per replication (G: network outputs, Z: multipliers)."""
+    G = np.asarray(G, np.float64)
+    Z = np.asarray(Z, np.float64)
+    return np.sum(G * Z, axis=1)
 
 
 def known_mean_control_variate(Y, H, beta, confidence=0.95):

@@ -3,26 +3,27 @@
 The paper has no variance reduction; the control variate is the growth path
 the method's statement of work adds. What is computed:
 
-  network   10 -> 128 -> 128 -> 1, ReLU after the two hidden layers.
+  network   10 -> 128 -> 128 -> 4, ReLU after the two hidden layers; the
+            four outputs are the coefficients of four zero-mean controls.
   operands  every matrix product rounds both of its operands to bfloat16
             (round to nearest, ties to even) and accumulates exactly here
             (fp64); biases and the ReLU masks stay in fp32/fp64.
-  loss      mean squared error over the batch of the prediction g(x), or,
-            with a per-sample multiplier z (the input control variate, whose
-            coefficient the network predicts), of g(x) z.
+  loss      mean squared error over the batch of sum_k g_k(x) z_k, with a
+            per-sample multiplier vector z (the sample's controls); without
+            multipliers, of the first output g_0(x) alone (z = e_0).
   optimizer Adam (Kingma and Ba, 2015, Algorithm 1) on fp32 master weights.
 
 Parameters are the flat fp32 vector [W1 (128x10), b1 (128), W2 (128x128),
-b2 (128), W3 (1x128), b3 (1)], row-major, 18049 values.
+b2 (128), W3 (4x128), b3 (4)], row-major, 18436 values.
 
 `bf16=False` turns the rounding off, which is what the finite-difference
 gradient pin uses.
 """
 import numpy as np
 
-D_IN, H = 10, 128
-SHAPES = (("W1", (H, D_IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (1, H)),
-          ("b3", (1,)))
+D_IN, H, D_OUT = 10, 128, 4
+SHAPES = (("W1", (H, D_IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (D_OUT, H)),
+          ("b3", (D_OUT,)))
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
 
 
@@ -67,36 +68,48 @@ def forward(theta, X, bf16=True):
     h2 = np.maximum(z2, 0.0)
     if bf16:
         h2 = h2.astype(np.float32)
-    y = (_op(h2, bf16) @ _op(p["W3"], bf16).T)[:, 0] + p["b3"][0]
+    y = _op(h2, bf16) @ _op(p["W3"], bf16).T + p["b3"]
     return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2)
 
 
 def _mult(z, n):
-    return np.ones(n) if z is None else np.asarray(z, np.float32).astype(np.float64)
+    """Per-sample multipliers as fp64 (n, 4); None is e_0 for every sample."""
+    if z is None:
+        m = np.zeros((n, D_OUT))
+        m[:, 0] = 1.0
+        return m
+    z = np.asarray(z, np.float32).astype(np.float64)
+    assert z.shape == (n, D_OUT)
+    return z
+
+
+def predict(theta, X, bf16=True, z=None):
+    """sum_k g_k(x) z_k per sample (g_0(x) without multipliers)."""
+    yh, _ = forward(theta, X, bf16)
+    return np.sum(yh * _mult(z, yh.shape[0]), axis=1)
 
 
 def loss(theta, X, y, bf16=True, z=None):
-    yh, _ = forward(theta, X, bf16)
-    zz = _mult(z, yh.shape[0])
-    return float(np.mean((yh * zz - np.asarray(y, np.float64)) ** 2))
+    return float(np.mean((predict(theta, X, bf16, z) - np.asarray(y, np.float64)) ** 2))
 
 
 def backward(theta, X, y, bf16=True, z=None):
-    """Gradient of the mean squared error of g(x) z (z = 1 by default), flat
-    like theta, and the loss."""
+    """Gradient of the mean squared error of sum_k g_k(x) z_k, flat like
+    theta, and the loss. The output gradient dy_k = 2 (pred - y) z_k / n is
+    rounded to fp32 before it enters the products."""
     p = unpack(theta)
     yh, c = forward(theta, X, bf16)
     n = yh.shape[0]
     y = np.asarray(y, np.float64)
     zz = _mult(z, n)
-    err = yh * zz - y
-    dy = 2.0 * err * zz / n
+    err = np.sum(yh * zz, axis=1) - y
+    dy = (2.0 * err / n)[:, None] * zz
     if bf16:
         dy = dy.astype(np.float32)
     g = {}
-    g["W3"] = _op(dy, bf16)[None, :] @ _op(c["h2"], bf16)
-    g["b3"] = np.array([np.sum(np.asarray(dy, np.float64))])
-    dh2 = _op(dy, bf16)[:, None] @ _op(p["W3"], bf16)
+    g["W3"] = _op(dy, bf16).T @ _op(c["h2"], bf16)
+    g["b3"] = np.sum(np.asarray(dy, np.float64), axis=0)
+    dh2 = _op(dy, bf16) @ _op(p["W3"], bf16)
     dz2 = dh2 * (c["z2"] > 0)
     if bf16:
         dz2 = dz2.astype(np.float32)

@@ -21,7 +21,11 @@
  *               one-walker runs.
  *   mm1      -- M/M/1 closed form Wq = rho/(mu-lambda), a hand-traced case,
  *               an independent absolute-clock event simulation, degenerate
- *               inputs (S == 0, A == 0).
+ *               inputs (S == 0, A == 0). Controls: hand-traced values, the
+ *               degenerate inputs against brute force, flow balance, the
+ *               grid mean's closed form, mean zero times functions of the
+ *               prefix over replications, and the perturbation-analysis
+ *               coefficients of the weighted pair.
  *   ff       -- injected-uniform cases with closed-form burnt counts and an
  *               independent array-rolling implementation on tiny grids.
  *   pi       -- hand-checked inside/outside points on and near the circle,
@@ -193,18 +197,42 @@ EXPORT int oracle_rw_injected(const uint8_t *dirs, uint32_t walkers, uint32_t gr
 /* Features over the first K customers (K = 0: none):                       */
 /*   [rho, mu, mean A, mean S, mean W, mean T, frac(W == 0), max W,         */
 /*    mean I, T_{K-1}]                                                      */
-/* and the net input after them, post = sum over n >= K of (S_n - A_n),     */
-/* exact in fp64: the raw material of a zero-mean control independent of    */
-/* the features (it draws on other customers' variates).                    */
+/* and four controls over the customers after them, n >= K, in fp64:       */
+/*   c0 = sum (S_n - E S)          c1 = sum (A_n - E A)                     */
+/*   c2 = sum T_{n-1} (S_n - E S)  c3 = sum T_{n-1} (A_n - E A)              */
+/* with E S, E A the variates' exact means. A_n and S_n are independent of  */
+/* everything before customer n, T_{n-1} included, so every term has mean  */
+/* zero given the past: each c_k times any function of the first K         */
+/* customers has mean zero (sums of martingale differences).               */
 /* ------------------------------------------------------------------------ */
 typedef struct {
   double sum_w, sum_t, sum_i;
   double f_sum_a, f_sum_s, f_sum_w, f_sum_t, f_sum_i, f_zero, f_max_w, f_last_t;
-  double post;
+  double es, ea;  /* exact means of S and A */
+  double ctl[4];
 } mm1_acc;
+
+/* E[-ln u] for u = (k + 1) 2^-24, k uniform on [0, 2^24): the average of   */
+/* -ln(j 2^-24) over j = 1..2^24, i.e. 24 ln 2 - ln((2^24)!) / 2^24.        */
+static double log_grid_mean(void) {
+  return 24.0 * log(2.0) - lgamma(16777217.0) / 16777216.0;
+}
+
+/* Exact mean of the exponential variate of the given rate as drawn: its   */
+/* fp32 scale (float)(1 / rate) times the grid mean of -ln u.               */
+EXPORT double oracle_variate_mean(float rate) {
+  return (double)(float)(1.0 / (double)rate) * log_grid_mean();
+}
 
 static void mm1_customer(float a, float s, float *t_prev, uint64_t n, uint64_t K,
                          mm1_acc *acc, float *w_out, float *i_out, float *t_out) {
+  if (n >= K) {
+    double ds = (double)s - acc->es, da = (double)a - acc->ea, tp = (double)*t_prev;
+    acc->ctl[0] += ds;
+    acc->ctl[1] += da;
+    acc->ctl[2] += tp * ds;
+    acc->ctl[3] += tp * da;
+  }
   float w = fmaxf(0.0f, *t_prev - a);
   float idle = fmaxf(0.0f, a - *t_prev);
   float t = w + s;
@@ -220,8 +248,6 @@ static void mm1_customer(float a, float s, float *t_prev, uint64_t n, uint64_t K
     acc->f_zero += (w == 0.0f) ? 1.0 : 0.0;
     if ((double)w > acc->f_max_w) acc->f_max_w = (double)w;
     if (n == K - 1) acc->f_last_t = (double)t;
-  } else {
-    acc->post += (double)s - (double)a;
   }
   if (w_out) *w_out = w;
   if (i_out) *i_out = idle;
@@ -249,13 +275,19 @@ static void mm1_finish(const mm1_acc *acc, uint64_t N, uint64_t K, float lambda,
   }
 }
 
+static void mm1_start(mm1_acc *acc, float lambda, float mu) {
+  memset(acc, 0, sizeof(*acc));
+  acc->es = oracle_variate_mean(mu);
+  acc->ea = oracle_variate_mean(lambda);
+}
+
 /* out[3] = {mean W, mean T, mean I}; feat[10] written when K > 0, and
- * *post (nullable) = sum over n >= K of (S_n - A_n). */
+ * ctl[4] (nullable) the four controls over n >= K. */
 EXPORT int oracle_mm1(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, float lambda,
-                      float mu, uint64_t K, float out[3], float *feat, double *post) {
+                      float mu, uint64_t K, float out[3], float *feat, double *ctl) {
   if (N == 0 || K > N) return -1;
   mm1_acc acc;
-  memset(&acc, 0, sizeof(acc));
+  mm1_start(&acc, lambda, mu);
   float t_prev = 0.0f;
   uint32_t blk[4];
   for (uint64_t n = 0; n < N; ++n) {
@@ -266,24 +298,27 @@ EXPORT int oracle_mm1(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, floa
     mm1_customer(a, s, &t_prev, n, K, &acc, NULL, NULL, NULL);
   }
   mm1_finish(&acc, N, K, lambda, mu, out, feat);
-  if (post) *post = acc.post;
+  if (ctl) memcpy(ctl, acc.ctl, sizeof(acc.ctl));
   return 0;
 }
 
 /* Test seam: explicit interarrival/service arrays; per-customer W, I, T
  * (any of them may be NULL), the three means and, after a prefix of K
- * customers, the net input *post (nullable). */
-EXPORT int oracle_mm1_injected(const float *A, const float *S, uint64_t N, uint64_t K, float *W,
-                               float *I, float *T, float out[3], double *post) {
+ * customers, the four controls with the given means es, ea (nullable). */
+EXPORT int oracle_mm1_injected(const float *A, const float *S, uint64_t N, uint64_t K, double es,
+                               double ea, float *W, float *I, float *T, float out[3],
+                               double *ctl) {
   if (N == 0 || K > N) return -1;
   mm1_acc acc;
   memset(&acc, 0, sizeof(acc));
+  acc.es = es;
+  acc.ea = ea;
   float t_prev = 0.0f;
   for (uint64_t n = 0; n < N; ++n)
     mm1_customer(A[n], S[n], &t_prev, n, K, &acc, W ? W + n : NULL, I ? I + n : NULL,
                  T ? T + n : NULL);
   mm1_finish(&acc, N, 0, 1.0f, 1.0f, out, NULL);
-  if (post) *post = acc.post;
+  if (ctl) memcpy(ctl, acc.ctl, sizeof(acc.ctl));
   return 0;
 }
 
@@ -484,10 +519,10 @@ EXPORT int oracle_rw_taus(uint64_t seed, uint32_t rep, uint32_t walkers, uint32_
 }
 
 EXPORT int oracle_mm1_taus(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, float lambda,
-                           float mu, uint64_t K, float out[3], float *feat, double *post) {
+                           float mu, uint64_t K, float out[3], float *feat, double *ctl) {
   if (N == 0 || K > N) return -1;
   mm1_acc acc;
-  memset(&acc, 0, sizeof(acc));
+  mm1_start(&acc, lambda, mu);
   float t_prev = 0.0f;
   uint32_t st[3];
   oracle_taus88_seed(seed, TAG_MM1, dp, rep, st);
@@ -497,6 +532,6 @@ EXPORT int oracle_mm1_taus(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N,
     mm1_customer(a, s, &t_prev, n, K, &acc, NULL, NULL, NULL);
   }
   mm1_finish(&acc, N, K, lambda, mu, out, feat);
-  if (post) *post = acc.post;
+  if (ctl) memcpy(ctl, acc.ctl, sizeof(acc.ctl));
   return 0;
 }

@@ -32,8 +32,8 @@ def philox_ref():
     if not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
         inc = os.path.join(os.path.dirname(torch.__file__), "include")
         subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__",
-                        "-I/opt/rocm/include", "-I" + inc, src, "-o", out + ".tmp"], check=True)
-        os.replace(out + ".tmp", out)
+                        "-I/opt/rocm/include", "-I" + inc, src, "-o", out + ".tmp%d" % os.getpid()], check=True)
+        os.replace(out + ".tmp%d" % os.getpid(), out)
     lib = C.CDLL(out)
     p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
     for fn in (lib.torch_philox_batch, lib.rocrand_philox_batch):

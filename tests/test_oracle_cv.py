@@ -1,54 +1,16 @@
-"""Pins for the oracle's two-phase control-variate estimator.
+"""Pins for the oracle's control-variate estimator and training host steps.
 
-Independent facts used: a constant control (g = c) reduces the estimator
-exactly to the plain mean; the estimator is unbiased in a model with a known
-mean; its variance matches the Monte Carlo variance over many experiments;
-a perfectly correlated control removes the first-phase variance.
+Independent facts used: a zero control reduces the estimator exactly to the
+plain mean; it is unbiased with the Monte Carlo variance in a model with a
+known mean; numpy's own statistics for the z-scores; least squares on the
+demeaned data for the pooled slopes; the exhaustive average of -ln u over
+its 2^24-point grid for the variates' mean.
 """
 import math
 
 import numpy as np
 
 from oracle import cv
-
-
-def test_constant_control_reduces_to_plain():
-    rng = np.random.default_rng(0)
-    Y = rng.normal(5.0, 1.0, 64)
-    c = 2.5
-    G = np.full(64, c)
-    Gp = np.full(200, c)
-    a = cv.control_variate(Y, G, Gp, beta=1.0)
-    b = cv.plain(Y)
-    assert abs(a["mean"] - b["mean"]) < 1e-12
-    assert abs(a["var"] - b["var"]) < 1e-12
-
-
-def test_unbiased_and_variance_estimate():
-    # Y = X + e with X ~ N(0, 1), e ~ N(0, 0.1^2); control g(X) = X; E[Y] = 0
-    rng = np.random.default_rng(1)
-    n, M, K = 64, 512, 3000
-    ests, vars_ = [], []
-    for _ in range(K):
-        X = rng.normal(size=n)
-        Y = X + 0.1 * rng.normal(size=n)
-        Xp = rng.normal(size=M)
-        r = cv.control_variate(Y, X, Xp, beta=1.0)
-        ests.append(r["mean"])
-        vars_.append(r["var"])
-    ests = np.array(ests)
-    assert abs(ests.mean()) < 4 * ests.std() / math.sqrt(K)
-    true_var = 0.01 / n + 1.0 / M
-    assert abs(ests.var() / true_var - 1) < 0.1
-    assert abs(np.mean(vars_) / true_var - 1) < 0.05
-
-
-def test_perfect_control_leaves_second_phase_only():
-    rng = np.random.default_rng(2)
-    X = rng.normal(size=64)
-    Xp = rng.normal(size=1000)
-    r = cv.control_variate(3 * X + 1, X, Xp, beta=3.0)
-    assert abs(r["var"] - 9 * np.var(Xp, ddof=1) / 1000) < 1e-12
 
 
 # ------------------------------------------------------ training host steps
@@ -164,7 +126,7 @@ def test_pooled_slope_constant_network_negative_slope_and_neighbour_fill():
     assert np.allclose(beta[:7], 1.5) and np.allclose(beta[7:], 4.0)
 
 
-# ------------------------------------------------- the input control variate
+# ------------------------------------------------- the martingale controls
 
 def test_log_grid_mean_equals_exhaustive_average():
     k = np.arange(1, 2 ** 24 + 1, dtype=np.float64)
@@ -173,21 +135,35 @@ def test_log_grid_mean_equals_exhaustive_average():
     assert 1.0 - 1e-6 < cv.LOG_GRID_MEAN < 1.0  # the cut tail: about 5.5e-7
 
 
-def test_input_control_is_standard_and_independent_of_the_features():
-    from oracle import core
-    N, K, R = 900, 300, 4000
-    for lam in (0.6, 0.95):
-        _, feat, post = core.mm1_many(11, R, N, lam, 1.0, features=K, threads=8, post=True)
-        z = np.array([cv.input_control(p, N, K, lam, 1.0) for p in post])
-        assert abs(z.mean()) < 4 / np.sqrt(R)
-        assert abs(z.var(ddof=1) - 1.0) < 4 * np.sqrt(2.0 / R)
-        for j in range(2, 10):  # the prefix statistics
-            c = np.corrcoef(feat[:, j], z)[0, 1]
-            assert abs(c) < 4 / np.sqrt(R), (lam, j, c)
-        # any fixed function of the features times z has mean 0
-        h = np.tanh(feat[:, 9] / 5.0 - 1.0) * z
-        assert abs(h.mean()) < 4 * h.std(ddof=1) / np.sqrt(R)
-    assert cv.input_control(123.0, 500, 500, 0.9, 1.0) == 0.0
+def test_control_multipliers_scale_per_customer_and_service_time():
+    c = np.array([4.0, -2.0, 8.0, 6.0])
+    assert np.array_equal(cv.control_multipliers(c, 4, 1.0), [1.0, -0.5, 2.0, 1.5])
+    # mu = 2: the service scale is 1/2, the weighted pair doubles
+    assert np.array_equal(cv.control_multipliers(c, 4, 2.0), [1.0, -0.5, 4.0, 3.0])
+
+
+def test_design_point_sd_and_training_multipliers():
+    rng = np.random.default_rng(9)
+    dp = np.repeat(np.arange(5), 16)
+    rng.shuffle(dp)
+    Y = rng.normal(size=dp.size) * (1 + dp)
+    Y[dp == 3] = 2.0
+    sd = cv.design_point_sd(Y, dp)
+    for d in range(5):
+        assert np.allclose(sd[dp == d], np.std(Y[dp == d], ddof=1), rtol=1e-13)
+    Z = rng.normal(size=(dp.size, 4))
+    M = cv.training_multipliers(Z, sd)
+    assert np.all(M[dp == 3] == 0.0)
+    ok = dp != 3
+    assert np.allclose(M[ok] * sd[ok, None], Z[ok], rtol=1e-13)
+    # the standardised target and the multipliers share the scale: a network
+    # predicting g fits t exactly when Y - mean_dp Y = sum_k g_k z_k
+    g = np.array([0.5, -1.0, 2.0, 0.25])
+    Y2 = Z @ g + 10.0 * dp
+    t = cv.standardized_target(Y2, dp)
+    M2 = cv.training_multipliers(Z - np.array([Z[dp == d].mean(0) for d in dp]),
+                                 cv.design_point_sd(Y2, dp))
+    assert np.allclose(cv.control_value(np.tile(g, (dp.size, 1)), M2), t, atol=1e-12)
 
 
 def test_known_mean_estimator_reduces_unbiased_and_matches_variance():

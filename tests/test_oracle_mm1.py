@@ -109,29 +109,97 @@ def test_closed_form_light_load():
     assert abs(m - 1.0) < 4 * se + 1e-3
 
 
-def test_post_prefix_net_input_obeys_flow_balance():
-    # T_n - T_{n-1} = S_n - A_n + I_n, so the net input after customer K-1 is
-    # T_{N-1} - T_{K-1} - sum_{n >= K} I_n (up to the fp32 rounding of T)
+def test_controls_hand_traced():
+    # (A, S) = ((1, 3), (2, 1), (0.5, 1)): T = (3, 2, 2.5); with means 1, 1
+    A = np.array([1.0, 2.0, 0.5], np.float32)
+    S = np.array([3.0, 1.0, 1.0], np.float32)
+    # K = 0: c0 = 2 + 0 + 0, c1 = 0 + 1 - 0.5, c2 = 0*2 + 3*0 + 2*0,
+    # c3 = 0*0 + 3*1 + 2*(-0.5)
+    assert list(core.mm1_injected(A, S, ctl_after=0)[4]) == [2.0, 0.5, 0.0, 2.0]
+    assert list(core.mm1_injected(A, S, ctl_after=1)[4]) == [0.0, 0.5, 0.0, 2.0]
+    assert list(core.mm1_injected(A, S, ctl_after=2)[4]) == [0.0, -0.5, 0.0, -1.0]
+    assert list(core.mm1_injected(A, S, ctl_after=3)[4]) == [0.0, 0.0, 0.0, 0.0]
+    # other means: c2 = 0*(3-0.5) + 3*(1-0.5) + 2*(1-0.5) = 2.5
+    c = core.mm1_injected(A, S, ctl_after=0, es=0.5, ea=2.0)[4]
+    assert list(c) == [3.5, -2.5, 2.5, -3.0]
+
+
+def test_controls_degenerate_inputs():
+    rng = np.random.default_rng(22)
+    N, K, es, ea = 700, 150, 1.0, 1.25
+    A = rng.exponential(1.25, N).astype(np.float32)
+    S = rng.exponential(1.0, N).astype(np.float32)
+    # S == 0: the system is always empty, T == 0, the weighted controls vanish
+    c = core.mm1_injected(A, np.zeros(N, np.float32), ctl_after=K, es=es, ea=ea)[4]
+    assert c[0] == -(N - K) * es and c[2] == 0.0 and c[3] == 0.0
+    assert abs(c[1] - (A[K:].astype(np.float64) - ea).sum()) < 1e-9
+    # A == 0: everyone arrives at once, T_n = S_0 + ... + S_n
+    _, _, T, _, c = core.mm1_injected(np.zeros(N, np.float32), S, ctl_after=K, es=es, ea=ea)
+    cum = np.cumsum(S.astype(np.float64))
+    prev = np.concatenate([[0.0], cum[:-1]])
+    want2 = np.sum(prev[K:] * (S[K:].astype(np.float64) - es))
+    want3 = np.sum(prev[K:] * (0.0 - ea))
+    # the oracle's T is the fp32 running sum: each T_n within n ulps of cum
+    tol = 2.0 ** -23 * N * np.sum(cum * (np.abs(S.astype(np.float64) - es) + ea))
+    assert abs(c[2] - want2) <= tol and abs(c[3] - want3) <= tol
+    assert np.max(np.abs(T - cum) / cum) < 2.0 ** -23 * N
+
+
+def test_controls_obey_flow_balance():
+    # T_n - T_{n-1} = S_n - A_n + I_n, so c0 - c1 + (N - K)(es - ea), the net
+    # input after customer K-1, is T_{N-1} - T_{K-1} - sum_{n >= K} I_n (up
+    # to the fp32 rounding of T)
     rng = np.random.default_rng(21)
-    N = 1500
+    N, es, ea = 1500, 0.997, 1.11
     for K, lam in ((0, 0.9), (200, 0.9), (700, 0.6), (N, 0.8), (N - 1, 1.2)):
         A = rng.exponential(1 / lam, N).astype(np.float32)
         S = rng.exponential(1.0, N).astype(np.float32)
-        W, I, T, _, post = core.mm1_injected(A, S, post_after=K)
+        W, I, T, _, c = core.mm1_injected(A, S, ctl_after=K, es=es, ea=ea)
         T64, I64 = T.astype(np.float64), I.astype(np.float64)
         tk = T64[K - 1] if K > 0 else 0.0
         want = T64[-1] - tk - I64[K:].sum()
+        got = c[0] - c[1] + (N - K) * (es - ea)
         tol = 2.0 ** -23 * np.abs(T64).sum() + 1e-9
-        assert abs(post - want) <= tol, (K, post, want)
+        assert abs(got - want) <= tol, (K, got, want)
 
 
-def test_post_prefix_net_input_has_the_variates_mean():
-    # E[post] = (N - K)(E[S] - E[A]) with the variates' exact means
+def test_variate_mean_is_the_grid_closed_form():
     from oracle import cv
-    N, K, lam, mu, R = 1200, 200, 0.8, 1.0, 3000
-    _, _, post = core.mm1_many(7, R, N, lam, mu, features=K, threads=8, post=True)
-    per = post / (N - K)
-    mean = cv.variate_mean(mu) - cv.variate_mean(lam)
-    se = np.sqrt((1.0 + 1.0 / lam ** 2) / (N - K) / R)
-    assert abs(per.mean() - mean) < 4 * se
-    assert abs(per.var(ddof=1) / ((1.0 + 1.0 / lam ** 2) / (N - K)) - 1) < 0.1
+    # the C oracle's lgamma and Python's agree to a few ulps
+    for rate in (0.5, 0.9, 1.0, 1.3, 3.7):
+        assert abs(core.variate_mean(rate) / cv.variate_mean(rate) - 1) < 1e-14
+    assert abs(core.variate_mean(1.0) - cv.LOG_GRID_MEAN) < 1e-14
+
+
+def test_controls_have_mean_zero_given_the_prefix():
+    # every control, alone or times a function of the first K customers'
+    # features, averages to zero over replications (the variates' exact
+    # means; the weight T_{n-1} precedes customer n's draws)
+    N, K, R = 900, 300, 4000
+    for lam in (0.6, 0.95):
+        _, feat, ctl = core.mm1_many(11, R, N, lam, 1.0, features=K, threads=8, ctl=True)
+        fs = [np.ones(R), np.tanh(feat[:, 9] / 5.0 - 1.0), feat[:, 6] - 0.5, feat[:, 4]]
+        for k in range(4):
+            for f in fs:
+                h = f * ctl[:, k]
+                assert abs(h.mean()) < 4 * h.std(ddof=1) / np.sqrt(R), (lam, k)
+        # the prefix statistics are independent of the unweighted pair
+        for j in range(2, 10):
+            for k in (0, 1):
+                assert abs(np.corrcoef(feat[:, j], ctl[:, k])[0, 1]) < 4 / np.sqrt(R)
+
+
+def test_controls_explain_the_mean_wait():
+    # perturbation analysis: a unit more work at load T delays the rest of
+    # its busy period, about lambda T / (1 - rho) customers, so the
+    # T-weighted pair carries coefficients near +-lambda / ((1 - rho) N) and
+    # the four controls explain most of the variance of the mean wait
+    N, K, R, lam = 20000, 1000, 1500, 0.9
+    out, _, ctl = core.mm1_many(12, R, N, lam, 1.0, features=K, threads=8, ctl=True)
+    Y = out[:, 0].astype(np.float64)
+    Xc = ctl - ctl.mean(0)
+    b, *_ = np.linalg.lstsq(Xc, Y - Y.mean(), rcond=None)
+    r2 = 1.0 - np.var(Y - Y.mean() - Xc @ b) / np.var(Y)
+    assert r2 > 0.85, r2
+    want = lam / (1 - lam) / N
+    assert abs(b[2] / want - 1) < 0.25 and abs(-b[3] / want - 1) < 0.25, b * N
