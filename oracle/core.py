@@ -153,10 +153,10 @@ def rw_many(seed, reps, walkers=64, grid=64, steps=1000, threads=1, rng="philox"
 def _mm1_call(fn, name, seed, rep, customers, lam, mu, dp, features, ctl):
     out = np.zeros(3, dtype=np.float32)
     feat = np.zeros(10, dtype=np.float32)
-    c4 = np.zeros(4, dtype=np.float64)
+    c8 = np.zeros(8, dtype=np.float64)
     _check(fn(seed, dp, rep, customers, lam, mu, features, out,
-              feat.ctypes.data if features else None, c4.ctypes.data if ctl else None), name)
-    res = (out,) + ((feat,) if features else ()) + ((c4,) if ctl else ())
+              feat.ctypes.data if features else None, c8.ctypes.data if ctl else None), name)
+    res = (out,) + ((feat,) if features else ()) + ((c8,) if ctl else ())
     return res if len(res) > 1 else out
 
 
@@ -167,14 +167,16 @@ def variate_mean(rate):
 
 def mm1(seed, rep, customers, lam, mu, dp=0, features=0, ctl=False):
     """(mean_wq, mean_T, mean_idle); when features > 0 also the 10 features;
-    with ctl, also the four controls over customers n >= features:
-    sum (S - E S), sum (A - E A), sum T_{n-1} (S - E S), sum T_{n-1} (A - E A)."""
+    with ctl, also the eight controls: over customers n >= features
+    sum (S - E S), sum (A - E A), sum T_{n-1} (S - E S), sum T_{n-1} (A - E A),
+    then the same four over customers n < features."""
     return _mm1_call(lib().oracle_mm1, "mm1", seed, rep, customers, lam, mu, dp, features, ctl)
 
 
 def mm1_injected(A, S, ctl_after=None, es=1.0, ea=1.0):
     """Per-customer W, I, T and the means on explicit arrays; with
-    ctl_after = K, also the four controls over n >= K with means es, ea."""
+    ctl_after = K, also the eight controls (n >= K, then n < K) with means
+    es, ea."""
     A = np.ascontiguousarray(A, dtype=np.float32)
     S = np.ascontiguousarray(S, dtype=np.float32)
     n = A.shape[0]
@@ -182,11 +184,11 @@ def mm1_injected(A, S, ctl_after=None, es=1.0, ea=1.0):
     I = np.zeros(n, np.float32)
     T = np.zeros(n, np.float32)
     out = np.zeros(3, np.float32)
-    c4 = np.zeros(4, np.float64)
+    c8 = np.zeros(8, np.float64)
     K = 0 if ctl_after is None else int(ctl_after)
     _check(lib().oracle_mm1_injected(A, S, n, K, es, ea, W.ctypes.data, I.ctypes.data,
-                                     T.ctypes.data, out, c4.ctypes.data), "mm1_injected")
-    return (W, I, T, out) if ctl_after is None else (W, I, T, out, c4)
+                                     T.ctypes.data, out, c8.ctypes.data), "mm1_injected")
+    return (W, I, T, out) if ctl_after is None else (W, I, T, out, c8)
 
 
 def mm1_taus(seed, rep, customers, lam, mu, dp=0, features=0, ctl=False):
@@ -209,7 +211,7 @@ def _stack(res, features, ctl):
 
 def mm1_many(seed, reps, customers, lam, mu, dp=0, features=0, threads=1, rng="philox",
              ctl=False):
-    """Outputs (R,3) float32, (R,10) features when requested, and the (R,4)
+    """Outputs (R,3) float32, (R,10) features when requested, and the (R,8)
     fp64 controls with ctl."""
     ids = list(range(reps)) if isinstance(reps, int) else list(reps)
     one = mm1 if rng == "philox" else mm1_taus

@@ -1,25 +1,26 @@
 """Control-variate estimator, oracle side -- TEST INFRASTRUCTURE ONLY.
 
-For one design point with n replications (Y_i, h_i), where h is a control of
-known mean zero fixed before the replications are drawn (up to the
-replication's own prefix, see below), and a coefficient beta fixed
-beforehand,
+For one design point with n replications (Y_i, F_i), where the columns of F
+are controls of known mean zero, and a coefficient vector a fixed
+beforehand (fitted on other replications),
 
-    Y_cv = mean_i(Y_i - beta h_i)
+    Y_cv = mean_i(Y_i - a . F_i)
 
-is unbiased for E[Y]; its variance estimate is s^2(Y - beta h)/n with a
+is unbiased for E[Y]; its variance estimate is s^2(Y - a . F)/n with a
 t_{n-1} interval. The plain estimate mean(Y) with its t_{n-1} interval is
 the fallback and the judge of the control's error.
 
-The control is h = sum_k g_k(X) z_k: four martingale controls z of the run
-after its first K customers (below), with coefficients g(X) the network
-predicts from the design's factor levels and summary statistics of those K
-customers.
+The controls are F = (h, z_pre): h = sum_k g_k(X) z_k with z the four
+martingale controls of the run after its first K customers (below) and
+coefficients g(X) the network predicts from the design's factor levels and
+summary statistics of those K customers; z_pre the same four controls over
+the first K customers. a is the per-bin-of-rho pooled least-squares fit of
+Y on F on held-out design points.
 
 Training's host steps (feature z-scores, the standardised within-design-
 point target and its multipliers, the held-out design points, and the
-per-bin pooled slope of Y on the control with its clamp at zero and
-nearest-bin fill) follow, one function each.
+per-bin pooled regression of Y on the controls with its nearest-bin fill)
+follow, one function each.
 """
 import math
 
@@ -107,50 +108,67 @@ def rho_bin(rho, lo, hi, bins):
     return min(max(k, 0), bins - 1)
 
 
-def pooled_slope_table(Y, G, dp, rho, lo, hi, bins=16):
-    """Per bin of rho: the pooled within-design-point least-squares slope of Y
-    on the control G, sum (Y - Ybar_dp)(G - Gbar_dp) / sum (G - Gbar_dp)^2
-    over the design points in the bin (rho taken per design point), clamped
-    at 0 so that a bin where the control does not help uses plain MRIP. A bin
-    with no variation of G takes the slope of its nearest bin that has some
-    (the lower one on a tie); with none anywhere every slope is 0."""
+def pooled_regression_table(Y, F, dp, rho, lo, hi, bins=16):
+    """Per bin of rho: the pooled within-design-point least-squares
+    coefficients of Y on the columns of F, i.e. the solution a_k of
+    (sum_dp Fc' Fc) a = sum_dp Fc' Yc over the design points in the bin
+    (rho taken per design point), with Fc, Yc centred on their design
+    point's means. A column without within-design-point variation in a bin
+    gets coefficient 0 there and leaves the system; a bin with no design
+    point takes the coefficients of its nearest bin that has one (the lower
+    one on a tie); with none anywhere every coefficient is 0. Returns
+    (bins, p) fp64."""
     Y = np.asarray(Y, np.float64)
-    G = np.asarray(G, np.float64)
+    F = np.asarray(F, np.float64)
+    if F.ndim == 1:
+        F = F[:, None]
     dp = np.asarray(dp)
     rho = np.asarray(rho)
-    sxy = [0.0] * bins
-    sxx = [0.0] * bins
+    p = F.shape[1]
+    A = np.zeros((bins, p, p))
+    b = np.zeros((bins, p))
+    seen = [False] * bins
     for d in sorted(set(dp.tolist())):
         idx = np.flatnonzero(dp == d)
-        my = sum(Y[i] for i in idx) / len(idx)
-        mg = sum(G[i] for i in idx) / len(idx)
+        Fc = F[idx] - F[idx].mean(axis=0)
+        Yc = Y[idx] - Y[idx].mean()
         k = rho_bin(rho[idx[0]], lo, hi, bins)
-        for i in idx:
-            sxy[k] += (Y[i] - my) * (G[i] - mg)
-            sxx[k] += (G[i] - mg) * (G[i] - mg)
-    beta = np.zeros(bins)
+        A[k] += Fc.T @ Fc
+        b[k] += Fc.T @ Yc
+        seen[k] = True
+    coef = np.zeros((bins, p))
+    for k in range(bins):
+        if not seen[k]:
+            continue
+        live = [j for j in range(p) if A[k, j, j] > 0.0]
+        if live:
+            coef[k, live] = np.linalg.solve(A[k][np.ix_(live, live)], b[k, live])
+    out = np.zeros((bins, p))
     for k in range(bins):
         src = None
         for dist in range(bins):
-            if k - dist >= 0 and sxx[k - dist] > 0.0:
+            if k - dist >= 0 and seen[k - dist]:
                 src = k - dist
                 break
-            if k + dist < bins and sxx[k + dist] > 0.0:
+            if k + dist < bins and seen[k + dist]:
                 src = k + dist
                 break
-        beta[k] = 0.0 if src is None else max(0.0, sxy[src] / sxx[src])
-    return beta
+        if src is not None:
+            out[k] = coef[src]
+    return out
 
 
 # ------------------------------------------------- the martingale controls
 # Four controls over the customers after the feature prefix (n >= K):
 #   c0 = sum (S_n - E S), c1 = sum (A_n - E A),
-#   c2 = sum T_{n-1} (S_n - E S), c3 = sum T_{n-1} (A_n - E A).
+#   c2 = sum T_{n-1} (S_n - E S), c3 = sum T_{n-1} (A_n - E A),
+# and c4..c7, the same sums over the prefix (n < K).
 # A_n and S_n are drawn independently of everything before customer n, so
 # each term has mean zero given the past (martingale differences). Any
 # function of the first K customers, the network's coefficients included,
-# times any c_k therefore has mean zero, and Y - h stays unbiased for E[Y]
-# with no second sample. The means are the variates' exact ones.
+# times any of c0..c3 therefore has mean zero, c4..c7 have mean zero, and
+# Y - a . F stays unbiased for E[Y] with no second sample. The means are
+# the variates' exact ones.
 
 # E[-ln u] for u = (k + 1) 2^-24, k uniform on [0, 2^24): the mean of the
 # exponential variate's inversion on its 24-bit grid, in closed form
@@ -167,14 +185,14 @@ def variate_mean(rate):
 
 
 def control_multipliers(ctl, customers, mu):
-    """The network's per-sample multipliers z from the four controls of a
-    replication of N customers: c / N, the two T-weighted controls also
-    divided by the service scale (float)(1 / mu), so that all four are in
-    time units per customer and the coefficients are plain numbers. A fixed
-    rescaling per design point keeps every mean zero."""
+    """The per-sample multipliers from a replication's controls (4 or 8 of
+    them) over a run of N customers: c / N, the T-weighted ones also divided
+    by the service scale (float)(1 / mu), so that all are in time units per
+    customer and their coefficients are plain numbers. A fixed rescaling per
+    design point keeps every mean zero."""
     ctl = np.asarray(ctl, np.float64)
     ms = float(np.float32(1.0 / float(np.float32(mu))))
-    scale = np.array([1.0, 1.0, 1.0 / ms, 1.0 / ms]) / float(customers)
+    scale = np.array([1.0, 1.0, 1.0 / ms, 1.0 / ms] * (ctl.shape[-1] // 4)) / float(customers)
     return ctl * scale
 
 
@@ -211,11 +229,16 @@ def control_value(G, Z):
     return np.sum(G * Z, axis=1)
 
 
-def known_mean_control_variate(Y, H, beta, confidence=0.95):
-    """mean(Y - beta H) for a control H of known mean 0, with the variance
-    s^2(Y - beta H) / n and a t_{n-1} interval (beta fixed beforehand)."""
-    Y, H = (np.asarray(a, np.float64) for a in (Y, H))
+def known_mean_control_variate(Y, F, coef, confidence=0.95):
+    """mean(Y - F . coef) for controls F (n, or n x p) of known mean 0, with
+    the variance s^2(Y - F . coef) / n and a t_{n-1} interval (coef fixed
+    beforehand)."""
+    Y = np.asarray(Y, np.float64)
+    F = np.asarray(F, np.float64)
+    if F.ndim == 1:
+        F = F[:, None]
+    coef = np.atleast_1d(np.asarray(coef, np.float64))
     n = Y.shape[0]
-    m, v = _mean_var(Y - beta * H)
+    m, v = _mean_var(Y - F @ coef)
     tq = t_quantile(0.5 + confidence / 2.0, n - 1)
     return dict(mean=m, var=v / n, half_width=tq * math.sqrt(v / n), dof=float(n - 1))

@@ -200,16 +200,18 @@ EXPORT int oracle_rw_injected(const uint8_t *dirs, uint32_t walkers, uint32_t gr
 /* and four controls over the customers after them, n >= K, in fp64:       */
 /*   c0 = sum (S_n - E S)          c1 = sum (A_n - E A)                     */
 /*   c2 = sum T_{n-1} (S_n - E S)  c3 = sum T_{n-1} (A_n - E A)              */
-/* with E S, E A the variates' exact means. A_n and S_n are independent of  */
+/* then c4..c7, the same four sums over the prefix, n < K.                 */
+/* E S, E A are the variates' exact means. A_n and S_n are independent of  */
 /* everything before customer n, T_{n-1} included, so every term has mean  */
-/* zero given the past: each c_k times any function of the first K         */
-/* customers has mean zero (sums of martingale differences).               */
+/* zero given the past: each of c0..c3 times any function of the first K   */
+/* customers has mean zero, and so has each of c4..c7 (sums of martingale */
+/* differences).                                                           */
 /* ------------------------------------------------------------------------ */
 typedef struct {
   double sum_w, sum_t, sum_i;
   double f_sum_a, f_sum_s, f_sum_w, f_sum_t, f_sum_i, f_zero, f_max_w, f_last_t;
   double es, ea;  /* exact means of S and A */
-  double ctl[4];
+  double ctl[8];  /* after the prefix (0..3), over it (4..7) */
 } mm1_acc;
 
 /* E[-ln u] for u = (k + 1) 2^-24, k uniform on [0, 2^24): the average of   */
@@ -226,12 +228,13 @@ EXPORT double oracle_variate_mean(float rate) {
 
 static void mm1_customer(float a, float s, float *t_prev, uint64_t n, uint64_t K,
                          mm1_acc *acc, float *w_out, float *i_out, float *t_out) {
-  if (n >= K) {
+  {
     double ds = (double)s - acc->es, da = (double)a - acc->ea, tp = (double)*t_prev;
-    acc->ctl[0] += ds;
-    acc->ctl[1] += da;
-    acc->ctl[2] += tp * ds;
-    acc->ctl[3] += tp * da;
+    double *c = acc->ctl + (n >= K ? 0 : 4);
+    c[0] += ds;
+    c[1] += da;
+    c[2] += tp * ds;
+    c[3] += tp * da;
   }
   float w = fmaxf(0.0f, *t_prev - a);
   float idle = fmaxf(0.0f, a - *t_prev);
@@ -282,7 +285,7 @@ static void mm1_start(mm1_acc *acc, float lambda, float mu) {
 }
 
 /* out[3] = {mean W, mean T, mean I}; feat[10] written when K > 0, and
- * ctl[4] (nullable) the four controls over n >= K. */
+ * ctl[8] (nullable) the four controls over n >= K, then over n < K. */
 EXPORT int oracle_mm1(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, float lambda,
                       float mu, uint64_t K, float out[3], float *feat, double *ctl) {
   if (N == 0 || K > N) return -1;
@@ -303,8 +306,8 @@ EXPORT int oracle_mm1(uint64_t seed, uint32_t dp, uint32_t rep, uint64_t N, floa
 }
 
 /* Test seam: explicit interarrival/service arrays; per-customer W, I, T
- * (any of them may be NULL), the three means and, after a prefix of K
- * customers, the four controls with the given means es, ea (nullable). */
+ * (any of them may be NULL), the three means and, for a prefix of K
+ * customers, the eight controls with the given means es, ea (nullable). */
 EXPORT int oracle_mm1_injected(const float *A, const float *S, uint64_t N, uint64_t K, double es,
                                double ea, float *W, float *I, float *T, float out[3],
                                double *ctl) {

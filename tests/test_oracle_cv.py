@@ -3,8 +3,9 @@
 Independent facts used: a zero control reduces the estimator exactly to the
 plain mean; it is unbiased with the Monte Carlo variance in a model with a
 known mean; numpy's own statistics for the z-scores; least squares on the
-demeaned data for the pooled slopes; the exhaustive average of -ln u over
-its 2^24-point grid for the variates' mean.
+demeaned data (numpy's lstsq on the stacked deviations) for the pooled
+regression, and exact recovery of a noise-free linear law; the exhaustive
+average of -ln u over its 2^24-point grid for the variates' mean.
 """
 import math
 
@@ -81,49 +82,67 @@ def _binned_design(rng, bins_used, reps=24, per_bin=6, lo=0.5, hi=0.95):
     return np.array(dp), np.array(rho, np.float32)
 
 
-def test_pooled_slope_recovers_a_linear_law_and_equals_demeaned_least_squares():
+def _deviations(v, sel, dp):
+    return np.concatenate([v[sel & (dp == d)] - v[sel & (dp == d)].mean(axis=0)
+                           for d in np.unique(dp[sel])])
+
+
+def test_pooled_regression_recovers_a_linear_law_and_equals_demeaned_least_squares():
     rng = np.random.default_rng(5)
     dp, rho = _binned_design(rng, range(16))
     k_of = np.array([cv.rho_bin(r, 0.5, 0.95, 16) for r in rho])
-    a = 0.2 + 0.1 * k_of  # true slope per bin
-    G = rng.normal(size=dp.size) + 3.0 * dp  # per-dp offsets in the control ...
-    Y = a * G + 50.0 * dp  # ... and in the response do not matter
-    beta = cv.pooled_slope_table(Y, G, dp, rho, 0.5, 0.95)
-    assert np.allclose(beta, 0.2 + 0.1 * np.arange(16), rtol=1e-10)
+    a = np.stack([0.2 + 0.1 * k_of, -1.0 + 0.05 * k_of, 3.0 - 0.2 * k_of], axis=1)
+    # per-dp offsets in the controls and in the response do not matter
+    F = rng.normal(size=(dp.size, 3)) + np.stack([3.0 * dp, -dp, 0.5 * dp], axis=1)
+    Y = np.sum(a * F, axis=1) + 50.0 * dp
+    coef = cv.pooled_regression_table(Y, F, dp, rho, 0.5, 0.95)
+    want = np.stack([0.2 + 0.1 * np.arange(16), -1.0 + 0.05 * np.arange(16),
+                     3.0 - 0.2 * np.arange(16)], axis=1)
+    assert np.allclose(coef, want, rtol=1e-9, atol=1e-10)
     # with noise: each bin equals least squares on the within-dp deviations
     Yn = Y + 0.3 * rng.normal(size=dp.size)
-    beta = cv.pooled_slope_table(Yn, G, dp, rho, 0.5, 0.95)
+    coef = cv.pooled_regression_table(Yn, F, dp, rho, 0.5, 0.95)
     for k in range(16):
         sel = k_of == k
-        yd = np.concatenate([Yn[sel & (dp == d)] - Yn[sel & (dp == d)].mean()
-                             for d in np.unique(dp[sel])])
-        gd = np.concatenate([G[sel & (dp == d)] - G[sel & (dp == d)].mean()
-                             for d in np.unique(dp[sel])])
-        ls = np.linalg.lstsq(gd[:, None], yd, rcond=None)[0][0]
-        assert abs(beta[k] - max(ls, 0.0)) < 1e-10
-        se = 0.3 / np.sqrt(np.sum(gd * gd))
-        assert abs(beta[k] - (0.2 + 0.1 * k)) < 4 * se
+        ls = np.linalg.lstsq(_deviations(F, sel, dp), _deviations(Yn, sel, dp), rcond=None)[0]
+        assert np.allclose(coef[k], ls, rtol=1e-9, atol=1e-12)
+    # one column: the pooled slope sum(dy dg) / sum(dg^2), written out
+    G = F[:, 0]
+    one = cv.pooled_regression_table(Yn, G, dp, rho, 0.5, 0.95)
+    for k in range(16):
+        sel = k_of == k
+        gd, yd = _deviations(G, sel, dp), _deviations(Yn, sel, dp)
+        sxy = sxx = 0.0
+        for u, v in zip(gd, yd):
+            sxy += u * v
+            sxx += u * u
+        assert abs(one[k, 0] - sxy / sxx) < 1e-10 * abs(sxy / sxx)
 
 
-def test_pooled_slope_constant_network_negative_slope_and_neighbour_fill():
+def test_pooled_regression_degenerate_columns_and_neighbour_fill():
     rng = np.random.default_rng(6)
     dp, rho = _binned_design(rng, range(16))
     Y = rng.normal(size=dp.size)
-    # a network constant within every design point (fp32 outputs, as the
-    # network gives them) gives no slope anywhere
-    G = (0.7 * dp).astype(np.float32).astype(np.float64)
-    assert np.all(cv.pooled_slope_table(Y, G, dp, rho, 0.5, 0.95) == 0.0)
-    # a control that moves against Y is clamped to plain MRIP
+    # a column constant within every design point (a constant network's
+    # control) gets 0 and leaves the others' fit unchanged
+    F = np.stack([(0.7 * dp).astype(np.float32).astype(np.float64), rng.normal(size=dp.size)],
+                 axis=1)
+    both = cv.pooled_regression_table(Y, F, dp, rho, 0.5, 0.95)
+    alone = cv.pooled_regression_table(Y, F[:, 1], dp, rho, 0.5, 0.95)
+    assert np.all(both[:, 0] == 0.0) and np.allclose(both[:, 1], alone[:, 0], rtol=1e-12)
+    # a control that moves against Y keeps its sign (no clamp)
     G = rng.normal(size=dp.size)
-    assert np.all(cv.pooled_slope_table(-2.0 * G, G, dp, rho, 0.5, 0.95) == 0.0)
+    assert np.allclose(cv.pooled_regression_table(-2.0 * G, G, dp, rho, 0.5, 0.95), -2.0)
     # only bins 3 and 9 hold design points: the others borrow the nearest,
     # the lower one on a tie (bin 6 is 3 from both)
     dp, rho = _binned_design(rng, [3, 9])
     G = rng.normal(size=dp.size)
     k_of = np.array([cv.rho_bin(r, 0.5, 0.95, 16) for r in rho])
     Y = np.where(k_of == 3, 1.5, 4.0) * G
-    beta = cv.pooled_slope_table(Y, G, dp, rho, 0.5, 0.95)
-    assert np.allclose(beta[:7], 1.5) and np.allclose(beta[7:], 4.0)
+    coef = cv.pooled_regression_table(Y, G, dp, rho, 0.5, 0.95)[:, 0]
+    assert np.allclose(coef[:7], 1.5) and np.allclose(coef[7:], 4.0)
+    # no design point at all: every coefficient 0
+    assert np.all(cv.pooled_regression_table(Y[:0], G[:0], dp[:0], rho[:0], 0.5, 0.95) == 0)
 
 
 # ------------------------------------------------- the martingale controls
@@ -140,6 +159,10 @@ def test_control_multipliers_scale_per_customer_and_service_time():
     assert np.array_equal(cv.control_multipliers(c, 4, 1.0), [1.0, -0.5, 2.0, 1.5])
     # mu = 2: the service scale is 1/2, the weighted pair doubles
     assert np.array_equal(cv.control_multipliers(c, 4, 2.0), [1.0, -0.5, 4.0, 3.0])
+    # all eight: the prefix four scale the same way, by the whole run length
+    c8 = np.concatenate([c, 2.0 * c])
+    assert np.array_equal(cv.control_multipliers(c8, 4, 2.0),
+                          [1.0, -0.5, 4.0, 3.0, 2.0, -1.0, 8.0, 6.0])
 
 
 def test_design_point_sd_and_training_multipliers():
@@ -169,7 +192,7 @@ def test_design_point_sd_and_training_multipliers():
 def test_known_mean_estimator_reduces_unbiased_and_matches_variance():
     rng = np.random.default_rng(8)
     Y = rng.normal(3.0, 2.0, 64)
-    zero = cv.known_mean_control_variate(Y, np.zeros(64), beta=2.0)
+    zero = cv.known_mean_control_variate(Y, np.zeros(64), 2.0)
     pl = cv.plain(Y)
     assert abs(zero["mean"] - pl["mean"]) < 1e-12 and abs(zero["var"] - pl["var"]) < 1e-12
     # Y = 1 + 2 H + e with E[H] = 0: unbiased, variance 0.25 / n
@@ -178,7 +201,7 @@ def test_known_mean_estimator_reduces_unbiased_and_matches_variance():
     for _ in range(K):
         H = rng.normal(size=n)
         Yk = 1.0 + 2.0 * H + 0.5 * rng.normal(size=n)
-        r = cv.known_mean_control_variate(Yk, H, beta=2.0)
+        r = cv.known_mean_control_variate(Yk, H, 2.0)
         ests.append(r["mean"])
         vs.append(r["var"])
     ests = np.array(ests)
@@ -186,4 +209,11 @@ def test_known_mean_estimator_reduces_unbiased_and_matches_variance():
     assert abs(ests.var() / (0.25 / n) - 1) < 4 * np.sqrt(2.0 / K)
     assert abs(np.mean(vs) / (0.25 / n) - 1) < 0.05
     H = rng.normal(size=n)
-    assert cv.known_mean_control_variate(5.0 + 3.0 * H, H, beta=3.0)["var"] < 1e-28
+    assert cv.known_mean_control_variate(5.0 + 3.0 * H, H, 3.0)["var"] < 1e-28
+    # several columns: Y - F a written out per replication
+    F = rng.normal(size=(n, 3))
+    a = np.array([0.5, -2.0, 1.25])
+    Y = 2.0 + F @ a + 0.1 * rng.normal(size=n)
+    r = cv.known_mean_control_variate(Y, F, a)
+    d = [Y[i] - (F[i, 0] * a[0] + F[i, 1] * a[1] + F[i, 2] * a[2]) for i in range(n)]
+    assert abs(r["mean"] - np.mean(d)) < 1e-12 and abs(r["var"] - np.var(d, ddof=1) / n) < 1e-14

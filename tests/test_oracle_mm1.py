@@ -114,14 +114,32 @@ def test_controls_hand_traced():
     A = np.array([1.0, 2.0, 0.5], np.float32)
     S = np.array([3.0, 1.0, 1.0], np.float32)
     # K = 0: c0 = 2 + 0 + 0, c1 = 0 + 1 - 0.5, c2 = 0*2 + 3*0 + 2*0,
-    # c3 = 0*0 + 3*1 + 2*(-0.5)
-    assert list(core.mm1_injected(A, S, ctl_after=0)[4]) == [2.0, 0.5, 0.0, 2.0]
-    assert list(core.mm1_injected(A, S, ctl_after=1)[4]) == [0.0, 0.5, 0.0, 2.0]
-    assert list(core.mm1_injected(A, S, ctl_after=2)[4]) == [0.0, -0.5, 0.0, -1.0]
-    assert list(core.mm1_injected(A, S, ctl_after=3)[4]) == [0.0, 0.0, 0.0, 0.0]
+    # c3 = 0*0 + 3*1 + 2*(-0.5); nothing in the prefix
+    assert list(core.mm1_injected(A, S, ctl_after=0)[4]) == [2.0, 0.5, 0.0, 2.0, 0, 0, 0, 0]
+    # K = 1: customer 0 (ds 2, da 0, T_{-1} = 0) moves to the prefix four
+    assert list(core.mm1_injected(A, S, ctl_after=1)[4]) == [0.0, 0.5, 0.0, 2.0, 2, 0, 0, 0]
+    # K = 2: the prefix holds customers 0, 1: (2 + 0, 0 + 1, 0 + 3*0, 0 + 3*1)
+    assert list(core.mm1_injected(A, S, ctl_after=2)[4]) == [0.0, -0.5, 0.0, -1.0, 2, 1, 0, 3]
+    assert list(core.mm1_injected(A, S, ctl_after=3)[4]) == [0.0, 0.0, 0.0, 0.0, 2, 0.5, 0, 2]
     # other means: c2 = 0*(3-0.5) + 3*(1-0.5) + 2*(1-0.5) = 2.5
     c = core.mm1_injected(A, S, ctl_after=0, es=0.5, ea=2.0)[4]
-    assert list(c) == [3.5, -2.5, 2.5, -3.0]
+    assert list(c[:4]) == [3.5, -2.5, 2.5, -3.0]
+
+
+def test_prefix_and_post_prefix_controls_partition_the_run():
+    # every customer's terms go to exactly one of the two sets: for any K
+    # the prefix four plus the post-prefix four are the whole run's four
+    rng = np.random.default_rng(23)
+    N, es, ea = 900, 0.99, 1.2
+    A = rng.exponential(1.2, N).astype(np.float32)
+    S = rng.exponential(1.0, N).astype(np.float32)
+    whole = core.mm1_injected(A, S, ctl_after=0, es=es, ea=ea)[4][:4]
+    scale = np.abs(whole).max() + N
+    for K in (1, 17, 450, N - 1, N):
+        c = core.mm1_injected(A, S, ctl_after=K, es=es, ea=ea)[4]
+        assert np.all(np.abs(c[:4] + c[4:] - whole) <= 1e-12 * scale), K
+    # K = N: the prefix four are the whole run's
+    assert np.array_equal(core.mm1_injected(A, S, ctl_after=N, es=es, ea=ea)[4][4:], whole)
 
 
 def test_controls_degenerate_inputs():
@@ -172,9 +190,10 @@ def test_variate_mean_is_the_grid_closed_form():
 
 
 def test_controls_have_mean_zero_given_the_prefix():
-    # every control, alone or times a function of the first K customers'
-    # features, averages to zero over replications (the variates' exact
-    # means; the weight T_{n-1} precedes customer n's draws)
+    # every post-prefix control, alone or times a function of the first K
+    # customers' features, averages to zero over replications (the variates'
+    # exact means; the weight T_{n-1} precedes customer n's draws), and so
+    # does every prefix control alone
     N, K, R = 900, 300, 4000
     for lam in (0.6, 0.95):
         _, feat, ctl = core.mm1_many(11, R, N, lam, 1.0, features=K, threads=8, ctl=True)
@@ -183,6 +202,9 @@ def test_controls_have_mean_zero_given_the_prefix():
             for f in fs:
                 h = f * ctl[:, k]
                 assert abs(h.mean()) < 4 * h.std(ddof=1) / np.sqrt(R), (lam, k)
+        for k in range(4, 8):
+            h = ctl[:, k]
+            assert abs(h.mean()) < 4 * h.std(ddof=1) / np.sqrt(R), (lam, k)
         # the prefix statistics are independent of the unweighted pair
         for j in range(2, 10):
             for k in (0, 1):
@@ -197,7 +219,7 @@ def test_controls_explain_the_mean_wait():
     N, K, R, lam = 20000, 1000, 1500, 0.9
     out, _, ctl = core.mm1_many(12, R, N, lam, 1.0, features=K, threads=8, ctl=True)
     Y = out[:, 0].astype(np.float64)
-    Xc = ctl - ctl.mean(0)
+    Xc = ctl[:, :4] - ctl[:, :4].mean(0)
     b, *_ = np.linalg.lstsq(Xc, Y - Y.mean(), rcond=None)
     r2 = 1.0 - np.var(Y - Y.mean() - Xc @ b) / np.var(Y)
     assert r2 > 0.85, r2
