@@ -122,7 +122,18 @@ typedef struct {
  *          2 = mean I (server idle time per arrival), all fp32;
  *          3 = when feature_prefix K > 0, 10 fp32 features per replication
  *              over customers 0..K-1: rho, mu, mean A, mean S, mean W,
- *              mean T, fraction with W = 0, max W, mean I, T_{K-1}.
+ *              mean T, fraction with W = 0, max W, mean I, T_{K-1};
+ *          4 = when K > 0, 8 fp32 controls per replication: over
+ *              customers n = K..N-1 sum (S_n - E S), sum (A_n - E A),
+ *              sum T_{n-1} (S_n - E S), sum T_{n-1} (A_n - E A), then the
+ *              same four over n = 0..K-1. E S and E A are the variates'
+ *              means as drawn, (float)(1/rate) times the mean of -ln u over
+ *              the 24-bit grid of u, in fp32. A_n and S_n are independent
+ *              of everything before customer n, so each term has mean zero
+ *              given the past (martingale differences): so has each of the
+ *              first four times any function of customers 0..K-1, and each
+ *              of the last four (up to the rounding of E S, E A and of the
+ *              variates).
  * mrip_run uses dp = 0. Requires 1 <= customers < 2^33, K <= customers. */
 typedef struct {
   uint32_t size;
@@ -236,16 +247,18 @@ MRIP_API mrip_status mrip_stats_back(mrip_ctx ctx, uint32_t back, uint32_t outpu
                                      double confidence, mrip_stats_t *out);
 
 /* Copy output `output` of the last run (n_reps values; 10 per replication
- * for M/M/1 features) to dst, a device pointer if dst_is_device, else host.
+ * for M/M/1 features, 8 for the controls) to dst, a device pointer if
+ * dst_is_device, else host.
  * `bytes` must be at least the output's size. Synchronises. */
 MRIP_API mrip_status mrip_outputs(mrip_ctx ctx, uint32_t output, void *dst, uint64_t bytes,
                          int dst_is_device);
 
 /* Bind a caller-owned device buffer (for example a torch tensor) as output
- * `output` (a scalar output, or 3 = the M/M/1 features): later runs and
- * plan runs write there instead of into a buffer of the context, and the
- * statistics reduce it. It must hold at least the run's output (n values,
- * 4 bytes each, 40 per replication for features; MRIP_E_INVAL at the run
+ * `output` (a scalar output, 3 = the M/M/1 features or 4 = the controls):
+ * later runs and plan runs write there instead of into a buffer of the
+ * context, and the statistics reduce it. It must hold at least the run's
+ * output (n values, 4 bytes each, 40 per replication for features and 32
+ * for the controls; MRIP_E_INVAL at the run
  * otherwise), be 4-byte aligned, and stay alive until the run's results
  * have been read. ptr_dev NULL unbinds (back to the context's buffer). */
 MRIP_API mrip_status mrip_bind_output(mrip_ctx ctx, uint32_t output, void *ptr_dev, uint64_t bytes);
@@ -321,24 +334,39 @@ MRIP_API mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_i
                           uint32_t *best_rpw, uint32_t *best_workgroup, float *best_ms);
 
 /* ----------------------------------------- learned control variate (CV) */
-/* Not in the paper: a small network g(x) maps the first K customers' summary
- * features x of an M/M/1 replication to a prediction of its mean wait Y; the
- * two-phase estimator mean(Y - beta g(X)) + beta mean(g(X')) over full and
- * independent prefix-only replications stays unbiased for any g. */
+/* Not in the paper; it extends MRIP's estimator (section 1: the mean of
+ * independent replications with a Student-t interval). Per replication of
+ * an M/M/1 context with feature prefix K, the controls are F = (h, z_pre):
+ *     h = sum_k g_k(x) z_k,
+ * z the first four controls of output 4 (after the prefix) divided by the
+ * run length N (the two T-weighted ones also by the service scale
+ * (float)(1/mu)), g a small network's four outputs from the prefix features
+ * x (output 3, z-scored); z_pre the last four (over the prefix), scaled the
+ * same way. Since every control term has mean zero given the past and g
+ * depends on customers 0..K-1 only, E[F] = 0 for any network: Y - a . F,
+ * with a fixed beforehand per bin of rho, is unbiased for E[Y], and no
+ * extra replications estimate E[F]. The plain estimate stays the fallback
+ * and the judge of the error. */
 
-#define MRIP_MLP_PARAMS 18049 /* W1[128x10] b1[128] W2[128x128] b2[128] W3[1x128] b3[1] */
-#define MRIP_CV_BETA_BINS 16  /* control coefficients over equal bins of rho */
+#define MRIP_MLP_OUT 4        /* network outputs: one coefficient per control */
+#define MRIP_MLP_PARAMS 18436 /* W1[128x10] b1[128] W2[128x128] b2[128] W3[4x128] b3[4] */
+#define MRIP_CV_BETA_BINS 16  /* coefficient rows over equal bins of rho */
+#define MRIP_CV_COEFS 5       /* per row: the network's control h, then the 4 prefix controls */
 
-/* Forward pass of the 10-128-128-1 ReLU network, bf16 operands with fp32
+/* Forward pass of the 10-128-128-4 ReLU network, bf16 operands with fp32
  * accumulation. theta_dev: MRIP_MLP_PARAMS fp32; x_dev: n x 10 fp32
- * (normalised features); y_dev: n fp32; n < 2^30. */
+ * (normalised features); y_dev: n x 4 fp32, 16-byte aligned; n < 2^30.
+ * Device pointers; MRIP_E_INVAL on a NULL or misaligned pointer. */
 MRIP_API mrip_status mrip_mlp_forward(const float *theta_dev, const float *x_dev, uint64_t n,
                              float *y_dev, void *hip_stream);
 
-/* Gradient of mean((g(x) - y)^2) over the n rows: grad_dev gets
- * MRIP_MLP_PARAMS fp32 values, loss_dev one fp32 (nullable). n <= 65536. */
-MRIP_API mrip_status mrip_mlp_grad(const float *theta_dev, const float *x_dev, const float *y_dev,
-                          uint64_t n, float *grad_dev, float *loss_dev, void *hip_stream);
+/* Gradient of mean((sum_k g_k(x) z_k - y)^2) over the n rows, with z_dev
+ * n x 4 fp32 per-row multipliers (16-byte aligned), or NULL for z = (1, 0,
+ * 0, 0) (the first output alone): grad_dev gets MRIP_MLP_PARAMS fp32
+ * values, loss_dev one fp32 (nullable). n <= 65536. Synchronises. */
+MRIP_API mrip_status mrip_mlp_grad(const float *theta_dev, const float *x_dev, const float *z_dev,
+                          const float *y_dev, uint64_t n, float *grad_dev, float *loss_dev,
+                          void *hip_stream);
 
 /* One Adam step (Kingma and Ba 2015, Algorithm 1) on fp32 weights;
  * `step` counts from 1; n_params <= 2^32 - 256. */
@@ -353,58 +381,66 @@ typedef struct {
 } mrip_cv_hparams;
 
 /* Generate the training set with the M/M/1 engine (items: design points
- * with at least two replications each; features over the context's
- * feature_prefix customers; response Y = mean W), and train the network
- * from theta0 (host, MRIP_MLP_PARAMS fp32) with Adam on z-scored features
- * and the target (Y - mean_dp Y) / sd_dp Y, the replication's standardised
- * deviation within its design point, over the first four fifths of the
- * design points. On the held-out fifth, fit the control coefficient of each
- * of MRIP_CV_BETA_BINS equal bins of rho = lambda/mu: the pooled
- * within-design-point slope of Y on g(X), clamped at 0 (an empty bin takes
- * its nearest neighbour's). hparams nullable (defaults). Synchronises. */
+ * with at least two replications each, disjoint from later apply items;
+ * features over the context's feature_prefix customers, the controls after
+ * them; response Y = mean W) and train the network from theta0 (host,
+ * MRIP_MLP_PARAMS fp32) with Adam on z-scored features: the target is the
+ * replication's standardised deviation within its design point,
+ * t = (Y - mean_dp Y) / sd_dp Y, fitted by sum_k g_k(x) z_k / sd_dp, over
+ * the first four fifths of the design points (ascending ids). On the
+ * held-out fifth, fit the coefficient row of each of MRIP_CV_BETA_BINS
+ * equal bins of rho = lambda/mu over the training range: the pooled
+ * within-design-point least-squares coefficients of Y on F = (h, z_pre); a
+ * column without within-design-point variation in a bin gets 0 there, and a
+ * bin without design points takes its nearest neighbour's row (the lower on
+ * a tie). hparams nullable (defaults). Host item table; synchronises. */
 MRIP_API mrip_status mrip_cv_train(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n,
                           const float *theta0, const mrip_cv_hparams *hparams, uint64_t seed,
                           void *hip_stream);
 
 /* Copy the model to host buffers (any may be NULL): weights
  * (MRIP_MLP_PARAMS), feature mean and std (10 + 10), the coefficient table
- * (MRIP_CV_BETA_BINS), its rho range (2) and the last epoch's mean training
- * loss (in units of the standardised target: 1 = no skill). */
+ * (MRIP_CV_BETA_BINS x MRIP_CV_COEFS, row-major), its rho range (2) and the
+ * last epoch's mean training loss (in units of the standardised target:
+ * 1 = no skill). */
 MRIP_API mrip_status mrip_cv_model(mrip_ctx ctx, float *theta, float *feat_mean, float *feat_std,
-                                   float *beta_table, float *rho_range, float *final_loss);
+                                   float *coef_table, float *rho_range, float *final_loss);
 
 /* Install a model instead of training one: theta (MRIP_MLP_PARAMS fp32),
  * feature mean / std (10 + 10 fp32, std > 0), the coefficient table
- * (MRIP_CV_BETA_BINS values >= 0) over rho in [rho_lo, rho_hi]; the
- * control is g(x) = net((x - mean) / std). Host pointers. */
+ * (MRIP_CV_BETA_BINS x MRIP_CV_COEFS finite values) over rho in
+ * [rho_lo, rho_hi]; the network's coefficients are g(x) = net((x - mean) /
+ * std). Host pointers. */
 MRIP_API mrip_status mrip_cv_set_model(mrip_ctx ctx, const float *theta, const float *feat_mean,
-                                       const float *feat_std, const float *beta_table,
+                                       const float *feat_std, const float *coef_table,
                                        float rho_lo, float rho_hi);
 
-/* Apply the trained control variate: full items (features + mean W) and
- * prefix-only items (customers >= feature prefix, stream ids disjoint from
- * the full ones) grouped by dp. Per design point with n full and M prefix
- * replications, beta_dp = beta[bin(rho)] * M / (M + n) (the
- * variance-minimising coefficient when E[g] is itself estimated from M
- * replications), and Y_cv = mean(Y) - beta_dp (mean g(X) - mean g(X')),
- * unbiased for any fixed network and coefficients. Synchronises. */
-MRIP_API mrip_status mrip_cv_apply(mrip_ctx ctx, const mrip_plan_item *full, uint64_t n_full,
-                          const mrip_plan_item *prefix, uint64_t n_prefix, uint64_t seed,
-                          void *hip_stream);
+/* Apply the trained control variate to n items (host table, at least two
+ * replications per design point): one run of the persistent engine with
+ * features and controls, inference, and per design point with n
+ * replications and a = the table's row at bin(rho):
+ *     Y_cv = mean(Y - a . F),  var = s^2(Y - a . F) / n,  dof n - 1,
+ * unbiased for any fixed network and table, beside the plain estimate
+ * mean(Y), s^2(Y) / n. Synchronises. */
+MRIP_API mrip_status mrip_cv_apply(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n,
+                          uint64_t seed, void *hip_stream);
 
-/* Per-replication values of the last apply, in item order: which = 0 mean W
- * of the full items, 1 g(X) of the full items, 2 g(X') of the prefix items,
- * 3 features of the full items (10 each), 4 features of the prefix items.
- * Host destination, `bytes` at least the output size. Synchronises. */
+/* Per-replication values, in item order, to a host buffer of at least the
+ * output's size. Of the last apply: which = 0 Y (mean W), 1 the network's
+ * control h, 2 the network outputs g (4 each), 3 the features (10 each), 4
+ * the raw controls (8 each, as output 4 of a run). Of the training run
+ * behind the model (MRIP_E_STATE after mrip_cv_set_model): 5 Y, 6 the
+ * features, 7 the raw controls, 8 the trained network's outputs.
+ * Synchronises. */
 MRIP_API mrip_status mrip_cv_outputs(mrip_ctx ctx, uint32_t which, void *dst, uint64_t bytes);
 
 /* CV and plain estimates for design point `dp` of the last apply. */
 MRIP_API mrip_status mrip_cv_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_stats_t *cv,
                           mrip_stats_t *plain);
 
-/* Milliseconds spent in the last apply on full replications, on prefix
- * replications and on network inference. */
-MRIP_API mrip_status mrip_cv_times(mrip_ctx ctx, float *full_ms, float *prefix_ms, float *infer_ms);
+/* Milliseconds the last apply spent in the simulation kernel (features and
+ * controls included) and in inference with the estimator's reductions. */
+MRIP_API mrip_status mrip_cv_times(mrip_ctx ctx, float *run_ms, float *infer_ms);
 
 /* ------------------------------------------------------------ utilities */
 

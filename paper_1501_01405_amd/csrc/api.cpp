@@ -51,6 +51,13 @@ uint32_t scalar_outputs(mrip_ctx c) {
   return m == MRIP_RW ? (c->rw.walker_sites ? 3 : 2) : m == MRIP_MM1 ? 3 : m == MRIP_PI ? 2 : 1;
 }
 
+// Values per replication of vector output o (M/M/1 with a feature prefix:
+// 3 = the 10 features, 4 = the 8 controls); 0 when o is no vector output.
+uint32_t vector_width(mrip_ctx c, uint32_t o) {
+  if (c->model != MRIP_MM1) return 0;
+  return o == 3 ? 10u : o == 4 ? 8u : 0u;
+}
+
 // dtype of scalar output o for the reduction kernel: 0 = int32, 1 = fp32
 int output_dtype(mrip_model m, uint32_t o) {
   return m == MRIP_MM1 ? 1 : (m == MRIP_PI && o == 1) ? 1 : 0;
@@ -394,11 +401,11 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   // library's own stream, so the next run's simulation need not wait for
   // it: runs alternate between two output sets.
   bool overlap = true;
-  for (uint32_t o = 0; o < 4; ++o) overlap = overlap && !ctx->bound[o].p;
+  for (uint32_t o = 0; o < mrip_ctx_s::MAX_OUT; ++o) overlap = overlap && !ctx->bound[o].p;
   const uint32_t set = overlap ? ctx->next_set : 0u;
   st = claim_set(ctx, set, s);
   if (st != MRIP_OK) return st;
-  void *outp[4] = {};
+  void *outp[mrip_ctx_s::MAX_OUT] = {};
   for (uint32_t o = 0; o < nout; ++o) {
     st = output_buffer(ctx, set, o, n_reps * 4, &outp[o]);
     if (st != MRIP_OK) return st;
@@ -464,7 +471,10 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     if (a.feature_prefix > 0) {
       st = output_buffer(ctx, set, 3, n_reps * 40, &outp[3]);
       if (st != MRIP_OK) return st;
+      st = output_buffer(ctx, set, 4, n_reps * 32, &outp[4]);
+      if (st != MRIP_OK) return st;
       a.features = (float *)outp[3];
+      a.controls = (float *)outp[4];
     }
     if (self_timed) {
       const KernelEvents ev = kernel_events(ctx);
@@ -556,8 +566,8 @@ mrip_status mrip_stats(mrip_ctx ctx, uint32_t output, double confidence, mrip_st
 mrip_status mrip_output_ptr(mrip_ctx ctx, uint32_t output, const void **ptr) {
   if (!ctx || !ptr) return MRIP_E_INVAL;
   if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
-  const bool feat = ctx->model == MRIP_MM1 && output == 3 && ctx->mm1.feature_prefix > 0;
-  if (output >= scalar_outputs(ctx) && !feat) return inval(ctx, "no such output");
+  const bool vec = vector_width(ctx, output) > 0 && ctx->mm1.feature_prefix > 0;
+  if (output >= scalar_outputs(ctx) && !vec) return inval(ctx, "no such output");
   *ptr = ctx->cur[output];
   return MRIP_OK;
 }
@@ -566,9 +576,9 @@ mrip_status mrip_outputs(mrip_ctx ctx, uint32_t output, void *dst, uint64_t byte
                          int dst_is_device) {
   if (!ctx || !dst) return MRIP_E_INVAL;
   if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
-  const bool feat = ctx->model == MRIP_MM1 && output == 3 && ctx->mm1.feature_prefix > 0;
-  if (output >= scalar_outputs(ctx) && !feat) return inval(ctx, "no such output");
-  const uint64_t need = ctx->last_n * (feat ? 40 : 4);
+  const bool vec = vector_width(ctx, output) > 0 && ctx->mm1.feature_prefix > 0;
+  if (output >= scalar_outputs(ctx) && !vec) return inval(ctx, "no such output");
+  const uint64_t need = ctx->last_n * 4 * (vec ? vector_width(ctx, output) : 1);
   if (bytes < need) return inval(ctx, "destination too small");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
   HIP_TRY(ctx, hipMemcpy(dst, ctx->cur[output], need,
@@ -677,7 +687,7 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
   if (st != MRIP_OK) return st;
   st = claim_set(ctx, 0, s);
   if (st != MRIP_OK) return st;
-  void *outp[4] = {};
+  void *outp[mrip_ctx_s::MAX_OUT] = {};
   for (uint32_t o = 0; o < 3; ++o) {
     st = output_buffer(ctx, 0, o, ctx->n_items * 4, &outp[o]);
     if (st != MRIP_OK) return st;
@@ -688,7 +698,10 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
   if (a.feature_prefix > 0) {
     st = output_buffer(ctx, 0, 3, ctx->n_items * 40, &outp[3]);
     if (st != MRIP_OK) return st;
+    st = output_buffer(ctx, 0, 4, ctx->n_items * 32, &outp[4]);
+    if (st != MRIP_OK) return st;
     a.features = (float *)outp[3];
+    a.controls = (float *)outp[4];
   }
   a.items.dp = ctx->it_dp.as<uint32_t>();
   a.items.rep = ctx->it_rep.as<uint32_t>();
@@ -780,8 +793,8 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
 
 mrip_status mrip_bind_output(mrip_ctx ctx, uint32_t output, void *ptr_dev, uint64_t bytes) {
   if (!ctx) return MRIP_E_INVAL;
-  const bool feat = ctx->model == MRIP_MM1 && output == 3;
-  if (output >= scalar_outputs(ctx) && !feat) return inval(ctx, "no such output");
+  const bool vec = vector_width(ctx, output) > 0;
+  if (output >= scalar_outputs(ctx) && !vec) return inval(ctx, "no such output");
   if (ptr_dev && (bytes == 0 || ((uintptr_t)ptr_dev & 3u)))
     return inval(ctx, "a bound output needs a non-empty, 4-byte aligned buffer");
   ctx->bound[output].p = ptr_dev;

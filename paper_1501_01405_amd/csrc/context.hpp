@@ -47,7 +47,7 @@ enum RunKind { RUN_NONE = 0, RUN_UNIFORM = 1, RUN_PLAN = 2 };
 // (longest first) and its grouping by design point (index + offsets).
 struct ItemBufs {
   DevBuf dp, rep, n, lambda, mu, order, index, offsets;
-  uint64_t count = 0, max_customers = 0;
+  uint64_t count = 0, max_customers = 0, n_long = 0;
   std::vector<uint32_t> dp_ids;          // distinct design points, ascending
   std::vector<uint64_t> group_offsets;   // host copy of offsets
   std::vector<uint32_t> index_host;      // host copy of index
@@ -57,9 +57,12 @@ struct ItemBufs {
 struct CvState {
   bool trained = false, applied = false;
   DevBuf theta, adam_m, adam_v, partial, loss_hist;
-  DevBuf queue, norm, colstats;
+  DevBuf queue, norm, colstats, unit4;
   std::vector<float> mean, std_;  // feature mean / std of the training set
-  std::vector<float> beta;        // MRIP_CV_BETA_BINS coefficients over [rho_lo, rho_hi]
+  // MRIP_CV_BETA_BINS rows of MRIP_CV_COEFS coefficients over [rho_lo, rho_hi]
+  // (the network's control h, then the four prefix controls), and on the device
+  std::vector<float> coef;
+  DevBuf coef_d;
   float rho_lo = 0.f, rho_hi = 1.f;
   float final_loss = 0.f, train_ms = 0.f;
   int bin_of(float rho) const {
@@ -67,15 +70,25 @@ struct CvState {
     const int k = (int)std::floor(u);
     return k < 0 ? 0 : k >= MRIP_CV_BETA_BINS ? MRIP_CV_BETA_BINS - 1 : k;
   }
-  // training and application buffers
-  ItemBufs train_items, full_items, pre_items;
-  DevBuf y_train, x_train, t_train, scratch_t, scratch_i, xn, yn;
-  DevBuf y_full, x_full, g_full, d_full, y_pre, x_pre, g_pre, red_d, red_g, red_y, red_f;
-  // per design point of the last apply: cv = (n, mean, var of the estimator,
-  // Welch dof, beta used), plain = (n, mean, var of Y)
+  // training: Y, features, controls and multipliers per item (item order),
+  // the standardised target, and the rows in training order (fit rows,
+  // then the held-out ones, grouped by design point): perm[j] is the item
+  // of row j; network outputs g_train in item order after training
+  ItemBufs train_items;
+  DevBuf y_train, x_train, c_train, z_train, t_train, zt_train, g_rows, g_train, group;
+  DevBuf xn, yn, zn, scratch_t, scratch_i;
+  std::vector<uint32_t> perm;
+  uint64_t n_fit = 0;
+  // application: per item Y, features, controls, network outputs, the
+  // network's control h, residual d = Y - coef . (h, z_pre) and the item's
+  // bin of rho
+  ItemBufs items;
+  DevBuf y, x, c, g, h, d, bin_item, red_y, red_d;
+  // per design point of the last apply: cv = (n, mean, var of the
+  // estimator, dof, coefficient of h used), plain = (n, mean, var of Y)
   std::vector<uint32_t> dp_ids;
   std::vector<double> cv, plain;
-  float full_ms = 0.f, prefix_ms = 0.f, infer_ms = 0.f;
+  float run_ms = 0.f, infer_ms = 0.f;
 };
 
 }  // namespace mrip
@@ -96,9 +109,13 @@ struct mrip_ctx_s {
   int rng = MRIP_RNG_PHILOX;
   mrip::DevBuf taus_tables;
 
+  // Outputs per run: up to three scalar outputs (idx 0..2) and, for M/M/1
+  // runs with a feature prefix, the features (idx 3, 10 per replication)
+  // and the controls (idx 4, 8 per replication).
+  static constexpr uint32_t MAX_OUT = 5;
   // Two sets of output buffers: a uniform run writes one while the
   // reduction of the run before it, on red_stream, still reads the other.
-  mrip::DevBuf out[2][4];
+  mrip::DevBuf out[2][MAX_OUT];
   uint32_t next_set = 0;                 // output set of the next uniform run
   bool set_pending[2] = {};              // a reduction may still read set i
   hipEvent_t ev_set_free[2] = {};        // recorded after that reduction
@@ -108,8 +125,8 @@ struct mrip_ctx_s {
   struct Bound {
     void *p = nullptr;
     uint64_t bytes = 0;
-  } bound[4];
-  void *cur[4] = {};
+  } bound[MAX_OUT];
+  void *cur[MAX_OUT] = {};
   mrip::DevBuf scratch;
   mrip::DevBuf walker_scratch;  // the walk's per-walker bitmaps
   mrip::DevBuf taus_walk;       // the walk's taus88 jump tables (its steps are fixed)

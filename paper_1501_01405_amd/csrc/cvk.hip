@@ -1,5 +1,6 @@
 // Small kernels around the control-variate network: per-column fp64 mean
-// and standard deviation, z-score normalisation, and D = Y - beta * G.
+// and standard deviation, z-score normalisation, and the controls'
+// per-sample multipliers with the training target.
 #include <hip/hip_runtime.h>
 
 #include "mlp.hpp"
@@ -62,20 +63,33 @@ __global__ void gather_normalize_kernel(const float *src, const uint32_t *perm, 
   dst[e] = (src[(uint64_t)perm[j] * cols + c] - mean[c]) * inv_std[c];
 }
 
-// t[i] = (y[i] - mean_g) / sd_g for the design point g = group[i], from the
-// (n, mean, var) triples of the groups; 0 where sd_g = 0.
-__global__ void center_kernel(const float *y, const uint32_t *group, const double *nmv,
-                              uint64_t n, float *t) {
+// Per replication i of N_i customers at service rate mu_i: the multipliers
+// z = (c0, c1, c2 / m, c3 / m, c4, c5, c6 / m, c7 / m) / N_i of its eight
+// controls c (after the prefix, then over it), with m = (float)(1 / mu_i)
+// the service scale (every z_k is a time per customer). With `group` set
+// (training): also t = (y - mean_g) / sd_g and zt = z_{0..3} / sd_g for the
+// replication's design point g (both 0 where sd_g = 0), the standardised
+// target and the multipliers of the network's four coefficients.
+__global__ void multipliers_kernel(const float *ctl, const uint64_t *customers, const float *mu,
+                                   uint64_t n, float *z, const float *y, const uint32_t *group,
+                                   const double *nmv, float *t, float *zt) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const double N = (double)customers[i];
+  const double m = (double)(float)(1.0 / (double)mu[i]);
+  const double sc[4] = {1.0 / N, 1.0 / N, (1.0 / m) / N, (1.0 / m) / N};
+  double zk[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    zk[k] = (double)ctl[8 * i + k] * sc[k & 3];
+    z[8 * i + k] = (float)zk[k];
+  }
+  if (!group) return;
   const uint32_t g = group[i];
   const double sd = sqrt(nmv[3 * g + 2]);
   t[i] = sd > 0.0 ? (float)(((double)y[i] - nmv[3 * g + 1]) / sd) : 0.0f;
-}
-
-__global__ void axpy_kernel(const float *y, const float *g, float beta, uint64_t n, float *d) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = y[i] - beta * g[i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) zt[4 * i + k] = sd > 0.0 ? (float)(zk[k] / sd) : 0.0f;
 }
 
 }  // namespace
@@ -105,19 +119,12 @@ hipError_t launch_gather_normalize(const float *src, const uint32_t *perm, uint6
   return hipGetLastError();
 }
 
-hipError_t launch_center(const float *y, const uint32_t *group, const double *nmv, uint64_t n,
-                         float *t, hipStream_t s) {
+hipError_t launch_multipliers(const float *ctl, const uint64_t *customers, const float *mu,
+                              uint64_t n, float *z, const float *y, const uint32_t *group,
+                              const double *nmv, float *t, float *zt, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(center_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, y, group,
-                     nmv, n, t);
-  return hipGetLastError();
-}
-
-hipError_t launch_axpy(const float *y, const float *g, float beta, uint64_t n, float *d,
-                       hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(axpy_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, y, g, beta,
-                     n, d);
+  hipLaunchKernelGGL(multipliers_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, ctl,
+                     customers, mu, n, z, y, group, nmv, t, zt);
   return hipGetLastError();
 }
 

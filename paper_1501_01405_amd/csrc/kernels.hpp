@@ -60,9 +60,22 @@ struct Mm1Args {
   uint32_t *queue_head;         // plan mode: device counter, zero at launch
   float *mean_w, *mean_t, *mean_i;
   float *features;              // n x 10 when feature_prefix > 0
+  // n x 8 when feature_prefix > 0: the martingale controls over customers
+  // n >= K, sum (S_n - es), sum (A_n - ea), sum T_{n-1} (S_n - es),
+  // sum T_{n-1} (A_n - ea), then the same four over n < K, with es, ea the
+  // variates' means in fp32. The launchers fill in ea, es (uniform mode)
+  // and log_grid_mean (plans derive each item's means from it).
+  float *controls;
+  float ea, es;
+  double log_grid_mean;
   int rng;                      // uniform mode only; plans use Philox
   const uint32_t *taus;
 };
+// Mean of -ln u over the 24-bit grid of u, {k 2^-24 : k = 1..2^24}, and
+// the fp32 mean of the exponential variate of `rate` as drawn, (float)(1 /
+// rate) times it: the controls' centring constants.
+double log_grid_mean();
+float variate_mean_f32(float rate);
 hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t reps_per_wave, uint32_t workgroup,
                            hipStream_t s);
 hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s);
@@ -127,9 +140,13 @@ hipError_t launch_reduce_f64(const void *x, int dtype, uint64_t n, const uint64_
 hipError_t launch_reduce_f64_multi(const ReduceSet &set, uint32_t n_outputs, uint64_t n,
                                    double *out, hipStream_t s);
 // Gathered variant: segment g reads x[index[offsets[g] .. offsets[g+1])].
+// The pair form reduces two fp32 arrays over the same segments in one launch.
 hipError_t launch_reduce_f64_gather(const void *x, int dtype, const uint32_t *index,
                                     const uint64_t *offsets, uint32_t n_segments, double *out,
                                     hipStream_t s);
+hipError_t launch_reduce_f64_gather2(const float *x0, const float *x1, const uint32_t *index,
+                                     const uint64_t *offsets, uint32_t n_segments, double *out0,
+                                     double *out1, hipStream_t s);
 
 // ------------------------------------------------------------ utilities
 // out[i] = output skip + i of the taus88 stream of (model, dp, rep), each

@@ -1,6 +1,8 @@
-// Control-variate network kernels: a 10-128-128-1 ReLU MLP with bfloat16
+// Control-variate network kernels: a 10-128-128-4 ReLU MLP with bfloat16
 // operands and fp32 accumulation on the gfx950 matrix cores
-// (v_mfma_f32_16x16x32_bf16), forward and backward, plus Adam.
+// (v_mfma_f32_16x16x32_bf16), forward and backward, plus Adam. Its four
+// outputs are the coefficients of four zero-mean controls; training fits
+// sum_k g_k(x) z_k to a target with per-sample multipliers z.
 //
 // Layout. A workgroup of 4 wavefronts takes 64 samples, 16 per wave. Every
 // layer is computed transposed, activations as [hidden][sample]:
@@ -12,7 +14,7 @@
 // 32j + 4g + (i&3) + 16(i>>2)), so activations never leave registers between
 // layers. Weight gradients contract over samples: dZ^T and the layer inputs
 // are staged in LDS as [unit][sample] and multiplied with samples as K.
-// The last layer (128 -> 1) is a VALU dot product.
+// The last layer (128 -> 4) is four VALU dot products.
 //
 // Every matrix product rounds both operands to bf16 (round to nearest even,
 // v_cvt_pk_bf16_f32); biases, ReLU masks and the loss stay fp32.
@@ -32,10 +34,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int DIN = MLP_DIN, H = MLP_H, TS = 64;  // samples per workgroup
 constexpr int SP = TS + 8;                       // padded row of the staging arrays
 
+constexpr int DOUT = MLP_DOUT;
+
 struct FwdLds {
   __bf16 w2[H][H + 8];   // W2[h2][h1]
   __bf16 w1[H][32 + 8];  // W1[h][f], f >= 10 zero
-  float b1[H], b2[H], w3[H];
+  float b1[H], b2[H], w3[DOUT][H];
 };
 
 struct BwdLds {
@@ -45,8 +49,8 @@ struct BwdLds {
   __bf16 dz2t[H][SP];    // dZ2^T[h2][s]
   __bf16 dz1t[H][SP];    // dZ1^T[h1][s]
   __bf16 xt[16][SP];     // X^T[f][s], f < 16
-  float red[3][4][H];    // per-wave sums of db1, db2, dW3
-  float red_s[2][4];     // per-wave sums of loss and db3
+  float red[2 + DOUT][4][H];  // per-wave sums of db1, db2, dW3[k]
+  float red_s[1 + DOUT][4];   // per-wave sums of loss and db3[k]
 };
 
 __device__ __forceinline__ __bf16 bf(float v) { return (__bf16)v; }
@@ -80,15 +84,19 @@ __device__ void stage_weights(const float *theta, FwdLds &L, BwdLds *B) {
   for (int e = tid; e < H; e += blockDim.x) {
     L.b1[e] = theta[MLP_OFF_B1 + e];
     L.b2[e] = theta[MLP_OFF_B2 + e];
-    L.w3[e] = bfr(theta[MLP_OFF_W3 + e]);
   }
+  for (int e = tid; e < DOUT * H; e += blockDim.x) L.w3[e / H][e % H] = bfr(theta[MLP_OFF_W3 + e]);
 }
+
+struct Out4 {
+  float v[DOUT];
+};
 
 // Forward pass of the wave's 16 samples. On return z1, z2 hold the
 // pre-activations of this lane's units (16t + 4g + i) for its sample, and
-// the return value is the prediction for the sample of column l%16.
-__device__ float forward_wave(const FwdLds &L, bf16x8 xb, float b3, float z1[8][4],
-                              float z2[8][4]) {
+// the return value is the four outputs for the sample of column l%16.
+__device__ Out4 forward_wave(const FwdLds &L, bf16x8 xb, const float *b3, float z1[8][4],
+                             float z2[8][4]) {
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
@@ -113,41 +121,85 @@ __device__ float forward_wave(const FwdLds &L, bf16x8 xb, float b3, float z1[8][
 #pragma unroll
     for (int i = 0; i < 4; ++i) z2[t][i] = acc[i] + L.b2[16 * t + 4 * g + i];
   }
-  float part = 0.0f;
+  Out4 o;
 #pragma unroll
-  for (int t = 0; t < 8; ++t)
+  for (int k = 0; k < DOUT; ++k) {
+    float part = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      part = fmaf(L.w3[16 * t + 4 * g + i], bfr(fmaxf(z2[t][i], 0.0f)), part);
-  part += __shfl_xor(part, 16, 64);
-  part += __shfl_xor(part, 32, 64);
-  return part + b3;
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        part = fmaf(L.w3[k][16 * t + 4 * g + i], bfr(fmaxf(z2[t][i], 0.0f)), part);
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    o.v[k] = part + b3[k];
+  }
+  return o;
 }
 
-__device__ __forceinline__ bf16x8 load_x(const float *x, int s, bool valid, int g) {
+__device__ __forceinline__ bf16x8 load_x(const float *x, uint64_t s, bool valid, int g) {
   bf16x8 xb;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int f = 8 * g + i;
-    xb[i] = bf((valid && f < DIN) ? x[(uint64_t)s * DIN + f] : 0.0f);
+    xb[i] = bf((valid && f < DIN) ? x[s * DIN + f] : 0.0f);
   }
   return xb;
 }
 
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *theta, const float *x,
-                                                          uint64_t n, float *y, float out_scale,
-                                                          float out_shift) {
+                                                          uint64_t n, float *y) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   FwdLds &L = *reinterpret_cast<FwdLds *>(smem);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const uint64_t s = (uint64_t)blockIdx.x * TS + 16 * w + c;
   const bool valid = s < n;
   stage_weights(theta, L, nullptr);
-  const bf16x8 xb = load_x(x, (int)s, valid, g);
+  const bf16x8 xb = load_x(x, s, valid, g);
   __syncthreads();
   float z1[8][4], z2[8][4];
-  const float yh = forward_wave(L, xb, theta[MLP_OFF_B3], z1, z2);
-  if (g == 0 && valid) y[s] = out_shift + out_scale * yh;
+  const Out4 yh = forward_wave(L, xb, theta + MLP_OFF_B3, z1, z2);
+  if (g == 0 && valid) *(float4 *)(y + 4 * s) = float4{yh.v[0], yh.v[1], yh.v[2], yh.v[3]};
+}
+
+// Inference of the control variate, fused: z-score the raw features, the
+// forward pass, then per sample (one lane each) the controls' multipliers,
+// the network's control h = sum_k g_k z_k and the residual
+// d = y - coef[bin] . (h, z_4..z_7), in fp64 (rounded once to fp32). The
+// z-scores round as the standalone normalisation does ((x - mean) * inv_std
+// in fp32, then bf16 for the product).
+__global__ __launch_bounds__(256) void cv_infer_kernel(const float *theta, const float *x,
+                                                       uint64_t n, CvInferArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  FwdLds &L = *reinterpret_cast<FwdLds *>(smem);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const uint64_t s = (uint64_t)blockIdx.x * TS + 16 * w + c;
+  const bool valid = s < n;
+  stage_weights(theta, L, nullptr);
+  bf16x8 xb;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int f = 8 * g + i;
+    xb[i] = bf((valid && f < DIN) ? (x[s * DIN + f] - a.mean[f]) * a.inv_std[f] : 0.0f);
+  }
+  __syncthreads();
+  float z1[8][4], z2[8][4];
+  const Out4 o = forward_wave(L, xb, theta + MLP_OFF_B3, z1, z2);
+  if (g != 0 || !valid) return;
+  if (a.g) *(float4 *)(a.g + 4 * s) = float4{o.v[0], o.v[1], o.v[2], o.v[3]};
+  const double N = (double)a.customers[s];
+  const double m = (double)(float)(1.0 / (double)a.mu[s]);
+  const double sc[4] = {1.0 / N, 1.0 / N, (1.0 / m) / N, (1.0 / m) / N};
+  const float *cl = a.ctl + 8 * s;
+  double h = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) h += (double)o.v[k] * (double)(float)((double)cl[k] * sc[k]);
+  const float *cf = a.coef + (uint64_t)a.bin[s] * CV_NCOEF;
+  double f = (double)cf[0] * h;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) f += (double)cf[1 + k] * (double)(float)((double)cl[4 + k] * sc[k]);
+  a.h[s] = (float)h;
+  a.d[s] = (float)((double)a.y[s] - f);
 }
 
 // Sum over the 16 lanes of a row (same g, every sample column).
@@ -157,11 +209,14 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
-// Gradient of mean((g(x) - y)^2) over n samples: one partial row per
-// workgroup (MLP_PSTRIDE floats: the 18049 gradients, then the loss sum).
+// Gradient of mean((sum_k g_k(x) z_k - y)^2) over n samples (z nullable:
+// z = e_0): one partial row per workgroup (MLP_PSTRIDE floats: the
+// MLP_NPARAMS gradients, then the loss sum). The output gradient
+// dy_k = 2 (pred - y) z_k / n is formed in fp32 and enters the products as
+// bf16.
 __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const float *x,
-                                                       const float *y, uint64_t n, float inv_n,
-                                                       float *partial) {
+                                                       const float *z, const float *y, uint64_t n,
+                                                       float inv_n, float *partial) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   BwdLds &B = *reinterpret_cast<BwdLds *>(smem);
   FwdLds &L = B.f;
@@ -170,7 +225,7 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
   const uint64_t s = (uint64_t)blockIdx.x * TS + sl;
   const bool valid = s < n;
   stage_weights(theta, L, &B);
-  const bf16x8 xb = load_x(x, (int)s, valid, g);
+  const bf16x8 xb = load_x(x, s, valid, g);
   if (g < 2) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) B.xt[8 * g + i][sl] = xb[i];
@@ -178,21 +233,45 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
   __syncthreads();
 
   float z1[8][4], z2[8][4];
-  const float yh = forward_wave(L, xb, theta[MLP_OFF_B3], z1, z2);
-  const float err = valid ? yh - y[s] : 0.0f;
-  const float dy = 2.0f * err * inv_n;
-  const float dyb = bfr(dy);
+  const Out4 yh = forward_wave(L, xb, theta + MLP_OFF_B3, z1, z2);
+  float zz[DOUT] = {1.0f, 0.0f, 0.0f, 0.0f};
+  if (z && valid) {
+    const float4 zv = *(const float4 *)(z + 4 * s);
+    zz[0] = zv.x;
+    zz[1] = zv.y;
+    zz[2] = zv.z;
+    zz[3] = zv.w;
+  }
+  float pred = 0.0f;
+#pragma unroll
+  for (int k = 0; k < DOUT; ++k) pred = fmaf(yh.v[k], zz[k], pred);
+  const float err = valid ? pred - y[s] : 0.0f;
+  const float e2 = 2.0f * err * inv_n;
+  float dy[DOUT], dyb[DOUT];
+#pragma unroll
+  for (int k = 0; k < DOUT; ++k) {
+    dy[k] = e2 * zz[k];
+    dyb[k] = bfr(dy[k]);
+  }
 
-  // last layer and the ReLU of the second
+  // last layer: dW3[k] partial sums over the wave's samples, and the ReLU of
+  // the second layer
   float dz2[8][4];
-  float p3[8][4];
 #pragma unroll
   for (int t = 0; t < 8; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int h = 16 * t + 4 * g + i;
-      p3[t][i] = dyb * bfr(fmaxf(z2[t][i], 0.0f));
-      dz2[t][i] = z2[t][i] > 0.0f ? L.w3[h] * dyb : 0.0f;
+      float d = 0.0f;
+#pragma unroll
+      for (int k = 0; k < DOUT; ++k) d = fmaf(L.w3[k][h], dyb[k], d);
+      dz2[t][i] = z2[t][i] > 0.0f ? d : 0.0f;
+      const float h2 = bfr(fmaxf(z2[t][i], 0.0f));
+#pragma unroll
+      for (int k = 0; k < DOUT; ++k) {
+        const float v = row16_sum(dyb[k] * h2);
+        if (c == 0) B.red[2 + k][w][h] = v;
+      }
     }
   // dH1^T = W2^T . dZ2^T, then the ReLU of the first layer
   bf16x8 db[4];
@@ -223,7 +302,7 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
       B.dz2t[h][sl] = bf(dz2[t][i]);
       B.dz1t[h][sl] = bf(dz1[t][i]);
     }
-  // per-wave sums over samples of db1, db2, dW3
+  // per-wave sums over samples of db1, db2, db3 and the loss
 #pragma unroll
   for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -231,21 +310,18 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
       const int h = 16 * t + 4 * g + i;
       const float v1 = row16_sum(dz1[t][i]);
       const float v2 = row16_sum(dz2[t][i]);
-      const float v3 = row16_sum(p3[t][i]);
       if (c == 0) {
         B.red[0][w][h] = v1;
         B.red[1][w][h] = v2;
-        B.red[2][w][h] = v3;
       }
     }
   {
-    float l2 = (g == 0) ? err * err : 0.0f;
-    float d3 = (g == 0) ? dy : 0.0f;
-    l2 = row16_sum(l2);
-    d3 = row16_sum(d3);
-    if (lane == 0) {
-      B.red_s[0][w] = l2;
-      B.red_s[1][w] = d3;
+    const float l2 = row16_sum(g == 0 ? err * err : 0.0f);
+    if (lane == 0) B.red_s[0][w] = l2;
+#pragma unroll
+    for (int k = 0; k < DOUT; ++k) {
+      const float d3 = row16_sum(g == 0 ? dy[k] : 0.0f);
+      if (lane == 0) B.red_s[1 + k][w] = d3;
     }
   }
   __syncthreads();
@@ -285,15 +361,16 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
       for (int i = 0; i < 4; ++i) out[MLP_OFF_W1 + (16 * t1 + 4 * g + i) * DIN + c] = acc[i];
     }
   }
-  if (tid < H) {
-    const int h = tid;
-    out[MLP_OFF_B1 + h] = ((B.red[0][0][h] + B.red[0][1][h]) + B.red[0][2][h]) + B.red[0][3][h];
-    out[MLP_OFF_B2 + h] = ((B.red[1][0][h] + B.red[1][1][h]) + B.red[1][2][h]) + B.red[1][3][h];
-    out[MLP_OFF_W3 + h] = ((B.red[2][0][h] + B.red[2][1][h]) + B.red[2][2][h]) + B.red[2][3][h];
+  // fixed-order sums of the four waves' rows: db1, db2, then dW3[k]
+  for (int e = tid; e < (2 + DOUT) * H; e += blockDim.x) {
+    const int r = e / H, h = e % H;
+    const float v = ((B.red[r][0][h] + B.red[r][1][h]) + B.red[r][2][h]) + B.red[r][3][h];
+    const int off = r == 0 ? MLP_OFF_B1 + h : r == 1 ? MLP_OFF_B2 + h : MLP_OFF_W3 + (r - 2) * H + h;
+    out[off] = v;
   }
-  if (tid == 0) {
-    out[MLP_OFF_B3] = ((B.red_s[1][0] + B.red_s[1][1]) + B.red_s[1][2]) + B.red_s[1][3];
-    out[MLP_NPARAMS] = ((B.red_s[0][0] + B.red_s[0][1]) + B.red_s[0][2]) + B.red_s[0][3];
+  if (tid <= DOUT) {
+    const float v = ((B.red_s[tid][0] + B.red_s[tid][1]) + B.red_s[tid][2]) + B.red_s[tid][3];
+    out[tid == 0 ? MLP_NPARAMS : MLP_OFF_B3 + tid - 1] = v;
   }
 }
 
@@ -346,25 +423,36 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 size_t mlp_partial_rows(uint64_t n) { return (size_t)((n + TS - 1) / TS); }
 
 hipError_t launch_mlp_forward(const float *theta, const float *x, uint64_t n, float *y,
-                              float out_scale, float out_shift, hipStream_t s) {
+                              hipStream_t s) {
   if (n == 0) return hipSuccess;
   const size_t lds = sizeof(FwdLds);
   hipError_t e = allow_lds(mlp_forward_kernel, lds);
   if (e != hipSuccess) return e;
   const uint64_t blocks = (n + TS - 1) / TS;
   hipLaunchKernelGGL(mlp_forward_kernel, dim3((uint32_t)blocks), dim3(256), lds, s, theta, x, n,
-                     y, out_scale, out_shift);
+                     y);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const float *theta, const float *x, const float *y, uint64_t n,
-                           float *partial, hipStream_t s) {
+hipError_t launch_cv_infer(const float *theta, const float *x, uint64_t n, const CvInferArgs &a,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t lds = sizeof(FwdLds);
+  hipError_t e = allow_lds(cv_infer_kernel, lds);
+  if (e != hipSuccess) return e;
+  const uint64_t blocks = (n + TS - 1) / TS;
+  hipLaunchKernelGGL(cv_infer_kernel, dim3((uint32_t)blocks), dim3(256), lds, s, theta, x, n, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float *theta, const float *x, const float *z, const float *y,
+                           uint64_t n, float *partial, hipStream_t s) {
   const size_t lds = sizeof(BwdLds);
   hipError_t e = allow_lds(mlp_grad_kernel, lds);
   if (e != hipSuccess) return e;
   const uint64_t blocks = (n + TS - 1) / TS;
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3((uint32_t)blocks), dim3(256), lds, s, theta, x, y, n,
-                     1.0f / (float)n, partial);
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3((uint32_t)blocks), dim3(256), lds, s, theta, x, z, y,
+                     n, 1.0f / (float)n, partial);
   return hipGetLastError();
 }
 

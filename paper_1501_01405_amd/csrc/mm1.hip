@@ -28,6 +28,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -44,16 +45,23 @@ struct Rep {
   uint64_t n;        // customers (0 = empty slot)
   float ca, cs;      // -(1/lambda) ln 2, -(1/mu) ln 2
   float lambda, mu;
+  float ea, es;      // means of the A and S variates as drawn (control centring)
   uint64_t out;      // output index
 };
 
+// Sums of W, T and I, and of the four martingale controls over customers
+// n >= K (FT forms only): S_n - E S, A_n - E A, and both weighted by T_{n-1}.
 struct Sums {
   Kahan w, t, i;
+  Kahan c[4];
 };
 
+// Prefix features, and the four controls over the prefix customers (n < K:
+// a lane holds about K / 64 of them, plain fp32 sums suffice).
 struct Feat {
   float sa = 0.f, ss = 0.f, sw = 0.f, st = 0.f, si = 0.f, wmax = 0.f, tlast = 0.f;
   int zeros = 0;
+  float pc[4] = {0.f, 0.f, 0.f, 0.f};
 };
 
 __device__ __forceinline__ float pick4(int q, float v0, float v1, float v2, float v3) {
@@ -170,14 +178,44 @@ __device__ __forceinline__ float carry_through(const ChunkScan &cs, float carry,
 }
 
 // The lane's P customers in order, from the system time T before the first;
-// sums of W, T and I (TAIL: only customers < n) and the prefix features.
-template <int P, bool FEAT, bool TAIL>
+// sums of W, T and I (TAIL: only customers < n) and, with FT, the prefix
+// features and prefix controls (customers < K, FEAT chunks only) and the
+// partial sums of the four controls after the prefix (customers >= K).
+// A_n and S_n are drawn independently of T_{n-1}, the system time the lane
+// holds when it reaches customer n, so every control term has mean zero
+// given the past.
+template <int P, bool FEAT, bool TAIL, bool FT>
 __device__ __forceinline__ void apply_lane(float T, const Draw<P> &dr, uint64_t n0, uint64_t n,
-                                           uint64_t K, float &sw, float &st, float &si,
-                                           Feat &ft) {
+                                           uint64_t K, float ea, float es, float &sw, float &st,
+                                           float &si, Feat &ft, float (&cl)[4]) {
   sw = st = si = 0.0f;
+  if (FT) cl[0] = cl[1] = cl[2] = cl[3] = 0.0f;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
+    if (FT) {
+      bool v = true;
+      if (FEAT) v = n0 + j >= K;
+      if (TAIL) v = v && n0 + j < n;
+      const float da = dr.A[j] - ea, ds = dr.S[j] - es;
+      if (FEAT) {  // customers < K <= n: the prefix four
+        const bool p = n0 + j < K;
+        ft.pc[0] += p ? ds : 0.0f;
+        ft.pc[1] += p ? da : 0.0f;
+        ft.pc[2] = p ? __builtin_fmaf(T, ds, ft.pc[2]) : ft.pc[2];
+        ft.pc[3] = p ? __builtin_fmaf(T, da, ft.pc[3]) : ft.pc[3];
+      }
+      if (FEAT || TAIL) {
+        cl[0] += v ? ds : 0.0f;
+        cl[1] += v ? da : 0.0f;
+        cl[2] = v ? __builtin_fmaf(T, ds, cl[2]) : cl[2];
+        cl[3] = v ? __builtin_fmaf(T, da, cl[3]) : cl[3];
+      } else {
+        cl[0] += ds;
+        cl[1] += da;
+        cl[2] = __builtin_fmaf(T, ds, cl[2]);
+        cl[3] = __builtin_fmaf(T, da, cl[3]);
+      }
+    }
     // I = max(0, A - T) = W - (T - A) exactly: A - T = -(T - A) in IEEE
     // arithmetic, and W is either 0 or T - A
     const float dlt = T - dr.A[j];
@@ -219,25 +257,31 @@ __device__ __forceinline__ uint64_t lane_first_customer(uint64_t base) {
 // One chunk: every segment of the replication takes 16 P customers, whose
 // variates are `dr`. FEAT accumulates the prefix features; TAIL masks
 // customers >= n (only chunks that reach past some replication's end need
-// it).
-template <int RPW, int P, bool FEAT, bool TAIL>
+// it); FT adds the controls.
+template <int RPW, int P, bool FEAT, bool TAIL, bool FT>
 __device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, const Rep &d,
                                            uint64_t K, float &carry, Sums &acc, Feat &ft) {
   const ChunkScan cs = compose_scan<P>(dr);
   float tin;
   carry = carry_through<RPW>(cs, carry, tin);
-  float sw, st, si;
-  apply_lane<P, FEAT, TAIL>(fmaxf(cs.ea, tin + cs.eb), dr, lane_first_customer<RPW, P>(base),
-                            d.n, K, sw, st, si, ft);
+  float sw, st, si, cl[4];
+  apply_lane<P, FEAT, TAIL, FT>(fmaxf(cs.ea, tin + cs.eb), dr, lane_first_customer<RPW, P>(base),
+                                d.n, K, d.ea, d.es, sw, st, si, ft, cl);
   acc.w.add(sw);
   acc.t.add(st);
   acc.i.add(si);
+  if (FT) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc.c[k].add(cl[k]);
+  }
 }
 
 // Fix-up chunk of a split replication: the same customers from two carries
 // (the true one and the speculative one the part started from); adds the
-// difference of their sums.
-template <int P, bool TAIL>
+// difference of their sums. Fix-up chunks lie after the feature prefix, so
+// with FT every customer counts for the controls; the two unweighted ones
+// do not depend on the carry.
+template <int P, bool TAIL, bool FT>
 __device__ __forceinline__ void fixup_chunk(uint64_t base, const Draw<P> &dr, const Rep &d,
                                             float &c_true, float &c_spec, Sums &acc) {
   const ChunkScan cs = compose_scan<P>(dr);
@@ -246,23 +290,32 @@ __device__ __forceinline__ void fixup_chunk(uint64_t base, const Draw<P> &dr, co
   c_spec = carry_through<1>(cs, c_spec, tin_s);
   const uint64_t n0 = lane_first_customer<1, P>(base);
   Feat none;
-  float wt, tt, it, ws, ts, is;
-  apply_lane<P, false, TAIL>(fmaxf(cs.ea, tin_t + cs.eb), dr, n0, d.n, 0, wt, tt, it, none);
-  apply_lane<P, false, TAIL>(fmaxf(cs.ea, tin_s + cs.eb), dr, n0, d.n, 0, ws, ts, is, none);
+  float wt, tt, it, ws, ts, is, clt[4], cls[4];
+  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_t + cs.eb), dr, n0, d.n, 0, d.ea, d.es, wt, tt,
+                                 it, none, clt);
+  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_s + cs.eb), dr, n0, d.n, 0, d.ea, d.es, ws, ts,
+                                 is, none, cls);
   acc.w.add(wt - ws);
   acc.t.add(tt - ts);
   acc.i.add(it - is);
+  if (FT) {
+    acc.c[2].add(clt[2] - cls[2]);
+    acc.c[3].add(clt[3] - cls[3]);
+  }
 }
 
 // Runs the replications of one wavefront (RPW of them, one per lane group)
-// to completion and writes their outputs.
-template <int RPW, class Src>
+// to completion and writes their outputs. FT: K > 0, with the prefix
+// features and the controls; the form without them (K = 0) carries none of
+// their registers.
+template <int RPW, bool FT, class Src>
 __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a) {
   constexpr int P = MM1_P;
   constexpr int S = 4 / RPW;
   constexpr int WIDTH = 16 * S;  // lanes per replication
   constexpr uint64_t CHUNK = 16u * P * S;
   const int lane = threadIdx.x & 63;
+  if (!FT) K = 0;
 
   // wave-uniform trip counts: chunks of the longest replication, and chunks
   // that are full for every non-empty replication of the wave
@@ -283,9 +336,10 @@ __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a)
 #define MRIP_CHUNK(F, TL)                                                            \
   {                                                                                  \
     const Draw<P> cur = src.template next<RPW, P>((uint64_t)c * CHUNK, d);          \
-    wave_chunk<RPW, P, F, TL>(c * CHUNK, cur, d, K, carry, acc, ft);                 \
+    wave_chunk<RPW, P, F, TL, FT>(c * CHUNK, cur, d, K, carry, acc, ft);             \
   }
-  for (; c < fchunks; ++c) MRIP_CHUNK(true, true)
+  if (FT)
+    for (; c < fchunks; ++c) MRIP_CHUNK(FT, true)
   for (; c < full; ++c) MRIP_CHUNK(false, false)
   for (; c < chunks; ++c) MRIP_CHUNK(false, true)
 #undef MRIP_CHUNK
@@ -293,8 +347,8 @@ __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a)
   const float sw = group_sum_compensated(acc.w.value(), WIDTH);
   const float st = group_sum_compensated(acc.t.value(), WIDTH);
   const float si = group_sum_compensated(acc.i.value(), WIDTH);
-  float f[10];
-  if (K > 0) {
+  float f[10], cl[8];
+  if (FT) {
     const float kf = (float)K;
     f[0] = d.lambda / d.mu;
     f[1] = d.mu;
@@ -306,21 +360,44 @@ __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a)
     f[7] = group_max(ft.wmax, WIDTH);
     f[8] = group_sum_compensated(ft.si, WIDTH) / kf;
     f[9] = group_sum_compensated(ft.tlast, WIDTH);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cl[k] = group_sum_compensated(acc.c[k].value(), WIDTH);
+      cl[4 + k] = group_sum_compensated(ft.pc[k], WIDTH);
+    }
   }
   if ((lane % WIDTH) == 0 && d.n > 0) {
     const float nf = (float)d.n;
     a.mean_w[d.out] = sw / nf;
     a.mean_t[d.out] = st / nf;
     a.mean_i[d.out] = si / nf;
-    if (K > 0) {
+    if (FT) {
 #pragma unroll
       for (int j = 0; j < 10; ++j) a.features[d.out * 10 + j] = f[j];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a.controls[d.out * 8 + k] = cl[k];
     }
   }
 }
 
+// The wavefront's replications in the form their prefix asks for (K is a
+// kernel argument: the branch is uniform over the grid).
+template <int RPW, class Src>
+__device__ __forceinline__ void wave_group_any(const Rep &d, Src &src, uint64_t K,
+                                               const Mm1Args &a) {
+  if (K > 0) wave_group<RPW, true>(d, src, K, a);
+  else wave_group<RPW, false>(d, src, 0, a);
+}
+
 __device__ __forceinline__ float neg_mean_ln2(float rate) {
   return (float)(-(1.0 / (double)rate) * 0.69314718055994530942);
+}
+
+// Mean of the exponential variate of `rate` as defined (fp32 scale
+// (float)(1 / rate) times the mean of -ln u over the 24-bit grid of u), in
+// fp32: the centring constant of the controls.
+__device__ __forceinline__ float variate_mean(float rate, double log_grid_mean) {
+  return (float)((double)(float)(1.0 / (double)rate) * log_grid_mean);
 }
 
 __device__ __forceinline__ Rep uniform_rep(const Mm1Args &a, uint64_t r, float ca, float cs) {
@@ -332,6 +409,8 @@ __device__ __forceinline__ Rep uniform_rep(const Mm1Args &a, uint64_t r, float c
   d.cs = cs;
   d.lambda = a.lambda;
   d.mu = a.mu;
+  d.ea = a.ea;
+  d.es = a.es;
   d.out = r;
   return d;
 }
@@ -354,6 +433,11 @@ __device__ __forceinline__ Rep item_rep(const Mm1Args &a, uint64_t slot, uint64_
   }
   d.ca = neg_mean_ln2(d.lambda);
   d.cs = neg_mean_ln2(d.mu);
+  d.ea = d.es = 0.0f;
+  if (a.feature_prefix > 0) {
+    d.ea = variate_mean(d.lambda, a.log_grid_mean);
+    d.es = variate_mean(d.mu, a.log_grid_mean);
+  }
   return d;
 }
 
@@ -368,7 +452,7 @@ __global__ void mm1_wave_kernel(Mm1Args a, float ca, float cs) {
   if (wave * RPW >= a.n_reps) return;  // whole wave idle (wave-uniform)
   const Rep d = uniform_rep(a, r, ca, cs);
   PhiloxSource src{k0, k1};
-  wave_group<RPW>(d, src, a.feature_prefix, a);
+  wave_group_any<RPW>(d, src, a.feature_prefix, a);
 }
 
 // taus88 streams, WAVE mapping. The LPR lanes of a replication (16 or 32 of
@@ -384,7 +468,7 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
   constexpr int G = LPR < 64 ? LPR : 64;  // lanes of one replication inside a wavefront
   constexpr int RPB = 256 / LPR;          // replications per workgroup
   __shared__ float sh_a[4], sh_b[4];      // wavefront totals of the scan
-  __shared__ float sh_f[4][11];           // per-wavefront partial sums
+  __shared__ float sh_f[4][19];           // per-wavefront partial sums
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j = tid % LPR;                // lane within the replication
   const int g = lane % G;                 // lane within its group of one wavefront
@@ -438,9 +522,14 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
   Feat ft;
   uint64_t n = n0;
   const uint64_t nf = min(n1, max(n0, K));  // customers of the feature prefix
-  for (; n < nf; ++n) {
+  for (; n < nf; ++n) {  // the prefix: features and the prefix controls
     const float A = exp_variate(taus_next(t), ca);
     const float S = exp_variate(taus_next(t), cs);
+    const float ds = S - a.es, da = A - a.ea;
+    ft.pc[0] += ds;
+    ft.pc[1] += da;
+    ft.pc[2] = __builtin_fmaf(T, ds, ft.pc[2]);
+    ft.pc[3] = __builtin_fmaf(T, da, ft.pc[3]);
     const float dlt = T - A;
     const float W = fmaxf(0.0f, dlt);
     const float I = W - dlt;
@@ -457,13 +546,24 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
     ft.wmax = fmaxf(ft.wmax, W);
     if (n + 1 == K) ft.tlast = T;
   }
+  // after the prefix (every customer from here on has n >= K): with K > 0,
+  // also the four controls, weighted by T_{n-1} where they are
+  Kahan kc[4];
+  const bool ctl = K > 0;
   while (n < n1) {
     // plain fp32 sums over up to 8 customers, then one compensated add
     const uint64_t ne = min(n1, n + 8);
-    float sw = 0.0f, st = 0.0f, si = 0.0f;
+    float sw = 0.0f, st = 0.0f, si = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
     for (; n < ne; ++n) {
       const float A = exp_variate(taus_next(t), ca);
       const float S = exp_variate(taus_next(t), cs);
+      if (ctl) {
+        const float ds = S - a.es, da = A - a.ea;
+        c0 += ds;
+        c1 += da;
+        c2 = __builtin_fmaf(T, ds, c2);
+        c3 = __builtin_fmaf(T, da, c3);
+      }
       const float dlt = T - A;
       const float W = fmaxf(0.0f, dlt);
       const float I = W - dlt;
@@ -475,11 +575,18 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
     kw.add(sw);
     kt.add(st);
     ki.add(si);
+    if (ctl) {
+      kc[0].add(c0);
+      kc[1].add(c1);
+      kc[2].add(c2);
+      kc[3].add(c3);
+    }
   }
 
   // the replication's sums: lanes of the wavefront, then its wavefronts in
-  // order. v: W, T, I, then the features' A, S, W, T, zeros, max W, T_{K-1}, I
-  float v[11];
+  // order. v: W, T, I, then the features' A, S, W, T, zeros, max W, T_{K-1}, I,
+  // then the four controls after the prefix and the four over it
+  float v[19];
   v[0] = group_sum_compensated(kw.value(), G);
   v[1] = group_sum_compensated(kt.value(), G);
   v[2] = group_sum_compensated(ki.value(), G);
@@ -491,15 +598,20 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
   v[8] = group_max(ft.wmax, G);
   v[9] = group_sum_compensated(ft.tlast, G);
   v[10] = group_sum_compensated(ft.si, G);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[11 + k] = group_sum_compensated(kc[k].value(), G);
+    v[15 + k] = group_sum_compensated(ft.pc[k], G);
+  }
   if (LPR > 64) {
     if (lane == 0) {
 #pragma unroll
-      for (int k = 0; k < 11; ++k) sh_f[wave][k] = v[k];
+      for (int k = 0; k < 19; ++k) sh_f[wave][k] = v[k];
     }
     __syncthreads();
     if (j == 0) {  // lane 0 of the replication's first wavefront
 #pragma unroll
-      for (int k = 0; k < 11; ++k) {
+      for (int k = 0; k < 19; ++k) {
         float hi = sh_f[wave][k], lo = 0.0f;
         for (int w = wave + 1; w < wave + LPR / 64; ++w) {
           if (k == 8) {
@@ -533,6 +645,8 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
       f[7] = v[8];
       f[8] = v[10] / kf;
       f[9] = v[9];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a.controls[r * 8 + k] = v[11 + k];
     }
   }
 }
@@ -553,7 +667,7 @@ __global__ void mm1_plan_kernel(Mm1Args a, uint64_t n_items) {
     unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)unit, 0, 64));
     if (unit >= n_units) break;
     PhiloxSource src{k0, k1};
-    wave_group<RPW>(item_rep(a, (uint64_t)unit * RPW + q, n_items), src, a.feature_prefix, a);
+    wave_group_any<RPW>(item_rep(a, (uint64_t)unit * RPW + q, n_items), src, a.feature_prefix, a);
   }
 }
 
@@ -581,7 +695,7 @@ constexpr int split_slots() {
 template <int X>
 struct SplitShared {
   float spec[split_slots<X>()][X], fin[split_slots<X>()][X];
-  float sum[split_slots<X>()][X][3];
+  float sum[split_slots<X>()][X][7];  // W, T, I, then the four controls
 };
 
 // Part h of replication d (slot `slot` of the workgroup); every thread of
@@ -599,9 +713,12 @@ struct SplitShared {
 // from that end.
 //
 // FT = false is the form for runs without prefix features (K = 0): the
-// feature chunks and their registers are compiled out (74 VGPRs instead of
-// 105 for the uniform kernel), which the uniform kernel takes when K = 0.
-template <int X, bool FT = true>
+// feature chunks, the controls and their registers are compiled out (74
+// VGPRs instead of 105 for the uniform kernel), which the kernels take when
+// K = 0. With FT every part adds the controls of its customers (all after
+// the prefix except in part 0's feature chunks); a correction adds the
+// difference of the two T-weighted controls between its two starts.
+template <int X, bool FT>
 __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, uint32_t k1,
                                   uint64_t K, const Mm1Args &a, SplitShared<X> &sh) {
   if (!FT) K = 0;
@@ -623,7 +740,7 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
 #define MRIP_CHUNK(F, TL)                                                          \
   {                                                                                \
     const Draw<P> dr = draw_chunk<1, P>((uint64_t)c * CHUNK, d, k0, k1);          \
-    wave_chunk<1, P, F, TL>((uint64_t)c * CHUNK, dr, d, K, carry, acc, ft);        \
+    wave_chunk<1, P, F, TL, FT>((uint64_t)c * CHUNK, dr, d, K, carry, acc, ft);    \
   }
   if (FT)
     for (; c < min(ce, fchunks); ++c) MRIP_CHUNK(true, true)
@@ -641,8 +758,8 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
     bool coupled = false;
     for (uint32_t cc = cb; cc < ce && !coupled; ++cc) {
       const Draw<P> dr = draw_chunk<1, P>((uint64_t)cc * CHUNK, d, k0, k1);
-      if (cc < full) fixup_chunk<P, false>((uint64_t)cc * CHUNK, dr, d, ct, cs, fix);
-      else fixup_chunk<P, true>((uint64_t)cc * CHUNK, dr, d, ct, cs, fix);
+      if (cc < full) fixup_chunk<P, false, FT>((uint64_t)cc * CHUNK, dr, d, ct, cs, fix);
+      else fixup_chunk<P, true, FT>((uint64_t)cc * CHUNK, dr, d, ct, cs, fix);
       coupled = __builtin_amdgcn_readfirstlane((int)(__float_as_uint(ct) == __float_as_uint(cs))) != 0;
     }
     return coupled ? carry : ct;
@@ -667,13 +784,25 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
   acc.w.add(fix.w.value());
   acc.t.add(fix.t.value());
   acc.i.add(fix.i.value());
+  if (FT) {
+    acc.c[2].add(fix.c[2].value());
+    acc.c[3].add(fix.c[3].value());
+  }
 
   // phase 3: part sums, then the replication's means in part order
-  const float sw = group_sum_compensated(acc.w.value(), 64);
-  const float st = group_sum_compensated(acc.t.value(), 64);
-  const float si = group_sum_compensated(acc.i.value(), 64);
-  float f[10];
+  constexpr int NS = FT ? 7 : 3;
+  float part[NS];
+  part[0] = group_sum_compensated(acc.w.value(), 64);
+  part[1] = group_sum_compensated(acc.t.value(), 64);
+  part[2] = group_sum_compensated(acc.i.value(), 64);
+  if (FT) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) part[3 + k] = group_sum_compensated(acc.c[k].value(), 64);
+  }
+  float f[10], pcs[4];
   if (FT && h == 0 && K > 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pcs[k] = group_sum_compensated(ft.pc[k], 64);
     const float kf = (float)K;
     f[0] = d.lambda / d.mu;
     f[1] = d.mu;
@@ -687,15 +816,14 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
     f[9] = group_sum_compensated(ft.tlast, 64);
   }
   if (lane == 0) {
-    sh.sum[slot][h][0] = sw;
-    sh.sum[slot][h][1] = st;
-    sh.sum[slot][h][2] = si;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) sh.sum[slot][h][k] = part[k];
   }
   __syncthreads();
   if (h == 0 && lane == 0 && d.n > 0) {
-    float tot[3];
+    float tot[NS];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < NS; ++k) {
       float hi = sh.sum[slot][0][k], lo = 0.0f;
 #pragma unroll
       for (int j = 1; j < X; ++j) {
@@ -713,6 +841,11 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
     if (FT && K > 0) {
 #pragma unroll
       for (int j = 0; j < 10; ++j) a.features[d.out * 10 + j] = f[j];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        a.controls[d.out * 8 + k] = tot[3 + k];
+        a.controls[d.out * 8 + 4 + k] = pcs[k];
+      }
     }
   }
 }
@@ -756,7 +889,8 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a
     if (first >= n_long) break;
     const uint64_t idx = first + slot;
     const Rep d = item_rep(a, idx, idx < n_long ? n_long : 0);
-    split_replication<X>(d, slot, h, k0, k1, a.feature_prefix, a, sh);
+    if (a.feature_prefix > 0) split_replication<X, true>(d, slot, h, k0, k1, a.feature_prefix, a, sh);
+    else split_replication<X, false>(d, slot, h, k0, k1, 0, a, sh);
   }
   __builtin_amdgcn_s_setprio(0);
   const int q = (lane >> 4) / S;
@@ -769,7 +903,8 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a
     if (unit >= n_units) break;
     const uint64_t j = (uint64_t)unit * RPW + q;
     PhiloxSource src{k0, k1};
-    wave_group<RPW>(item_rep(a, n_long + j, j < n_short ? n_items : 0), src, a.feature_prefix, a);
+    wave_group_any<RPW>(item_rep(a, n_long + j, j < n_short ? n_items : 0), src, a.feature_prefix,
+                        a);
   }
 }
 
@@ -782,7 +917,7 @@ __device__ void simt_replication(const Rep &d, uint64_t K, uint32_t k0, uint32_t
                                  const Mm1Args &a) {
   const uint64_t N = d.n;
   float tprev = 0.0f;
-  Kahan sw, st, si;
+  Kahan sw, st, si, ctl[8];
   Feat ft;
   Taus ts;
   if (RNG == RNG_TAUS88) ts = taus_seed(TAG_MM1, d.dp, d.rep, k0, k1);
@@ -802,6 +937,14 @@ __device__ void simt_replication(const Rep &d, uint64_t K, uint32_t k0, uint32_t
       if (n >= N) break;
       const float A = exp_variate(h ? b.z : b.x, d.ca);
       const float Sv = exp_variate(h ? b.w : b.y, d.cs);
+      if (K > 0) {  // the controls (after the prefix, or over it), weighted by T_{n-1}
+        const float ds = Sv - d.es, da = A - d.ea;
+        Kahan *c = ctl + (n >= K ? 0 : 4);
+        c[0].add(ds);
+        c[1].add(da);
+        c[2].add(tprev * ds);
+        c[3].add(tprev * da);
+      }
       const float W = fmaxf(0.0f, tprev - A);
       const float I = fmaxf(0.0f, A - tprev);
       const float T = W + Sv;
@@ -838,6 +981,8 @@ __device__ void simt_replication(const Rep &d, uint64_t K, uint32_t k0, uint32_t
     f[7] = ft.wmax;
     f[8] = ft.si / kf;
     f[9] = ft.tlast;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a.controls[d.out * 8 + k] = ctl[k].value();
   }
 }
 
@@ -875,7 +1020,29 @@ float host_neg_mean_ln2(float rate) {
   return (float)(-(1.0 / (double)rate) * 0.69314718055994530942);
 }
 
+// The launch's copy of the arguments with the controls' centring constants.
+Mm1Args centred(const Mm1Args &a) {
+  Mm1Args b = a;
+  if (b.feature_prefix > 0) {
+    b.log_grid_mean = log_grid_mean();
+    if (!b.items.dp) {
+      b.ea = variate_mean_f32(b.lambda);
+      b.es = variate_mean_f32(b.mu);
+    }
+  }
+  return b;
+}
+
 }  // namespace
+
+// (1 / 2^24) sum_{k=1}^{2^24} (24 ln 2 - ln k) = 24 ln 2 - ln((2^24)!) / 2^24
+double log_grid_mean() {
+  return 24.0 * std::log(2.0) - std::lgamma(16777217.0) / 16777216.0;
+}
+
+float variate_mean_f32(float rate) {
+  return (float)((double)(float)(1.0 / (double)rate) * log_grid_mean());
+}
 
 template <int LPR>
 hipError_t taus_launch(const Mm1Args &a, hipStream_t s) {
@@ -886,7 +1053,8 @@ hipError_t taus_launch(const Mm1Args &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mm1_taus(const Mm1Args &a, uint32_t lanes_per_rep, hipStream_t s) {
+hipError_t launch_mm1_taus(const Mm1Args &a_in, uint32_t lanes_per_rep, hipStream_t s) {
+  const Mm1Args a = centred(a_in);
   switch (lanes_per_rep) {
     case 16: return taus_launch<16>(a, s);
     case 32: return taus_launch<32>(a, s);
@@ -897,7 +1065,8 @@ hipError_t launch_mm1_taus(const Mm1Args &a, uint32_t lanes_per_rep, hipStream_t
   }
 }
 
-hipError_t launch_mm1_wave(const Mm1Args &a, uint32_t rpw, uint32_t wg, hipStream_t s) {
+hipError_t launch_mm1_wave(const Mm1Args &a_in, uint32_t rpw, uint32_t wg, hipStream_t s) {
+  const Mm1Args a = centred(a_in);
   const uint64_t waves = (a.n_reps + rpw - 1) / rpw;
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (waves + wpb - 1) / wpb;
@@ -930,8 +1099,9 @@ hipError_t split_launch(const Mm1Args &a, float ca, float cs, hipStream_t s,
                               : split_launch_as<X, false>(a, ca, cs, s, ev);
 }
 
-hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_t s,
+hipError_t launch_mm1_split(const Mm1Args &a_in, uint32_t waves_per_rep, hipStream_t s,
                             const KernelEvents *ev) {
+  const Mm1Args a = centred(a_in);
   if (a.rng == RNG_TAUS88) {
     if (ev) return hipErrorInvalidValue;  // the taus88 form is not self-timed
     return launch_mm1_taus(a, 64 * waves_per_rep, s);
@@ -943,7 +1113,8 @@ hipError_t launch_mm1_split(const Mm1Args &a, uint32_t waves_per_rep, hipStream_
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s) {
+hipError_t launch_mm1_simt(const Mm1Args &a_in, bool one_lane, hipStream_t s) {
+  const Mm1Args a = centred(a_in);
   const uint32_t wg = 64;
   const uint64_t threads = a.n_reps * (one_lane ? 64 : 1);
   const uint64_t blocks = (threads + wg - 1) / wg;
@@ -959,8 +1130,9 @@ hipError_t launch_mm1_simt(const Mm1Args &a, bool one_lane, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mm1_plan_simt(const Mm1Args &a, uint64_t n_items, bool one_lane,
+hipError_t launch_mm1_plan_simt(const Mm1Args &a_in, uint64_t n_items, bool one_lane,
                                 hipStream_t s) {
+  const Mm1Args a = centred(a_in);
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -975,8 +1147,9 @@ hipError_t launch_mm1_plan_simt(const Mm1Args &a, uint64_t n_items, bool one_lan
   return hipGetLastError();
 }
 
-hipError_t launch_mm1_plan(const Mm1Args &a, uint64_t n_items, uint32_t rpw, uint32_t wg,
+hipError_t launch_mm1_plan(const Mm1Args &a_in, uint64_t n_items, uint32_t rpw, uint32_t wg,
                            hipStream_t s) {
+  const Mm1Args a = centred(a_in);
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -1000,8 +1173,9 @@ hipError_t launch_mm1_plan(const Mm1Args &a, uint64_t n_items, uint32_t rpw, uin
   return hipGetLastError();
 }
 
-hipError_t launch_mm1_plan_split(const Mm1Args &a, uint64_t n_items, uint64_t n_long,
+hipError_t launch_mm1_plan_split(const Mm1Args &a_in, uint64_t n_items, uint64_t n_long,
                                  uint32_t waves_per_rep, uint32_t rpw, hipStream_t s) {
+  const Mm1Args a = centred(a_in);
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;

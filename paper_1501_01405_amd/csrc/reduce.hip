@@ -42,11 +42,19 @@ __device__ long long block_sum_ll(long long v, long long *sh) {
   return r;
 }
 
+// Segment blockIdx.x of x (blockIdx.y = 0) or of x1, a second fp32 array
+// reduced alongside in the same launch (blockIdx.y = 1, into out1).
 __global__ void reduce_kernel(const void *x, int dtype, const uint32_t *index,
-                              const uint64_t *offsets, uint64_t n, double *out) {
+                              const uint64_t *offsets, uint64_t n, double *out, const float *x1,
+                              double *out1) {
   __shared__ double shd[RB];
   __shared__ long long shl[RB];
   const uint32_t g = blockIdx.x;
+  if (blockIdx.y == 1) {
+    x = x1;
+    dtype = 1;
+    out = out1;
+  }
   const uint64_t begin = offsets ? offsets[g] : 0;
   const uint64_t end = offsets ? offsets[g + 1] : n;
   const uint64_t cnt = end - begin;
@@ -131,7 +139,7 @@ __global__ void taus_dump_kernel(uint64_t seed, uint32_t model, uint32_t dp, uin
 hipError_t launch_reduce_f64(const void *x, int dtype, uint64_t n, const uint64_t *offsets,
                              uint32_t n_segments, double *out, hipStream_t s) {
   hipLaunchKernelGGL(reduce_kernel, dim3(n_segments), dim3(RB), 0, s, x, dtype, nullptr, offsets,
-                     n, out);
+                     n, out, (const float *)nullptr, (double *)nullptr);
   return hipGetLastError();
 }
 
@@ -139,7 +147,15 @@ hipError_t launch_reduce_f64_gather(const void *x, int dtype, const uint32_t *in
                                     const uint64_t *offsets, uint32_t n_segments, double *out,
                                     hipStream_t s) {
   hipLaunchKernelGGL(reduce_kernel, dim3(n_segments), dim3(RB), 0, s, x, dtype, index, offsets,
-                     (uint64_t)0, out);
+                     (uint64_t)0, out, (const float *)nullptr, (double *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_f64_gather2(const float *x0, const float *x1, const uint32_t *index,
+                                     const uint64_t *offsets, uint32_t n_segments, double *out0,
+                                     double *out1, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(n_segments, 2), dim3(RB), 0, s, (const void *)x0, 1,
+                     index, offsets, (uint64_t)0, out0, x1, out1);
   return hipGetLastError();
 }
 

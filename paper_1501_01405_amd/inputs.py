@@ -45,29 +45,27 @@ def uniform_items(n_dp, reps, customers, rho, mu=1.0, dp_base=0, rep_base=0):
     return items
 
 
-def cv_design(n_train=100000, train_reps=32, n_apply_dp=256, reps=64, prefix_reps=256,
-              customers=100000, prefix=1000, rho_lo=0.5, rho_hi=0.95, seed=7):
+def cv_design(n_train=100000, train_reps=32, n_apply_dp=256, reps=64, customers=100000,
+              rho_lo=0.5, rho_hi=0.95, seed=7):
     """Control-variate experiment: a training set of n_train replications
     (design points with rho ~ U[rho_lo, rho_hi], `train_reps` replications
-    each), then new design points with `reps` full replications and
-    `prefix_reps` prefix-only replications each. Ids never overlap: training
-    dps are 0..n_train/train_reps-1, application dps start at n_train;
-    prefix replications use rep ids from 2^20 up."""
+    each), then new design points with `reps` replications each. Ids never
+    overlap: training dps are 0..n_train/train_reps-1, application dps start
+    at n_train."""
     rng = np.random.default_rng(seed)
     n_tdp = max(1, n_train // train_reps)
     train = uniform_items(n_tdp, train_reps, customers, rng.uniform(rho_lo, rho_hi, n_tdp))
     rho = rng.uniform(rho_lo, rho_hi, n_apply_dp)
-    full = uniform_items(n_apply_dp, reps, customers, rho, dp_base=n_train)
-    pre = uniform_items(n_apply_dp, prefix_reps, prefix, rho, dp_base=n_train, rep_base=1 << 20)
-    return train, full, pre
+    apply = uniform_items(n_apply_dp, reps, customers, rho, dp_base=n_train)
+    return train, apply
 
 
-def he_uniform_init(seed=3, d_in=10, hidden=128):
-    """Flat fp32 weights [W1 (h x d), b1, W2 (h x h), b2, W3 (1 x h), b3] with
-    W ~ U(-sqrt(6/fan_in), +sqrt(6/fan_in)) and zero biases."""
+def he_uniform_init(seed=3, d_in=10, hidden=128, d_out=4):
+    """Flat fp32 weights [W1 (h x d), b1, W2 (h x h), b2, W3 (d_out x h), b3]
+    with W ~ U(-sqrt(6/fan_in), +sqrt(6/fan_in)) and zero biases."""
     rng = np.random.default_rng(seed)
     parts = []
-    for rows, cols in ((hidden, d_in), (hidden, hidden), (1, hidden)):
+    for rows, cols in ((hidden, d_in), (hidden, hidden), (d_out, hidden)):
         lim = math.sqrt(6.0 / cols)
         parts.append(rng.uniform(-lim, lim, rows * cols))
         parts.append(np.zeros(rows))

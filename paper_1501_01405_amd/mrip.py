@@ -18,8 +18,10 @@ MRIP_OK, MRIP_E_INVAL, MRIP_E_NOMEM, MRIP_E_HIP, MRIP_E_STATE, MRIP_E_TOO_FEW, \
 MRIP_RW, MRIP_MM1, MRIP_FF, MRIP_PI = 1, 2, 3, 4
 MRIP_MAP_AUTO, MRIP_MAP_SIMT, MRIP_MAP_WAVE, MRIP_MAP_LANE0 = 0, 1, 2, 3
 MRIP_RNG_PHILOX, MRIP_RNG_TAUS88 = 0, 1
-MRIP_MLP_PARAMS = 18049
+MRIP_MLP_OUT = 4
+MRIP_MLP_PARAMS = 18436
 MRIP_CV_BETA_BINS = 16
+MRIP_CV_COEFS = 5
 
 
 class mrip_rw_params(C.Structure):
@@ -95,16 +97,16 @@ _SIGS = {
     "mrip_autotune": (st, [ctx_t, u64, u64, vp, C.POINTER(u32), C.POINTER(u32),
                            C.POINTER(f32)]),
     "mrip_mlp_forward": (st, [vp, vp, u64, vp, vp]),
-    "mrip_mlp_grad": (st, [vp, vp, vp, u64, vp, vp, vp]),
+    "mrip_mlp_grad": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
     "mrip_adam_step": (st, [vp, vp, vp, vp, u64, u64, f32, f32, f32, f32, vp]),
     "mrip_cv_train": (st, [ctx_t, vp, u64, vp, C.POINTER(mrip_cv_hparams), u64, vp]),
     "mrip_cv_model": (st, [ctx_t, vp, vp, vp, vp, vp, vp]),
     "mrip_cv_set_model": (st, [ctx_t, vp, vp, vp, vp, f32, f32]),
     "mrip_cv_outputs": (st, [ctx_t, u32, vp, u64]),
-    "mrip_cv_apply": (st, [ctx_t, vp, u64, vp, u64, u64, vp]),
+    "mrip_cv_apply": (st, [ctx_t, vp, u64, u64, vp]),
     "mrip_cv_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t),
                            C.POINTER(mrip_stats_t)]),
-    "mrip_cv_times": (st, [ctx_t, C.POINTER(f32), C.POINTER(f32), C.POINTER(f32)]),
+    "mrip_cv_times": (st, [ctx_t, C.POINTER(f32), C.POINTER(f32)]),
     "mrip_philox": (st, [u64, vp, u64, vp, vp]),
     "mrip_taus88": (st, [u64, u32, u32, u32, u64, u64, vp, vp]),
     "mrip_t_quantile": (f64, [f64, f64]),
@@ -285,9 +287,9 @@ def mrip_mlp_forward(theta, x, n, y, stream=None):
     check(load().mrip_mlp_forward(_ptr(theta), _ptr(x), n, _ptr(y), stream))
 
 
-def mrip_mlp_grad(theta, x, y, n, grad, loss=None, stream=None):
-    check(load().mrip_mlp_grad(_ptr(theta), _ptr(x), _ptr(y), n, _ptr(grad), _ptr(loss),
-                               stream))
+def mrip_mlp_grad(theta, x, z, y, n, grad, loss=None, stream=None):
+    check(load().mrip_mlp_grad(_ptr(theta), _ptr(x), _ptr(z), _ptr(y), n, _ptr(grad),
+                               _ptr(loss), stream))
 
 
 def mrip_adam_step(theta, m, v, grad, n_params, step, lr=1e-3, beta1=0.9, beta2=0.999,
@@ -306,42 +308,44 @@ def mrip_cv_train(ctx, items, theta0, hparams=None, seed=42, stream=None):
 
 
 def mrip_cv_model(ctx):
-    """dict(theta, feat_mean, feat_std, beta (table), rho_range, final_loss)."""
+    """dict(theta, feat_mean, feat_std, coef (bins x coefs), rho_range, final_loss)."""
     theta = np.zeros(MRIP_MLP_PARAMS, np.float32)
     mean = np.zeros(10, np.float32)
     std = np.zeros(10, np.float32)
-    beta = np.zeros(MRIP_CV_BETA_BINS, np.float32)
+    coef = np.zeros((MRIP_CV_BETA_BINS, MRIP_CV_COEFS), np.float32)
     rr = np.zeros(2, np.float32)
     loss = f32()
     check(load().mrip_cv_model(ctx, theta.ctypes.data, mean.ctypes.data, std.ctypes.data,
-                               beta.ctypes.data, rr.ctypes.data, C.byref(loss)), ctx)
-    return dict(theta=theta, feat_mean=mean, feat_std=std, beta=beta,
+                               coef.ctypes.data, rr.ctypes.data, C.byref(loss)), ctx)
+    return dict(theta=theta, feat_mean=mean, feat_std=std, coef=coef,
                 rho_range=(float(rr[0]), float(rr[1])), final_loss=loss.value)
 
 
-def mrip_cv_set_model(ctx, theta, feat_mean, feat_std, beta_table, rho_lo, rho_hi):
+def mrip_cv_set_model(ctx, theta, feat_mean, feat_std, coef_table, rho_lo, rho_hi):
+    """coef_table: (MRIP_CV_BETA_BINS, MRIP_CV_COEFS), or one row for every bin."""
     theta = np.ascontiguousarray(theta, dtype=np.float32)
     feat_mean = np.ascontiguousarray(feat_mean, dtype=np.float32)
     feat_std = np.ascontiguousarray(feat_std, dtype=np.float32)
-    beta_table = np.ascontiguousarray(np.broadcast_to(beta_table, (MRIP_CV_BETA_BINS,)),
-                                      dtype=np.float32)
+    coef = np.ascontiguousarray(np.broadcast_to(np.asarray(coef_table, np.float32),
+                                                (MRIP_CV_BETA_BINS, MRIP_CV_COEFS)))
     check(load().mrip_cv_set_model(ctx, theta.ctypes.data, feat_mean.ctypes.data,
-                                   feat_std.ctypes.data, beta_table.ctypes.data, rho_lo, rho_hi),
-          ctx)
+                                   feat_std.ctypes.data, coef.ctypes.data, rho_lo, rho_hi), ctx)
+
+
+# columns per replication of each mrip_cv_outputs `which`
+CV_OUTPUT_COLS = {0: 1, 1: 1, 2: 4, 3: 10, 4: 8, 5: 1, 6: 10, 7: 8, 8: 4}
 
 
 def mrip_cv_outputs(ctx, which, n):
-    cols = 10 if which in (3, 4) else 1
+    cols = CV_OUTPUT_COLS.get(which, 1)
     out = np.zeros((n, cols) if cols > 1 else n, np.float32)
     check(load().mrip_cv_outputs(ctx, which, out.ctypes.data, out.nbytes), ctx)
     return out
 
 
-def mrip_cv_apply(ctx, full, prefix, seed=42, stream=None):
-    full = np.ascontiguousarray(full, dtype=PLAN_ITEM_DTYPE)
-    prefix = np.ascontiguousarray(prefix, dtype=PLAN_ITEM_DTYPE)
-    check(load().mrip_cv_apply(ctx, full.ctypes.data, full.shape[0], prefix.ctypes.data,
-                               prefix.shape[0], seed, stream), ctx)
+def mrip_cv_apply(ctx, items, seed=42, stream=None):
+    items = np.ascontiguousarray(items, dtype=PLAN_ITEM_DTYPE)
+    check(load().mrip_cv_apply(ctx, items.ctypes.data, items.shape[0], seed, stream), ctx)
 
 
 def mrip_cv_stats(ctx, dp, confidence=0.95):
@@ -351,9 +355,10 @@ def mrip_cv_stats(ctx, dp, confidence=0.95):
 
 
 def mrip_cv_times(ctx):
-    a, b, c = f32(), f32(), f32()
-    check(load().mrip_cv_times(ctx, C.byref(a), C.byref(b), C.byref(c)), ctx)
-    return a.value, b.value, c.value
+    """(simulation kernel ms, inference and estimator ms) of the last apply."""
+    a, b = f32(), f32()
+    check(load().mrip_cv_times(ctx, C.byref(a), C.byref(b)), ctx)
+    return a.value, b.value
 
 
 def mrip_philox(seed, ctr, n, out, stream=None):
@@ -441,8 +446,8 @@ class Context:
     def output(self, output=0, n=None):
         import torch
         n = self.n if n is None else n
-        if self.model == MRIP_MM1 and output == 3:
-            t = torch.empty((n, 10), dtype=torch.float32, device="cuda")
+        if self.model == MRIP_MM1 and output in (3, 4):
+            t = torch.empty((n, 10 if output == 3 else 8), dtype=torch.float32, device="cuda")
         else:
             dt = getattr(torch, _OUT_DTYPES[self.model][output])
             t = torch.empty(n, dtype=dt, device="cuda")

@@ -1,7 +1,8 @@
 """GPU parity of the control-variate network kernels against the oracle:
-forward pass, gradients (per-tensor relative Frobenius error < 1e-3 on the
-same bf16 operands) and Adam, at batch sizes that span several 64-sample
-workgroups and a ragged tail."""
+forward pass (four outputs), gradients of the multiplier loss (per-tensor
+relative Frobenius error < 1e-3 on the same bf16 operands, with per-sample
+multipliers and with the first output alone) and Adam, at batch sizes that
+span several 64-sample workgroups and a ragged tail."""
 import numpy as np
 import pytest
 import torch
@@ -35,53 +36,74 @@ def test_forward_matches_oracle(gpu, n):
     rng = np.random.default_rng(n)
     x = rng.normal(size=(n, 10)).astype(np.float32)
     theta = _theta(1)
-    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    y = torch.empty((n, mrip.MRIP_MLP_OUT), dtype=torch.float32, device="cuda")
     mrip.mrip_mlp_forward(_dev(theta), _dev(x), n, y, mrip.current_stream())
     torch.cuda.synchronize()
     got = y.cpu().numpy().astype(np.float64)
     ref, _ = omlp.forward(theta, x, bf16=True)
+    assert got.shape == ref.shape
     assert np.max(np.abs(got - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("n", [64, 777, 1024, 4096])
-def test_gradient_matches_oracle(gpu, n):
-    announce("mlp grad", n)
+@pytest.mark.parametrize("n,mult", [(64, True), (777, True), (1024, False), (4096, True),
+                                    (1000, False)])
+def test_gradient_matches_oracle(gpu, n, mult):
+    announce("mlp grad", n, mult)
     rng = np.random.default_rng(7 + n)
     x = rng.normal(size=(n, 10)).astype(np.float32)
     yt = rng.normal(size=n).astype(np.float32)
+    z = rng.normal(size=(n, 4)).astype(np.float32) if mult else None
     theta = _theta(2)
     grad = torch.empty(mrip.MRIP_MLP_PARAMS, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    mrip.mrip_mlp_grad(_dev(theta), _dev(x), _dev(yt), n, grad, loss, mrip.current_stream())
+    mrip.mrip_mlp_grad(_dev(theta), _dev(x), None if z is None else _dev(z), _dev(yt), n, grad,
+                       loss, mrip.current_stream())
     torch.cuda.synchronize()
     g = grad.cpu().numpy().astype(np.float64)
-    ref, ref_loss = omlp.backward(theta, x, yt, bf16=True)
+    ref, ref_loss = omlp.backward(theta, x, yt, bf16=True, z=z)
     gd, rd = omlp.unpack(g), omlp.unpack(ref)
     for name in NAMES:
         err = np.linalg.norm(gd[name] - rd[name]) / max(np.linalg.norm(rd[name]), 1e-30)
         assert err < 1e-3, (name, err)
     assert abs(float(loss.cpu()[0]) - ref_loss) <= 1e-4 * ref_loss
+    if not mult:  # z = e_0: the other outputs' weights get no gradient
+        assert np.all(gd["W3"][1:] == 0.0) and np.all(gd["b3"][1:] == 0.0)
 
 
 def test_gradient_of_constant_network_is_bias_only(gpu):
-    # W3 = 0: every gradient except dW3 and db3 vanishes; db3 = 2 mean(c - y)
+    # W3 = 0: every gradient except dW3 and db3 vanishes; with prediction
+    # c = b3 . z, db3_k = 2 mean((c - y) z_k)
     announce("mlp grad constant")
     n = 300
     rng = np.random.default_rng(3)
     x = rng.normal(size=(n, 10)).astype(np.float32)
     yt = rng.normal(size=n).astype(np.float32)
+    z = rng.normal(size=(n, 4)).astype(np.float32)
     d = omlp.unpack(_theta(4).astype(np.float64))
     d = {k: v.copy() for k, v in d.items()}
     d["W3"][:] = 0.0
-    d["b3"][:] = 0.5
+    d["b3"][:] = [0.5, -0.25, 1.0, 0.125]
     theta = omlp.pack(d).astype(np.float32)
     grad = torch.empty(mrip.MRIP_MLP_PARAMS, dtype=torch.float32, device="cuda")
-    mrip.mrip_mlp_grad(_dev(theta), _dev(x), _dev(yt), n, grad, None, mrip.current_stream())
+    mrip.mrip_mlp_grad(_dev(theta), _dev(x), _dev(z), _dev(yt), n, grad, None,
+                       mrip.current_stream())
     torch.cuda.synchronize()
     gd = omlp.unpack(grad.cpu().numpy().astype(np.float64))
     for name in ("W1", "b1", "W2", "b2"):
         assert np.all(gd[name] == 0.0), name
-    assert abs(gd["b3"][0] - 2 * np.mean(0.5 - yt.astype(np.float64))) < 1e-5
+    z64 = z.astype(np.float64)
+    err = z64 @ d["b3"] - yt.astype(np.float64)
+    want = 2.0 * (err[:, None] * z64).mean(axis=0)
+    assert np.max(np.abs(gd["b3"] - want)) < 1e-5 * max(1.0, np.abs(want).max())
+
+
+def test_misaligned_output_is_refused(gpu):
+    announce("mlp alignment")
+    theta = torch.zeros(mrip.MRIP_MLP_PARAMS, dtype=torch.float32, device="cuda")
+    x = torch.zeros((4, 10), dtype=torch.float32, device="cuda")
+    y = torch.zeros(20, dtype=torch.float32, device="cuda")
+    with pytest.raises(mrip.MripError):
+        mrip.mrip_mlp_forward(theta, x, 4, y[1:], mrip.current_stream())
 
 
 def test_adam_matches_oracle(gpu):
