@@ -368,6 +368,21 @@ MRIP_API mrip_status mrip_mlp_grad(const float *theta_dev, const float *x_dev, c
                           const float *y_dev, uint64_t n, float *grad_dev, float *loss_dev,
                           void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * gradient as mrip_mlp_grad, bit for bit, with its per-64-sample partial
+ * rows in a fixed device array of the library (MRIP_MLP_GRAD_NOALLOC_MAX /
+ * 64 rows of 18440 floats, about 4.7 MB, held by each GPU the library
+ * runs on until the process ends) instead of an allocation. Calls no
+ * allocating routine and does not synchronise. n <= MRIP_MLP_GRAD_NOALLOC_MAX
+ * (MRIP_E_INVAL beyond it); the other arguments as for mrip_mlp_grad. Every
+ * call on one GPU shares that array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller. */
+#define MRIP_MLP_GRAD_NOALLOC_MAX 4096
+MRIP_API mrip_status mrip_mlp_grad_noalloc(const float *theta_dev, const float *x_dev,
+                                           const float *z_dev, const float *y_dev, uint64_t n,
+                                           float *grad_dev, float *loss_dev, void *hip_stream);
+
 /* One Adam step (Kingma and Ba 2015, Algorithm 1) on fp32 weights;
  * `step` counts from 1; n_params <= 2^32 - 256. */
 MRIP_API mrip_status mrip_adam_step(float *theta_dev, float *m_dev, float *v_dev, const float *grad_dev,

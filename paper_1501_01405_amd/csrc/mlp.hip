@@ -20,6 +20,9 @@
 // v_cvt_pk_bf16_f32); biases, ReLU masks and the loss stay fp32.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
+#include "../../include/mrip.h"
 #include "device.hpp"
 #include "mlp.hpp"
 
@@ -474,4 +477,63 @@ hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint
   return hipGetLastError();
 }
 
+// ------------------------------------------------ gradient without allocation
+// The partial-gradient rows of mrip_mlp_grad_noalloc live in a file-scope
+// device array: each GPU the library runs on holds its own copy, at its own
+// address, until the process ends. Host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (the array's name is a
+// host-side stand-in there, not a device address).
+namespace {
+
+constexpr uint64_t NOALLOC_MAX_N = MRIP_MLP_GRAD_NOALLOC_MAX;
+constexpr uint64_t NOALLOC_ROWS = NOALLOC_MAX_N / TS;
+static_assert(NOALLOC_MAX_N % TS == 0, "whole partial rows");
+
+__device__ __align__(256) float scratch[NOALLOC_ROWS * MLP_PSTRIDE];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of this device's scratch, looked up on its first use
+// with the device current.
+hipError_t scratch_on_device(float **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (float *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
 }  // namespace mrip
+
+extern "C" MRIP_API mrip_status mrip_mlp_grad_noalloc(const float *theta_dev, const float *x_dev,
+                                                      const float *z_dev, const float *y_dev,
+                                                      uint64_t n, float *grad_dev, float *loss_dev,
+                                                      void *hip_stream) {
+  using namespace mrip;
+  if (n == 0 || !theta_dev || !x_dev || !y_dev || !grad_dev) return MRIP_E_INVAL;
+  if (n > NOALLOC_MAX_N) return MRIP_E_INVAL;  // beyond the scratch array
+  if (z_dev && ((uintptr_t)z_dev & 15u)) return MRIP_E_INVAL;
+  float *part = nullptr;
+  if (scratch_on_device(&part) != hipSuccess) return MRIP_E_HIP;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const uint64_t rows = (n + TS - 1) / TS;
+  // every row the reduction reads is written first by the gradient kernel
+  if (launch_mlp_grad(theta_dev, x_dev, z_dev, y_dev, n, part, s) != hipSuccess) return MRIP_E_HIP;
+  AdamArgs none{};
+  if (launch_grad_reduce(part, (uint32_t)rows, n, grad_dev, loss_dev, nullptr, nullptr, nullptr,
+                         none, s) != hipSuccess)
+    return MRIP_E_HIP;
+  return MRIP_OK;
+}
+

@@ -19,6 +19,7 @@ MRIP_RW, MRIP_MM1, MRIP_FF, MRIP_PI = 1, 2, 3, 4
 MRIP_MAP_AUTO, MRIP_MAP_SIMT, MRIP_MAP_WAVE, MRIP_MAP_LANE0 = 0, 1, 2, 3
 MRIP_RNG_PHILOX, MRIP_RNG_TAUS88 = 0, 1
 MRIP_MLP_OUT = 4
+MRIP_MLP_GRAD_NOALLOC_MAX = 4096
 MRIP_MLP_PARAMS = 18436
 MRIP_CV_BETA_BINS = 16
 MRIP_CV_COEFS = 5
@@ -98,6 +99,7 @@ _SIGS = {
                            C.POINTER(f32)]),
     "mrip_mlp_forward": (st, [vp, vp, u64, vp, vp]),
     "mrip_mlp_grad": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
+    "mrip_mlp_grad_noalloc": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
     "mrip_adam_step": (st, [vp, vp, vp, vp, u64, u64, f32, f32, f32, f32, vp]),
     "mrip_cv_train": (st, [ctx_t, vp, u64, vp, C.POINTER(mrip_cv_hparams), u64, vp]),
     "mrip_cv_model": (st, [ctx_t, vp, vp, vp, vp, vp, vp]),
@@ -290,6 +292,11 @@ def mrip_mlp_forward(theta, x, n, y, stream=None):
 def mrip_mlp_grad(theta, x, z, y, n, grad, loss=None, stream=None):
     check(load().mrip_mlp_grad(_ptr(theta), _ptr(x), _ptr(z), _ptr(y), n, _ptr(grad),
                                _ptr(loss), stream))
+
+
+def mrip_mlp_grad_noalloc(theta, x, z, y, n, grad, loss=None, stream=None):
+    check(load().mrip_mlp_grad_noalloc(_ptr(theta), _ptr(x), _ptr(z), _ptr(y), n, _ptr(grad),
+                                       _ptr(loss), stream))
 
 
 def mrip_adam_step(theta, m, v, grad, n_params, step, lr=1e-3, beta1=0.9, beta2=0.999,
