@@ -230,6 +230,9 @@ def cpu_baseline(seconds, per_workload=True):
            "kind": "oracle",
            "sample": "the whole workload (%d replications x %d customers), %d passes "
                      "(seeds 42..%d), %.1f s wall" % (R, N, passes, 41 + passes, dt),
+           "single_core": {"value": N / one, "unit": "customers/s", "cores": 1,
+                           "sample": "4 replications of the workload (ids 0..3) on one "
+                                     "thread, one after the other"},
            "cpu_model": model, "host_cpus": os.cpu_count()}
     if per_workload:
         out["per_workload"] = oracle_workloads(core, threads)
@@ -247,8 +250,10 @@ def oracle_workloads(core, threads):
 
     res = {}
     dt = timed(lambda: core.rw_many(42, 32, 64, 64, 1000, threads=threads))
+    one = timed(lambda: core.rw_many(42, 4, 64, 64, 1000, threads=1))
     res["rw_32x64x1000"] = {"walker_steps_per_s": 32 * 64 * 1000 / dt,
-                            "sample": "the whole workload (32 replications)"}
+                            "single_core_walker_steps_per_s": 4 * 64 * 1000 / one,
+                            "sample": "the whole workload (32 replications); one core: 4"}
     # pi: one replication of 1e7 points on one core (the paper's CPU-vs-GPU
     # crossover), then one replication per thread
     one = timed(lambda: core.pi_hits(7, 0, 10_000_000))
@@ -257,15 +262,20 @@ def oracle_workloads(core, threads):
                      "sample": "%d replications of 1e7 points (of 1024)" % threads}
     n_ff = 2 * threads
     dt = timed(lambda: core.ff_many(42, n_ff, 128, 2000, 0.01, 1e-5, threads=threads))
+    one = timed(lambda: core.ff_many(42, 1, 128, 2000, 0.01, 1e-5, threads=1))
     res["ff_4096x128x128x2000"] = {
         "cell_updates_per_s": n_ff * 128 * 128 * 2000 / dt,
-        "sample": "%d whole replications (of 4096)" % n_ff}
+        "single_core_cell_updates_per_s": 128 * 128 * 2000 / one,
+        "sample": "%d whole replications (of 4096); one core: 1" % n_ff}
     items = inputs.plan_table()
     rows = [(int(i["dp"]), int(i["rep"]), int(i["customers"]), float(i["lambda_"]),
              float(i["mu"])) for i in items]
     dt = timed(lambda: core.mm1_items(42, rows, threads=threads))
+    sub = rows[::64]  # every 64th item, the length mix kept
+    one = timed(lambda: core.mm1_items(42, sub, threads=1))
     res["plan_64x32"] = {"customers_per_s": float(items["customers"].sum()) / dt,
-                         "sample": "the whole plan (2048 items)"}
+                         "single_core_customers_per_s": float(sum(r[2] for r in sub)) / one,
+                         "sample": "the whole plan (2048 items); one core: every 64th item"}
     return res
 
 

@@ -191,7 +191,8 @@ MRIP_API void mrip_destroy(mrip_ctx ctx);
 
 /* WAVE launch shape: replications per wavefront (1, 2 or 4; M/M/1 only)
  * and workgroup size (64, 256 or 1024) of the one-wavefront-per-replication
- * kernels. Outputs do not depend on it. Defaults 1 and 256. Runs of few
+ * kernels, for runs and for plans (mrip_autotune later sets the plans'
+ * alone). Outputs do not depend on it. Defaults 1 and 256. Runs of few
  * replications use workgroup-per-replication forms instead, whose size the
  * model fixes: the walk up to 2048 replications (16 lanes per walker), pi
  * below 4096 replications of at least 65536 points (2 to 16 wavefronts). */
@@ -318,20 +319,49 @@ MRIP_API mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidenc
 MRIP_API mrip_status mrip_set_plan_split(mrip_ctx ctx, uint32_t waves_per_item,
                                          uint64_t long_min);
 
-/* Current launch shape: reps_per_wave, workgroup, wavefronts per
+/* Current launch shape: reps_per_wave, workgroup and wavefronts per
  * replication of mrip_run, wavefronts per long plan item (any may be NULL). */
 MRIP_API mrip_status mrip_get_shape(mrip_ctx ctx, uint32_t *reps_per_wave, uint32_t *workgroup,
                                     uint32_t *split, uint32_t *plan_split);
 
 /* Time every (reps_per_wave, workgroup) in {1,2,4} x {64,256,1024}, and,
  * when the plan has long items, every reps_per_wave with long items split
- * over 2 or 4 wavefronts (workgroup 256), on the uploaded plan (or on an
- * evenly strided slice of `calib_items` items of its longest-first order,
- * 0 = all); keep the fastest as the context's plan shape and report its
- * reps_per_wave, workgroup and time (mrip_get_shape gives the split).
- * WAVE contexts only (MRIP_E_UNSUPPORTED otherwise). Synchronises. */
+ * over 2, 4 or 8 wavefronts (workgroups of 256 threads, 512 for 8), on the
+ * uploaded plan (or on an evenly strided slice of `calib_items` items of
+ * its longest-first order, 0 = all); keep the fastest as the context's plan
+ * shape (mrip_run's shape is left as it is) and report its reps_per_wave,
+ * the workgroup size it launches and its time (mrip_get_shape gives the
+ * split). WAVE contexts only (MRIP_E_UNSUPPORTED otherwise). Synchronises. */
 MRIP_API mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, void *hip_stream,
                           uint32_t *best_rpw, uint32_t *best_workgroup, float *best_ms);
+
+/* The autotuner's cache (the paper's section 6 leaves the block size to
+ * tune for occupancy). When the environment variable MRIP_TUNE_CACHE names a
+ * file, mrip_autotune first looks up the plan's key there and, when found,
+ * installs that shape without timing; otherwise it times the shapes and
+ * stores the winner. The file holds one line per key: the key, reps per
+ * wavefront, workgroup, wavefronts per long item and milliseconds. */
+typedef struct {
+  uint32_t reps_per_wave, workgroup, plan_split;
+  float ms;
+} mrip_tune_entry;
+
+/* The cache key of a plan: model, mapping, log2 buckets of the item count,
+ * of the long items + 1 and of the longest item's customers, the GPU's
+ * architecture name (blanks and '/' become '_') and its compute-unit count,
+ * written to out (at most cap bytes with the terminating 0). Host only;
+ * MRIP_E_INVAL on NULL or empty arguments, n_items = 0 or a short buffer. */
+MRIP_API mrip_status mrip_tune_key(mrip_model model, mrip_mapping mapping, uint64_t n_items,
+                                   uint64_t n_long, uint64_t max_customers, const char *arch,
+                                   uint32_t cus, char *out, uint64_t cap);
+/* The last entry stored for `key` in the cache file at `path`: MRIP_E_STATE
+ * when the file or the key is absent, MRIP_E_INVAL on bad arguments. */
+MRIP_API mrip_status mrip_tune_cache_get(const char *path, const char *key, mrip_tune_entry *out);
+/* Store (or replace) `key`'s entry: the file is rewritten beside the old one
+ * and renamed into place. MRIP_E_INVAL on bad arguments or an unwritable
+ * path. */
+MRIP_API mrip_status mrip_tune_cache_put(const char *path, const char *key,
+                                         const mrip_tune_entry *e);
 
 /* ----------------------------------------- learned control variate (CV) */
 /* Not in the paper; it extends MRIP's estimator (section 1: the mean of

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -87,6 +88,7 @@ mrip_status ensure_events(mrip_ctx c) {
     if (!c->ev_set_free[i])
       HIP_TRY(c, hipEventCreateWithFlags(&c->ev_set_free[i], hipEventDisableTiming));
   if (!c->red_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->red_stream, hipStreamNonBlocking));
+  if (!c->ev_done) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
   if (!c->stats_host) {
     const size_t bytes = sizeof(double) * mrip_ctx_s::STATS_RING * mrip_ctx_s::STATS_SLOT;
     HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, bytes, hipHostMallocMapped));
@@ -125,18 +127,28 @@ mrip_status commit_stats_slot(mrip_ctx c, hipStream_t s) {
   return MRIP_OK;
 }
 
+// Work enqueued on another stream than the last call's first waits, on the
+// device, for everything that call enqueued on its stream: the context's
+// buffers (device queue, scratch, outputs) serve one call at a time. Every
+// launching call makes this its first enqueue and ends with mark_done.
+mrip_status order_after_last(mrip_ctx c, hipStream_t s) {
+  if (c->done_pending && s != c->last_stream) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_done, 0));
+  return MRIP_OK;
+}
+
+mrip_status mark_done(mrip_ctx c, hipStream_t s) {
+  HIP_TRY(c, hipEventRecord(c->ev_done, s));
+  c->done_pending = true;
+  c->last_stream = s;
+  return MRIP_OK;
+}
+
 // Events bracketing one simulation-kernel launch: the next slot of the
 // run-history ring (the last run's pair is the slot before `launches`).
-// A launch on another stream than the last one first waits for the last
-// launch: the context's scratch buffers serve one launch at a time.
 // `markers`: record the pair as separate stream markers; otherwise the one
 // kernel of the launch records them itself (KernelEvents), which saves two
 // packets between consecutive runs.
 mrip_status record_begin(mrip_ctx c, hipStream_t s, bool markers = true) {
-  if (c->launches > 0 && s != c->last_stream) {
-    const uint32_t prev = (uint32_t)((c->launches - 1) % mrip_ctx_s::RING);
-    HIP_TRY(c, hipStreamWaitEvent(s, c->ring1[prev], 0));
-  }
   const uint32_t slot = (uint32_t)(c->launches % mrip_ctx_s::RING);
   if (!c->ring0[slot]) HIP_TRY(c, hipEventCreate(&c->ring0[slot]));
   if (!c->ring1[slot]) HIP_TRY(c, hipEventCreate(&c->ring1[slot]));
@@ -324,8 +336,8 @@ mrip_status mrip_set_shape(mrip_ctx ctx, uint32_t rpw, uint32_t wg) {
   if (rpw != 1 && ctx->model != MRIP_MM1)
     return inval(ctx, "reps_per_wave > 1 is only defined for the M/M/1 engine");
   if (rpw != 1 && ctx->split != 1) return inval(ctx, "a split replication needs reps_per_wave = 1");
-  ctx->rpw = rpw;
-  ctx->wg = wg;
+  ctx->rpw = ctx->plan_rpw = rpw;
+  ctx->wg = ctx->plan_wg = wg;
   return MRIP_OK;
 }
 
@@ -395,6 +407,8 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
                       "(replications x lanes per replication must stay below 2^32 - 1024)");
   hipStream_t s = (hipStream_t)hip_stream;
   mrip_status st = ensure_events(ctx);
+  if (st != MRIP_OK) return st;
+  st = order_after_last(ctx, s);
   if (st != MRIP_OK) return st;
   const uint32_t nout = scalar_outputs(ctx);
   // With the outputs in the context's buffers, the reduction runs on the
@@ -535,9 +549,10 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     ctx->set_pending[set] = true;
     ctx->next_set = set ^ 1u;
   }
+  st = mark_done(ctx, s);
+  if (st != MRIP_OK) return st;
   ctx->last = RUN_UNIFORM;
   ctx->last_n = n_reps;
-  ctx->last_stream = s;
   return MRIP_OK;
 }
 
@@ -685,6 +700,8 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
                                  uint32_t split, bool reduce) {
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
+  st = order_after_last(ctx, s);  // before the queue reset below
+  if (st != MRIP_OK) return st;
   st = claim_set(ctx, 0, s);
   if (st != MRIP_OK) return st;
   void *outp[mrip_ctx_s::MAX_OUT] = {};
@@ -740,8 +757,7 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
     st = commit_stats_slot(ctx, s);
     if (st != MRIP_OK) return st;
   }
-  ctx->last_stream = s;
-  return MRIP_OK;
+  return mark_done(ctx, s);
 }
 
 mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
@@ -750,7 +766,8 @@ mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
   if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
   const uint64_t n_long = count_long(ctx->lpt_customers, ctx->n_items, ctx->long_min);
   mrip_status st = run_plan_impl(ctx, seed, (hipStream_t)hip_stream, ctx->it_order.as<uint32_t>(),
-                                 ctx->n_items, n_long, ctx->rpw, ctx->wg, ctx->plan_split, true);
+                                 ctx->n_items, n_long, ctx->plan_rpw, ctx->plan_wg, ctx->plan_split,
+                                 true);
   if (st != MRIP_OK) return st;
   ctx->last = RUN_PLAN;
   ctx->last_n = ctx->n_items;
@@ -775,8 +792,10 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
       todo_n.push_back(ctx->lpt_customers[j]);
     }
   }
-  // a previous resume may still read the queue buffer
+  // an earlier plan run (on this stream or the last one) may still read the
+  // resume queue
   HIP_TRY(ctx, hipStreamSynchronize(s));
+  if (ctx->last_stream && ctx->last_stream != s) HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
   if (!todo.empty()) {
     HIP_TRY(ctx, ctx->resume_order.ensure(4 * todo.size()));
     HIP_TRY(ctx, hipMemcpy(ctx->resume_order.p, todo.data(), 4 * todo.size(),
@@ -784,7 +803,7 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
   }
   const uint64_t n_long = count_long(todo_n, todo.size(), ctx->long_min);
   mrip_status st = run_plan_impl(ctx, seed, s, ctx->resume_order.as<uint32_t>(), todo.size(),
-                                 n_long, ctx->rpw, ctx->wg, ctx->plan_split, true);
+                                 n_long, ctx->plan_rpw, ctx->plan_wg, ctx->plan_split, true);
   if (st != MRIP_OK) return st;
   ctx->last = RUN_PLAN;
   ctx->last_n = ctx->n_items;
@@ -848,6 +867,34 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
     for (uint64_t j = 0; j < n; ++j) lpt[j] = ctx->lpt_customers[(uint64_t)(j * stride)];
   }
   const uint64_t n_long = count_long(lpt, n, ctx->long_min);
+  // the cache named by MRIP_TUNE_CACHE: a stored shape for this kind of
+  // plan on this kind of GPU is installed without timing
+  const char *cache = std::getenv("MRIP_TUNE_CACHE");
+  char key[256] = {0};
+  bool use_cache = false;
+  if (cache && *cache) {
+    int dev = 0, cus = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(ctx, hipGetDevice(&dev));
+    HIP_TRY(ctx, hipGetDeviceProperties(&prop, dev));
+    HIP_TRY(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    use_cache = mrip_tune_key(ctx->model, ctx->mapping, n, n_long, lpt.empty() ? 0 : lpt[0],
+                              prop.gcnArchName, (uint32_t)cus, key, sizeof key) == MRIP_OK;
+    mrip_tune_entry e{};
+    if (use_cache && mrip_tune_cache_get(cache, key, &e) == MRIP_OK &&
+        (e.reps_per_wave == 1 || e.reps_per_wave == 2 || e.reps_per_wave == 4) &&
+        (e.workgroup == 64 || e.workgroup == 256 || e.workgroup == 1024) &&
+        (e.plan_split == 1 || e.plan_split == 2 || e.plan_split == 4 || e.plan_split == 8)) {
+      ctx->plan_rpw = e.reps_per_wave;
+      ctx->plan_wg = e.workgroup;
+      ctx->plan_split = e.plan_split;
+      if (best_rpw) *best_rpw = e.reps_per_wave;
+      if (best_wg)
+        *best_wg = (e.plan_split > 1 && n_long > 0) ? (e.plan_split == 8 ? 512u : 256u) : e.workgroup;
+      if (best_ms) *best_ms = e.ms;
+      return MRIP_OK;
+    }
+  }
   struct Shape { uint32_t rpw, wg, split; };
   std::vector<Shape> shapes;
   for (uint32_t r : {1u, 2u, 4u})
@@ -856,7 +903,7 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
     for (uint32_t r : {1u, 2u, 4u})
       for (uint32_t x : {2u, 4u, 8u}) shapes.push_back({r, 256u, x});
   float best = 1e30f;
-  uint32_t br = ctx->rpw, bw = ctx->wg, bx = ctx->plan_split;
+  uint32_t br = ctx->plan_rpw, bw = ctx->plan_wg, bx = ctx->plan_split;
   for (const Shape &sh : shapes) {
     float t_min = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {  // the first launch warms up
@@ -875,11 +922,17 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
     }
   }
   ctx->plan_split = bx;
-  ctx->rpw = br;
-  ctx->wg = bw;
+  ctx->plan_rpw = br;
+  ctx->plan_wg = bw;
   ctx->last = RUN_NONE;  // outputs of the timing runs are partial
+  if (use_cache) {
+    const mrip_tune_entry e{br, bw, bx, best};
+    (void)mrip_tune_cache_put(cache, key, &e);  // a cache that cannot be written is only slower
+  }
   if (best_rpw) *best_rpw = br;
-  if (best_wg) *best_wg = bw;
+  // the workgroup size actually launched: a split plan launches 256
+  // threads per workgroup for 2 or 4 wavefronts per item, 512 for 8
+  if (best_wg) *best_wg = (bx > 1 && n_long > 0) ? (bx == 8 ? 512u : 256u) : bw;
   if (best_ms) *best_ms = best;
   return MRIP_OK;
 }

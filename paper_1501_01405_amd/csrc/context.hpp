@@ -102,6 +102,9 @@ struct mrip_ctx_s {
   mrip_pi_params pi;
   uint32_t rpw = 1, wg = 256;
   uint32_t split = 1;  // wavefronts per M/M/1 replication in mrip_run
+  // the plans' shape: mrip_set_shape sets it with the runs' one, the
+  // autotuner alone (it never touches the runs' shape)
+  uint32_t plan_rpw = 1, plan_wg = 256;
   // plans: wavefronts per long item (1 = none) and what counts as long
   uint32_t plan_split = 8;
   uint64_t long_min = 65536;
@@ -140,7 +143,12 @@ struct mrip_ctx_s {
   uint64_t stats_runs = 0;               // reductions enqueued so far
   mrip::RunKind last = mrip::RUN_NONE;
   uint64_t last_n = 0;
+  // the stream of the last launching call, and an event recorded after
+  // everything that call enqueued on it (a call on another stream waits
+  // for it first)
   hipStream_t last_stream = nullptr;
+  hipEvent_t ev_done = nullptr;
+  bool done_pending = false;
   // event pairs of the last RING simulation-kernel launches (run history)
   static constexpr uint32_t RING = 256;
   hipEvent_t ring0[RING] = {}, ring1[RING] = {};
@@ -166,6 +174,7 @@ struct mrip_ctx_s {
     for (uint32_t i = 0; i < 2; ++i)
       if (ev_set_free[i]) (void)hipEventDestroy(ev_set_free[i]);
     if (red_stream) (void)hipStreamDestroy(red_stream);
+    if (ev_done) (void)hipEventDestroy(ev_done);
     for (uint32_t i = 0; i < RING; ++i) {
       if (ring0[i]) (void)hipEventDestroy(ring0[i]);
       if (ring1[i]) (void)hipEventDestroy(ring1[i]);

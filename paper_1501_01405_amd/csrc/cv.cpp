@@ -150,9 +150,9 @@ mrip_status run_items(mrip_ctx c, ItemBufs &b, uint64_t seed, uint64_t K, float 
   CV_TRY(c, launch_zero_u32(a.queue_head, 2, s));
   if (ms) CV_TRY(c, hipEventRecord(e0, s));
   if (c->plan_split > 1 && b.n_long > 0)
-    CV_TRY(c, launch_mm1_plan_split(a, b.count, b.n_long, c->plan_split, c->rpw, s));
+    CV_TRY(c, launch_mm1_plan_split(a, b.count, b.n_long, c->plan_split, c->plan_rpw, s));
   else
-    CV_TRY(c, launch_mm1_plan(a, b.count, c->rpw, c->wg, s));
+    CV_TRY(c, launch_mm1_plan(a, b.count, c->plan_rpw, c->plan_wg, s));
   if (ms) {
     CV_TRY(c, hipEventRecord(e1, s));
     CV_TRY(c, hipEventSynchronize(e1));

@@ -58,6 +58,11 @@ class mrip_plan_item(C.Structure):
                 ("lambda_", C.c_float), ("mu", C.c_float)]
 
 
+class mrip_tune_entry(C.Structure):
+    _fields_ = [("reps_per_wave", C.c_uint32), ("workgroup", C.c_uint32),
+                ("plan_split", C.c_uint32), ("ms", C.c_float)]
+
+
 class mrip_cv_hparams(C.Structure):
     _fields_ = [("size", C.c_uint32), ("epochs", C.c_uint32), ("batch", C.c_uint32),
                 ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
@@ -97,6 +102,9 @@ _SIGS = {
     "mrip_plan_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t)]),
     "mrip_autotune": (st, [ctx_t, u64, u64, vp, C.POINTER(u32), C.POINTER(u32),
                            C.POINTER(f32)]),
+    "mrip_tune_key": (st, [C.c_int, C.c_int, u64, u64, u64, C.c_char_p, u32, C.c_char_p, u64]),
+    "mrip_tune_cache_get": (st, [C.c_char_p, C.c_char_p, C.POINTER(mrip_tune_entry)]),
+    "mrip_tune_cache_put": (st, [C.c_char_p, C.c_char_p, C.POINTER(mrip_tune_entry)]),
     "mrip_mlp_forward": (st, [vp, vp, u64, vp, vp]),
     "mrip_mlp_grad": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
     "mrip_mlp_grad_noalloc": (st, [vp, vp, vp, vp, u64, vp, vp, vp]),
@@ -283,6 +291,28 @@ def mrip_autotune(ctx, seed, calib_items=0, stream=None):
     check(load().mrip_autotune(ctx, seed, calib_items, stream, C.byref(r), C.byref(w),
                                C.byref(ms)), ctx)
     return r.value, w.value, ms.value
+
+
+def mrip_tune_key(model, mapping, n_items, n_long, max_customers, arch, cus):
+    buf = C.create_string_buffer(256)
+    check(load().mrip_tune_key(model, mapping, n_items, n_long, max_customers, arch.encode(), cus,
+                               buf, len(buf)))
+    return buf.value.decode()
+
+
+def mrip_tune_cache_get(path, key):
+    """dict(reps_per_wave, workgroup, plan_split, ms), or None when absent."""
+    e = mrip_tune_entry()
+    s = load().mrip_tune_cache_get(str(path).encode(), key.encode(), C.byref(e))
+    if s == MRIP_E_STATE:
+        return None
+    check(s)
+    return {k: getattr(e, k) for k, _ in e._fields_}
+
+
+def mrip_tune_cache_put(path, key, reps_per_wave, workgroup, plan_split, ms):
+    e = mrip_tune_entry(reps_per_wave, workgroup, plan_split, ms)
+    check(load().mrip_tune_cache_put(str(path).encode(), key.encode(), C.byref(e)))
 
 
 def mrip_mlp_forward(theta, x, n, y, stream=None):

@@ -172,3 +172,32 @@ def test_c_example_is_built_and_checks_its_arguments():
     assert subprocess.run([exe], capture_output=True, timeout=60).returncode == 2
     r = subprocess.run([exe, "pi", "100", "4", "42", "warp"], capture_output=True, timeout=60)
     assert r.returncode == 2 and b"unknown mapping" in r.stderr
+
+
+def test_tune_cache_key_and_file_round_trip(tmp_path):
+    # the autotuner's cache on the host: keys bucket the plan by powers of
+    # two, entries survive a write and a read, the last put for a key wins,
+    # other keys are kept, and an absent file or key reads as absent
+    key = mrip.mrip_tune_key(mrip.MRIP_MM1, mrip.MRIP_MAP_WAVE, 2048, 70, 997000, "gfx950:sramecc+",
+                             256)
+    assert key == "m2/map2/n2^11/long2^6/max2^19/gfx950:sramecc+/256cu"
+    # same buckets, same key; another bucket, another key; the arch is one token
+    assert mrip.mrip_tune_key(2, 2, 3000, 100, 600000, "gfx950:sramecc+", 256) == key
+    assert mrip.mrip_tune_key(2, 2, 4096, 70, 997000, "gfx950:sramecc+", 256) != key
+    assert " " not in mrip.mrip_tune_key(2, 2, 1, 0, 1, "gfx 950/x", 8)
+    with pytest.raises(mrip.MripError):
+        mrip.mrip_tune_key(2, 2, 0, 0, 1, "gfx950", 256)
+    path = tmp_path / "tune.txt"
+    assert mrip.mrip_tune_cache_get(path, key) is None
+    mrip.mrip_tune_cache_put(path, key, 2, 256, 8, 0.612)
+    mrip.mrip_tune_cache_put(path, "other", 1, 64, 1, 1.5)
+    got = mrip.mrip_tune_cache_get(path, key)
+    assert got["reps_per_wave"] == 2 and got["workgroup"] == 256 and got["plan_split"] == 8
+    assert abs(got["ms"] - 0.612) < 1e-6
+    mrip.mrip_tune_cache_put(path, key, 4, 1024, 1, 0.5)
+    assert mrip.mrip_tune_cache_get(path, key)["reps_per_wave"] == 4
+    assert mrip.mrip_tune_cache_get(path, "other")["workgroup"] == 64
+    assert len(path.read_text().splitlines()) == 2
+    assert mrip.mrip_tune_cache_get(path, "absent") is None
+    with pytest.raises(mrip.MripError):
+        mrip.mrip_tune_cache_put(path, "has space", 1, 64, 1, 1.0)

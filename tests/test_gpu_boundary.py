@@ -123,6 +123,57 @@ def test_runs_on_two_streams_share_scratch_in_order(gpu):
     assert np.array_equal(got[1][ids], distinct)
 
 
+def test_plans_on_two_streams_run_in_order(gpu):
+    # the persistent plan kernel pops from the context's device queue: a
+    # plan enqueued on a second stream, with no host synchronisation, must
+    # not reset the queue under the first; and a run after a plan on a third
+    # stream waits for it too
+    announce("plans on two streams")
+    items = inputs.plan_table(n_dp=16, reps=16, n_lo=2000, n_hi=200000, seed=8)
+    s1, s2, s3 = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 100000), WAVE)
+    ctx.plan_set(items)
+    ref = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 100000), WAVE)
+    ref.plan_set(items)
+    ref.run_plan(seed=2)
+    want = [ref.output(o, n=len(items)).cpu().numpy() for o in range(3)]
+    want_stats = {int(d): ref.plan_stats(int(d)) for d in np.unique(items["dp"])}
+    for _ in range(3):
+        ctx.run_plan(seed=1, stream=s1.cuda_stream)
+        ctx.run_plan(seed=2, stream=s2.cuda_stream)
+        got = [ctx.output(o, n=len(items)).cpu().numpy() for o in range(3)]
+        for o in range(3):
+            assert np.array_equal(got[o], want[o]), o
+        for d, st in want_stats.items():
+            assert ctx.plan_stats(d) == st
+    # a plain run on a third stream right after a plan on the second
+    ctx.run_plan(seed=1, stream=s2.cuda_stream)
+    ctx.run(64, seed=5, stream=s3.cuda_stream)
+    ref1 = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 100000), WAVE)
+    ref1.run(64, seed=5)
+    assert np.array_equal(ctx.output(0).cpu().numpy(), ref1.output(0).cpu().numpy())
+
+
+def test_autotune_leaves_the_run_shape_alone(gpu):
+    # the tuner sets the plans' shape only: a split run context stays valid
+    announce("autotune and the run shape")
+    items = inputs.plan_table(n_dp=4, reps=8, n_lo=1000, n_hi=100000, seed=4)
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 20000), WAVE)
+    ctx.set_split(4)
+    ctx.plan_set(items)
+    ctx.set_plan_split(8, 50000)
+    rpw, wg, ms = ctx.autotune(42)
+    sh = ctx.shape()
+    assert sh["reps_per_wave"] == 1 and sh["split"] == 4
+    if sh["plan_split"] == 8:
+        assert wg == 512
+    elif sh["plan_split"] in (2, 4):
+        assert wg == 256
+    ctx.set_split(2)  # still accepted: reps_per_wave stayed 1
+    ctx.run(8, seed=1)
+    assert ctx.stats(0)["n"] == 8
+
+
 def test_kernel_times_of_self_timed_and_marked_launches(gpu):
     # the split M/M/1 launch records its timing events from its own
     # dispatch, the other launches between stream markers; a context that

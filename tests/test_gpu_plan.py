@@ -160,3 +160,29 @@ def test_plan_thread_form_item_equals_standalone_run(gpu, mapping):
     solo = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 5000), mapping)
     solo.run(40, seed=42)
     assert np.array_equal(got, solo.output(0).cpu().numpy())
+
+
+def test_autotune_cache_round_trip(gpu, tmp_path, monkeypatch):
+    # with MRIP_TUNE_CACHE set, the first tuning stores its winner and a
+    # second context with a plan of the same kind installs it untimed
+    items = inputs.plan_table(n_dp=8, reps=8, n_lo=1000, n_hi=50000, seed=6)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MRIP_TUNE_CACHE", str(path))
+    announce("autotune cache")
+    a = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 100000), WAVE)
+    a.plan_set(items)
+    a.set_plan_split(8, 20000)
+    first = a.autotune(42)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("m2/map2/")
+    b = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(0.9, 1.0, 100000), WAVE)
+    b.plan_set(items)
+    b.set_plan_split(8, 20000)
+    second = b.autotune(42)
+    assert second[0] == first[0] and second[1] == first[1]
+    assert abs(second[2] - first[2]) <= 1e-6 * first[2]  # the stored time, not a new one
+    assert b.shape()["plan_split"] == a.shape()["plan_split"]
+    b.run_plan(42)
+    a.run_plan(42)
+    assert np.array_equal(a.output(0, n=len(items)).cpu().numpy(),
+                          b.output(0, n=len(items)).cpu().numpy())
