@@ -88,7 +88,6 @@ mrip_status ensure_events(mrip_ctx c) {
     if (!c->ev_set_free[i])
       HIP_TRY(c, hipEventCreateWithFlags(&c->ev_set_free[i], hipEventDisableTiming));
   if (!c->red_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->red_stream, hipStreamNonBlocking));
-  if (!c->ev_done) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
   if (!c->stats_host) {
     const size_t bytes = sizeof(double) * mrip_ctx_s::STATS_RING * mrip_ctx_s::STATS_SLOT;
     HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, bytes, hipHostMallocMapped));
@@ -130,17 +129,25 @@ mrip_status commit_stats_slot(mrip_ctx c, hipStream_t s) {
 // Work enqueued on another stream than the last call's first waits, on the
 // device, for everything that call enqueued on its stream: the context's
 // buffers (device queue, scratch, outputs) serve one call at a time. Every
-// launching call makes this its first enqueue and ends with mark_done.
+// launching call makes this its first enqueue and ends with mark_done,
+// naming the last event it recorded on its stream (no extra packet between
+// consecutive runs on one stream).
 mrip_status order_after_last(mrip_ctx c, hipStream_t s) {
-  if (c->done_pending && s != c->last_stream) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_done, 0));
+  if (c->done_ev && s != c->last_stream) HIP_TRY(c, hipStreamWaitEvent(s, c->done_ev, 0));
   return MRIP_OK;
 }
 
-mrip_status mark_done(mrip_ctx c, hipStream_t s) {
-  HIP_TRY(c, hipEventRecord(c->ev_done, s));
-  c->done_pending = true;
+void mark_done(mrip_ctx c, hipStream_t s, hipEvent_t last_on_s) {
+  c->done_ev = last_on_s;
   c->last_stream = s;
-  return MRIP_OK;
+}
+
+// The last run-history and statistics events recorded.
+hipEvent_t last_ring_event(mrip_ctx c) {
+  return c->ring1[(c->launches - 1) % mrip_ctx_s::RING];
+}
+hipEvent_t last_stats_event(mrip_ctx c) {
+  return c->ev_stats[(c->stats_runs - 1) % mrip_ctx_s::STATS_RING];
 }
 
 // Events bracketing one simulation-kernel launch: the next slot of the
@@ -549,8 +556,9 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     ctx->set_pending[set] = true;
     ctx->next_set = set ^ 1u;
   }
-  st = mark_done(ctx, s);
-  if (st != MRIP_OK) return st;
+  // on s: the kernel's end, and after it the reduction unless that ran on
+  // the library's stream
+  mark_done(ctx, s, overlap ? last_ring_event(ctx) : last_stats_event(ctx));
   ctx->last = RUN_UNIFORM;
   ctx->last_n = n_reps;
   return MRIP_OK;
@@ -757,7 +765,8 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
     st = commit_stats_slot(ctx, s);
     if (st != MRIP_OK) return st;
   }
-  return mark_done(ctx, s);
+  mark_done(ctx, s, reduce ? last_stats_event(ctx) : last_ring_event(ctx));
+  return MRIP_OK;
 }
 
 mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {

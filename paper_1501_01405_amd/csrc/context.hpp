@@ -143,12 +143,11 @@ struct mrip_ctx_s {
   uint64_t stats_runs = 0;               // reductions enqueued so far
   mrip::RunKind last = mrip::RUN_NONE;
   uint64_t last_n = 0;
-  // the stream of the last launching call, and an event recorded after
-  // everything that call enqueued on it (a call on another stream waits
-  // for it first)
+  // the stream of the last launching call, and the last event that call
+  // recorded on it, after everything it enqueued there (a call on another
+  // stream waits for it first)
   hipStream_t last_stream = nullptr;
-  hipEvent_t ev_done = nullptr;
-  bool done_pending = false;
+  hipEvent_t done_ev = nullptr;
   // event pairs of the last RING simulation-kernel launches (run history)
   static constexpr uint32_t RING = 256;
   hipEvent_t ring0[RING] = {}, ring1[RING] = {};
@@ -174,7 +173,6 @@ struct mrip_ctx_s {
     for (uint32_t i = 0; i < 2; ++i)
       if (ev_set_free[i]) (void)hipEventDestroy(ev_set_free[i]);
     if (red_stream) (void)hipStreamDestroy(red_stream);
-    if (ev_done) (void)hipEventDestroy(ev_done);
     for (uint32_t i = 0; i < RING; ++i) {
       if (ring0[i]) (void)hipEventDestroy(ring0[i]);
       if (ring1[i]) (void)hipEventDestroy(ring1[i]);

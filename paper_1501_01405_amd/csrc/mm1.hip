@@ -71,7 +71,7 @@ __device__ __forceinline__ float pick4(int q, float v0, float v1, float v2, floa
 // Customers per lane per chunk (P / 2 Philox blocks). A segment of 16 lanes
 // takes 16 P consecutive customers; this fixes the association of the scan,
 // so it is the same for every launch shape.
-constexpr int MM1_P = 8;
+constexpr int MM1_P = 16;
 
 // The variates of one chunk for this lane: P customers from P/2 blocks.
 template <int P>
@@ -380,15 +380,6 @@ __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a)
   }
 }
 
-// The wavefront's replications in the form their prefix asks for (K is a
-// kernel argument: the branch is uniform over the grid).
-template <int RPW, class Src>
-__device__ __forceinline__ void wave_group_any(const Rep &d, Src &src, uint64_t K,
-                                               const Mm1Args &a) {
-  if (K > 0) wave_group<RPW, true>(d, src, K, a);
-  else wave_group<RPW, false>(d, src, 0, a);
-}
-
 __device__ __forceinline__ float neg_mean_ln2(float rate) {
   return (float)(-(1.0 / (double)rate) * 0.69314718055994530942);
 }
@@ -441,8 +432,15 @@ __device__ __forceinline__ Rep item_rep(const Mm1Args &a, uint64_t slot, uint64_
   return d;
 }
 
-template <int RPW>
-__global__ void mm1_wave_kernel(Mm1Args a, float ca, float cs) {
+// FT kernels (features and controls) launch at most 256 threads per
+// workgroup, which leaves them 256 VGPRs instead of 128.
+template <bool FT>
+constexpr int ft_max_wg() {
+  return FT ? 256 : 1024;
+}
+
+template <int RPW, bool FT>
+__global__ __launch_bounds__(ft_max_wg<FT>()) void mm1_wave_kernel(Mm1Args a, float ca, float cs) {
   constexpr int S = 4 / RPW;
   const int lane = threadIdx.x & 63;
   const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -452,7 +450,7 @@ __global__ void mm1_wave_kernel(Mm1Args a, float ca, float cs) {
   if (wave * RPW >= a.n_reps) return;  // whole wave idle (wave-uniform)
   const Rep d = uniform_rep(a, r, ca, cs);
   PhiloxSource src{k0, k1};
-  wave_group_any<RPW>(d, src, a.feature_prefix, a);
+  wave_group<RPW, FT>(d, src, a.feature_prefix, a);
 }
 
 // taus88 streams, WAVE mapping. The LPR lanes of a replication (16 or 32 of
@@ -654,8 +652,8 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
 // Persistent plan kernel: every wave pops units of RPW items (longest first)
 // until the queue is empty; the exit test is wave-uniform, so the grid always
 // drains.
-template <int RPW>
-__global__ void mm1_plan_kernel(Mm1Args a, uint64_t n_items) {
+template <int RPW, bool FT>
+__global__ __launch_bounds__(ft_max_wg<FT>()) void mm1_plan_kernel(Mm1Args a, uint64_t n_items) {
   constexpr int S = 4 / RPW;
   const int lane = threadIdx.x & 63;
   const int q = (lane >> 4) / S;
@@ -667,7 +665,7 @@ __global__ void mm1_plan_kernel(Mm1Args a, uint64_t n_items) {
     unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)unit, 0, 64));
     if (unit >= n_units) break;
     PhiloxSource src{k0, k1};
-    wave_group_any<RPW>(item_rep(a, (uint64_t)unit * RPW + q, n_items), src, a.feature_prefix, a);
+    wave_group<RPW, FT>(item_rep(a, (uint64_t)unit * RPW + q, n_items), src, a.feature_prefix, a);
   }
 }
 
@@ -772,7 +770,8 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
   __syncthreads();
 
   // phase 3: in order, only where the assumed start was not the true one
-#pragma unroll
+  // (kept rolled: one copy of the correction instead of X - 1)
+#pragma unroll 1
   for (int j = 1; j < X; ++j) {
     if (split && h == j &&
         __float_as_uint(sh.fin[slot][j - 1]) != __float_as_uint(sh.spec[slot][j - 1])) {
@@ -869,7 +868,7 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_split_kernel(Mm1Args a, flo
 // its issue slots when it shares a SIMD; then every wavefront serves the
 // rest RPW items at a time (queue_head[1]). Both exits are uniform (the
 // first per workgroup, the second per wavefront), so the grid drains.
-template <int X, int RPW>
+template <int X, int RPW, bool FT>
 __global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a, uint64_t n_items,
                                                                        uint64_t n_long) {
   constexpr int SLOTS = split_slots<X>();
@@ -889,8 +888,7 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a
     if (first >= n_long) break;
     const uint64_t idx = first + slot;
     const Rep d = item_rep(a, idx, idx < n_long ? n_long : 0);
-    if (a.feature_prefix > 0) split_replication<X, true>(d, slot, h, k0, k1, a.feature_prefix, a, sh);
-    else split_replication<X, false>(d, slot, h, k0, k1, 0, a, sh);
+    split_replication<X, FT>(d, slot, h, k0, k1, a.feature_prefix, a, sh);
   }
   __builtin_amdgcn_s_setprio(0);
   const int q = (lane >> 4) / S;
@@ -903,7 +901,7 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a
     if (unit >= n_units) break;
     const uint64_t j = (uint64_t)unit * RPW + q;
     PhiloxSource src{k0, k1};
-    wave_group_any<RPW>(item_rep(a, n_long + j, j < n_short ? n_items : 0), src, a.feature_prefix,
+    wave_group<RPW, FT>(item_rep(a, n_long + j, j < n_short ? n_items : 0), src, a.feature_prefix,
                         a);
   }
 }
@@ -1067,15 +1065,20 @@ hipError_t launch_mm1_taus(const Mm1Args &a_in, uint32_t lanes_per_rep, hipStrea
 
 hipError_t launch_mm1_wave(const Mm1Args &a_in, uint32_t rpw, uint32_t wg, hipStream_t s) {
   const Mm1Args a = centred(a_in);
+  if (a.feature_prefix > 0) wg = std::min<uint32_t>(wg, ft_max_wg<true>());
   const uint64_t waves = (a.n_reps + rpw - 1) / rpw;
   const uint32_t wpb = wg / 64;
   const uint64_t blocks = (waves + wpb - 1) / wpb;
   const float ca = host_neg_mean_ln2(a.lambda), cs = host_neg_mean_ln2(a.mu);
   const dim3 g((uint32_t)blocks), b(wg);
   if (a.rng == RNG_TAUS88) return launch_mm1_taus(a, 64 / rpw, s);
-  if (rpw == 1) hipLaunchKernelGGL(mm1_wave_kernel<1>, g, b, 0, s, a, ca, cs);
-  else if (rpw == 2) hipLaunchKernelGGL(mm1_wave_kernel<2>, g, b, 0, s, a, ca, cs);
-  else hipLaunchKernelGGL(mm1_wave_kernel<4>, g, b, 0, s, a, ca, cs);
+  const bool ft = a.feature_prefix > 0;
+  if (rpw == 1 && ft) hipLaunchKernelGGL((mm1_wave_kernel<1, true>), g, b, 0, s, a, ca, cs);
+  else if (rpw == 1) hipLaunchKernelGGL((mm1_wave_kernel<1, false>), g, b, 0, s, a, ca, cs);
+  else if (rpw == 2 && ft) hipLaunchKernelGGL((mm1_wave_kernel<2, true>), g, b, 0, s, a, ca, cs);
+  else if (rpw == 2) hipLaunchKernelGGL((mm1_wave_kernel<2, false>), g, b, 0, s, a, ca, cs);
+  else if (ft) hipLaunchKernelGGL((mm1_wave_kernel<4, true>), g, b, 0, s, a, ca, cs);
+  else hipLaunchKernelGGL((mm1_wave_kernel<4, false>), g, b, 0, s, a, ca, cs);
   return hipGetLastError();
 }
 
@@ -1150,14 +1153,19 @@ hipError_t launch_mm1_plan_simt(const Mm1Args &a_in, uint64_t n_items, bool one_
 hipError_t launch_mm1_plan(const Mm1Args &a_in, uint64_t n_items, uint32_t rpw, uint32_t wg,
                            hipStream_t s) {
   const Mm1Args a = centred(a_in);
+  if (a.feature_prefix > 0) wg = std::min<uint32_t>(wg, ft_max_wg<true>());
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const void *fn = rpw == 1 ? (const void *)mm1_plan_kernel<1>
-                 : rpw == 2 ? (const void *)mm1_plan_kernel<2>
-                            : (const void *)mm1_plan_kernel<4>;
+  const bool ft = a.feature_prefix > 0;
+  const void *fn = rpw == 1 ? (ft ? (const void *)mm1_plan_kernel<1, true>
+                                  : (const void *)mm1_plan_kernel<1, false>)
+                 : rpw == 2 ? (ft ? (const void *)mm1_plan_kernel<2, true>
+                                  : (const void *)mm1_plan_kernel<2, false>)
+                            : (ft ? (const void *)mm1_plan_kernel<4, true>
+                                  : (const void *)mm1_plan_kernel<4, false>);
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)wg, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
@@ -1167,9 +1175,9 @@ hipError_t launch_mm1_plan(const Mm1Args &a_in, uint64_t n_items, uint32_t rpw, 
   const uint64_t need = (units + wg / 64 - 1) / (wg / 64);
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
-  if (rpw == 1) hipLaunchKernelGGL(mm1_plan_kernel<1>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, n_items);
-  else if (rpw == 2) hipLaunchKernelGGL(mm1_plan_kernel<2>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, n_items);
-  else hipLaunchKernelGGL(mm1_plan_kernel<4>, dim3((uint32_t)blocks), dim3(wg), 0, s, a, n_items);
+  void *args[] = {(void *)&a, (void *)&n_items};
+  e = hipLaunchKernel(fn, dim3((uint32_t)blocks), dim3(wg), args, 0, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -1181,7 +1189,9 @@ hipError_t launch_mm1_plan_split(const Mm1Args &a_in, uint64_t n_items, uint64_t
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-#define MRIP_PICK(X, R) (const void *)mm1_plan_split_kernel<X, R>
+  const bool ft = a.feature_prefix > 0;
+#define MRIP_PICK(X, R) (ft ? (const void *)mm1_plan_split_kernel<X, R, true> \
+                            : (const void *)mm1_plan_split_kernel<X, R, false>)
 #define MRIP_PICK_X(X) (rpw == 1 ? MRIP_PICK(X, 1) : rpw == 2 ? MRIP_PICK(X, 2) : MRIP_PICK(X, 4))
   const void *fn = waves_per_rep == 2   ? MRIP_PICK_X(2)
                    : waves_per_rep == 4 ? MRIP_PICK_X(4)
