@@ -48,7 +48,11 @@ extern "C" {
 
 typedef struct mrip_ctx_s *mrip_ctx;
 
-typedef enum {
+/* The enumerated types are plain 32-bit integers at the boundary, so that
+ * any value a caller passes is one the library can receive and refuse
+ * (MRIP_E_INVAL) rather than an out-of-range enumeration. */
+typedef int32_t mrip_status;
+enum {
   MRIP_OK = 0,
   MRIP_E_INVAL = -1,       /* bad argument or parameter                       */
   MRIP_E_NOMEM = -2,       /* device or host allocation failed                */
@@ -56,9 +60,10 @@ typedef enum {
   MRIP_E_STATE = -4,       /* call out of order (e.g. stats before any run)   */
   MRIP_E_TOO_FEW = -5,     /* fewer than two replications for an interval     */
   MRIP_E_UNSUPPORTED = -6  /* valid request the library does not implement    */
-} mrip_status;
+};
 
-typedef enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3, MRIP_PI = 4 } mrip_model;
+typedef int32_t mrip_model;
+enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3, MRIP_PI = 4 };
 
 /* SIMT: one replication per lane (the paper's thread-level form, section
  * 3). WAVE: one replication per 64-lane wavefront with every lane working on
@@ -79,14 +84,11 @@ typedef enum { MRIP_RW = 1, MRIP_MM1 = 2, MRIP_FF = 3, MRIP_PI = 4 } mrip_model;
  * On TAUS88 streams: pi point i takes outputs 2i, 2i+1; M/M/1 customer n
  * takes 2n (A) and 2n+1 (S); walk move t of walker w takes bits 2(t&15) of
  * output w*ceil(steps/16) + (t>>4). */
-typedef enum { MRIP_RNG_PHILOX = 0, MRIP_RNG_TAUS88 = 1 } mrip_rng;
+typedef int32_t mrip_rng;
+enum { MRIP_RNG_PHILOX = 0, MRIP_RNG_TAUS88 = 1 };
 
-typedef enum {
-  MRIP_MAP_AUTO = 0,
-  MRIP_MAP_SIMT = 1,
-  MRIP_MAP_WAVE = 2,
-  MRIP_MAP_LANE0 = 3
-} mrip_mapping;
+typedef int32_t mrip_mapping;
+enum { MRIP_MAP_AUTO = 0, MRIP_MAP_SIMT = 1, MRIP_MAP_WAVE = 2, MRIP_MAP_LANE0 = 3 };
 
 /* Parameter structs: `size` must equal sizeof(the struct); they are copied
  * by mrip_create. */

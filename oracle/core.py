@@ -20,10 +20,11 @@ f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
 
 
 def lib():
-    """Load liboracle.so, compiling it first if it is missing or stale."""
+    """Load liboracle.so, compiling it first if it is missing or stale
+    (MRIP_ORACLE_LIB names another build of it, loaded as it is)."""
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
+        path = os.environ.get("MRIP_ORACLE_LIB") or _build.build(force=False)
         L = C.CDLL(path)
         L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.oracle_philox_batch.argtypes = [C.c_uint64, u32p, u32p, u32p]

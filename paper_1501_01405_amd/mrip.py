@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmrip.so")
+# MRIP_LIB names another build of the library (for example one with the
+# host code under sanitizers); the default is the in-tree build
+LIB_PATH = os.environ.get("MRIP_LIB") or os.path.join(_HERE, "libmrip.so")
 
 MRIP_OK, MRIP_E_INVAL, MRIP_E_NOMEM, MRIP_E_HIP, MRIP_E_STATE, MRIP_E_TOO_FEW, \
     MRIP_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
