@@ -89,11 +89,120 @@ __device__ __forceinline__ void walk16(uint32_t word, uint32_t g, uint32_t steps
   }
 }
 
+// (a << SH) + b and (a << SH) | b as one instruction each (the compiler
+// splits the shift of a sign-extended field into two otherwise).
+template <int SH>
+__device__ __forceinline__ uint32_t lshl_add(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "i"(SH), "v"(b));
+  return r;
+}
+template <int SH>
+__device__ __forceinline__ uint32_t lshl_or(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "i"(SH), "v"(b));
+  return r;
+}
+
+// The 16 moves of a word as sign-extended 2-bit dx and dy fields, so that a
+// move's components are one bit-field extract each: d = 0 (+x) -> dx 01,
+// 1 (-x) -> dx 11, 2 (+y) -> dy 01, 3 (-y) -> dy 11, 0 elsewhere.
+__device__ __forceinline__ void split_moves(uint32_t word, uint32_t &DX, uint32_t &DY) {
+  constexpr uint32_t M = 0x55555555u;
+  const uint32_t L = word & M, H = (word >> 1) & M;  // low and high bit of each field
+  DX = (H ^ M) | ((L & ~H) << 1);
+  DY = H | ((H & L) << 1);
+}
+
+// Mark `mask` in the LDS word at byte address `addr`.
+__device__ __forceinline__ void lds_or(uint32_t addr, uint32_t mask) {
+  typedef __attribute__((address_space(3))) uint32_t lds_u32;
+  __atomic_fetch_or((lds_u32 *)(uintptr_t)addr, mask, __ATOMIC_RELAXED);
+}
+
+// Up to 16 moves of every lane of a wavefront whose lanes are all walkers,
+// on a GRID >= 32 torus, marking a row-major LDS bitmap (GRID / 32 words
+// per row) at LDS byte address `base`. The walker keeps X and YB = Y *
+// GRID / 8, the byte offset of its row (both unwrapped): a site's word is at
+// base | (YB & rows) | ((X >> 3) & cols), its bit X & 31. Marks gather in
+// the lane's pending word (paddr, pmask) while the walker stays in that
+// word (an x move does, 31 times in 32) and reach LDS, as one or, when it
+// leaves: about half the moves need no LDS operation.
+template <int GRID>
+__device__ __forceinline__ void walk16_full(uint32_t word, uint32_t g, uint32_t steps, int &X,
+                                           int &YB, uint32_t base, uint32_t &paddr,
+                                           uint32_t &pmask) {
+  static_assert(GRID >= 32, "a row of the bitmap is at least one word");
+  constexpr int ROWB = GRID / 8;                           // bytes per row
+  constexpr int LOG_ROWB = GRID == 32 ? 2 : GRID == 64 ? 3 : 4;
+  constexpr uint32_t ROWS = (uint32_t)(GRID * ROWB - 1) & ~(uint32_t)(ROWB - 1);
+  constexpr uint32_t COLS = (uint32_t)(ROWB - 1) & ~3u;
+  constexpr int LOG_COLW = GRID == 128 ? 2 : 1;  // bits of the word index within a row
+  uint32_t DX, DY;
+  split_moves(word, DX, DY);
+  auto move = [&](int i) {
+    X += __builtin_amdgcn_sbfe((int)DX, 2 * i, 2);
+    YB = (int)lshl_add<LOG_ROWB>((uint32_t)__builtin_amdgcn_sbfe((int)DY, 2 * i, 2), (uint32_t)YB);
+    const uint32_t row = ((uint32_t)YB & ROWS) | base;
+    const uint32_t addr =
+        COLS ? lshl_or<2>(__builtin_amdgcn_ubfe((uint32_t)X, 5, LOG_COLW), row) : row;
+    if (addr != paddr) {
+      lds_or(paddr, pmask);
+      pmask = 0u;
+    }
+    paddr = addr;
+    pmask |= 1u << ((uint32_t)X & 31u);
+  };
+  if (g + 16u <= steps) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) move(i);
+  } else {
+    for (int i = 0; g + (uint32_t)i < steps; ++i) move(i);
+  }
+}
+
+// The walk of a wavefront whose 64 lanes are all walkers, on Philox
+// streams, in the lean form (GRID >= 32, no per-walker bitmaps); false when
+// the form does not apply and nothing was done.
+template <int GRID, bool PW>
+__device__ __forceinline__ bool lean_walk(const RwArgs &a, uint64_t r, uint32_t w, uint32_t k0,
+                                          uint32_t k1, uint32_t *bm, int &X, int &Y) {
+  if constexpr (GRID >= 32 && !PW) {
+    if (a.walkers != 64u) return false;
+    if (r < a.n_reps) {
+      constexpr int LOG_ROWB = GRID == 32 ? 2 : GRID == 64 ? 3 : 4;
+      // the bitmap's LDS byte address (a multiple of its size, so the
+      // site's offset can be or-ed into it)
+      typedef __attribute__((address_space(3))) uint32_t lds_u32;
+      const uint32_t base = (uint32_t)(uintptr_t)(lds_u32 *)bm;
+      int YB = Y << LOG_ROWB;
+      // the start site is the first pending mark
+      const int c0 = Y * GRID + X;
+      uint32_t paddr = base + 4u * ((uint32_t)c0 >> 5), pmask = 1u << (c0 & 31);
+      for (uint32_t g = 0; g < a.steps; g += 64) {
+        const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
+        walk16_full<GRID>(b.x, g, a.steps, X, YB, base, paddr, pmask);
+        walk16_full<GRID>(b.y, g + 16, a.steps, X, YB, base, paddr, pmask);
+        walk16_full<GRID>(b.z, g + 32, a.steps, X, YB, base, paddr, pmask);
+        walk16_full<GRID>(b.w, g + 48, a.steps, X, YB, base, paddr, pmask);
+      }
+      lds_or(paddr, pmask);
+      Y = YB >> LOG_ROWB;  // arithmetic shift: YB is Y times a power of two
+    }
+    return true;
+  } else {
+    (void)a, (void)r, (void)w, (void)k0, (void)k1, (void)bm, (void)X, (void)Y;
+    return false;
+  }
+}
+
 template <int GRID, int RNG, bool PW>
 __global__ void rw_wave_kernel(RwArgs a) {
   constexpr int WORDS = GRID * GRID / 32;
   constexpr int WB = PW ? WB_OWN : WB_NONE;
-  extern __shared__ uint32_t lds[];
+  // aligned to the largest bitmap (128 x 128 bits), so that each
+  // wavefront's bitmap address is a multiple of its size
+  extern __shared__ __attribute__((aligned(2048))) uint32_t lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t r = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -121,6 +230,8 @@ __global__ void rw_wave_kernel(RwArgs a) {
     taus_jump(t, a.taus_walk + (uint64_t)w * TAUS_COLS);  // to walker w's run
     for (uint32_t g = 0; g < a.steps; g += 16)
       walk16<GRID, true, WB>(taus_next(t), g, a.steps, active, X, Y, bm, spare, wb);
+  } else if (lean_walk<GRID, PW>(a, r, w, k0, k1, bm, X, Y)) {
+    // every lane a walker (or the whole wavefront idle): done in the lean form
   } else {
     for (uint32_t g = 0; g < a.steps; g += 64) {
       const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
