@@ -386,8 +386,9 @@ MRIP_API mrip_status mrip_tune_cache_put(const char *path, const char *key,
 #define MRIP_CV_COEFS 5       /* per row: the network's control h, then the 4 prefix controls */
 
 /* Forward pass of the 10-128-128-4 ReLU network, bf16 operands with fp32
- * accumulation. theta_dev: MRIP_MLP_PARAMS fp32; x_dev: n x 10 fp32
- * (normalised features); y_dev: n x 4 fp32, 16-byte aligned; n < 2^30.
+ * accumulation. theta_dev: MRIP_MLP_PARAMS fp32, 16-byte aligned; x_dev:
+ * n x 10 fp32 (normalised features); y_dev: n x 4 fp32, 16-byte aligned;
+ * n < 2^30.
  * Device pointers; MRIP_E_INVAL on a NULL or misaligned pointer. */
 MRIP_API mrip_status mrip_mlp_forward(const float *theta_dev, const float *x_dev, uint64_t n,
                              float *y_dev, void *hip_stream);
@@ -395,7 +396,8 @@ MRIP_API mrip_status mrip_mlp_forward(const float *theta_dev, const float *x_dev
 /* Gradient of mean((sum_k g_k(x) z_k - y)^2) over the n rows, with z_dev
  * n x 4 fp32 per-row multipliers (16-byte aligned), or NULL for z = (1, 0,
  * 0, 0) (the first output alone): grad_dev gets MRIP_MLP_PARAMS fp32
- * values, loss_dev one fp32 (nullable). n <= 65536. Synchronises. */
+ * values, loss_dev one fp32 (nullable). theta_dev 16-byte aligned (the
+ * weights are read as 16-byte vectors); n <= 65536. Synchronises. */
 MRIP_API mrip_status mrip_mlp_grad(const float *theta_dev, const float *x_dev, const float *z_dev,
                           const float *y_dev, uint64_t n, float *grad_dev, float *loss_dev,
                           void *hip_stream);
@@ -403,9 +405,10 @@ MRIP_API mrip_status mrip_mlp_grad(const float *theta_dev, const float *x_dev, c
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * gradient as mrip_mlp_grad, bit for bit, with its per-64-sample partial
- * rows in a fixed device array of the library (MRIP_MLP_GRAD_NOALLOC_MAX /
- * 64 rows of 18440 floats, about 4.7 MB, held by each GPU the library
- * runs on until the process ends) instead of an allocation. Calls no
+ * rows and its bf16 image of the weights in a fixed device array of the
+ * library (MRIP_MLP_GRAD_NOALLOC_MAX / 64 rows of 18440 floats and 82960
+ * bytes, about 4.8 MB, held by each GPU the library runs on until the
+ * process ends) instead of an allocation. Calls no
  * allocating routine and does not synchronise. n <= MRIP_MLP_GRAD_NOALLOC_MAX
  * (MRIP_E_INVAL beyond it); the other arguments as for mrip_mlp_grad. Every
  * call on one GPU shares that array: calls that overlap on one GPU (other

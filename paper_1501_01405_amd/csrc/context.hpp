@@ -57,6 +57,7 @@ struct ItemBufs {
 struct CvState {
   bool trained = false, applied = false;
   DevBuf theta, adam_m, adam_v, partial, loss_hist;
+  DevBuf image;  // the weights' bf16 image the gradient kernel stages (Adam keeps it current)
   DevBuf queue, norm, colstats, unit4;
   std::vector<float> mean, std_;  // feature mean / std of the training set
   // MRIP_CV_BETA_BINS rows of MRIP_CV_COEFS coefficients over [rho_lo, rho_hi]

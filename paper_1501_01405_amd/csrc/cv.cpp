@@ -209,6 +209,7 @@ mrip_status upload_coefs(mrip_ctx c) {
 
 std::mutex g_grad_mu;
 DevBuf g_grad_partial;  // partial-gradient rows for the context-free mrip_mlp_grad
+DevBuf g_grad_image;    // and its weights' image
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -219,7 +220,7 @@ extern "C" {
 mrip_status mrip_mlp_forward(const float *theta_dev, const float *x_dev, uint64_t n, float *y_dev,
                              void *hip_stream) {
   if (n > 0 && (!theta_dev || !x_dev || !y_dev)) return MRIP_E_INVAL;
-  if (n > 0 && !aligned16(y_dev)) return MRIP_E_INVAL;
+  if (n > 0 && (!aligned16(y_dev) || !aligned16(theta_dev))) return MRIP_E_INVAL;
   if (n >= (1ull << 30)) return MRIP_E_INVAL;  // 4 lanes per row: one launch < 2^32 lanes
   hipError_t e = launch_mlp_forward(theta_dev, x_dev, n, y_dev, (hipStream_t)hip_stream);
   return e == hipSuccess ? MRIP_OK : MRIP_E_HIP;
@@ -229,17 +230,20 @@ mrip_status mrip_mlp_grad(const float *theta_dev, const float *x_dev, const floa
                           const float *y_dev, uint64_t n, float *grad_dev, float *loss_dev,
                           void *hip_stream) {
   if (n == 0 || n > 65536 || !theta_dev || !x_dev || !y_dev || !grad_dev) return MRIP_E_INVAL;
-  if (z_dev && !aligned16(z_dev)) return MRIP_E_INVAL;
+  if (!aligned16(theta_dev) || (z_dev && !aligned16(z_dev))) return MRIP_E_INVAL;
   std::lock_guard<std::mutex> lock(g_grad_mu);
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t rows = mlp_partial_rows(n);
-  if (g_grad_partial.ensure(rows * MLP_PSTRIDE * sizeof(float)) != hipSuccess) return MRIP_E_NOMEM;
-  if (launch_mlp_grad(theta_dev, x_dev, z_dev, y_dev, n, g_grad_partial.as<float>(), s) !=
+  if (g_grad_partial.ensure(rows * MLP_PSTRIDE * sizeof(float)) != hipSuccess ||
+      g_grad_image.ensure(MLP_IMAGE_BYTES) != hipSuccess)
+    return MRIP_E_NOMEM;
+  if (launch_mlp_pack(theta_dev, g_grad_image.p, s) != hipSuccess) return MRIP_E_HIP;
+  if (launch_mlp_grad(g_grad_image.p, x_dev, z_dev, y_dev, n, g_grad_partial.as<float>(), s) !=
       hipSuccess)
     return MRIP_E_HIP;
   AdamArgs none{};
   if (launch_grad_reduce(g_grad_partial.as<float>(), (uint32_t)rows, n, grad_dev, loss_dev, nullptr,
-                         nullptr, nullptr, none, s) != hipSuccess)
+                         nullptr, nullptr, none, nullptr, s) != hipSuccess)
     return MRIP_E_HIP;
   // the shared partial buffer must not be reused before this call's kernels ran
   return hipStreamSynchronize(s) == hipSuccess ? MRIP_OK : MRIP_E_HIP;
@@ -376,6 +380,8 @@ mrip_status mrip_cv_train(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n,
   CV_TRY(ctx, hipMemcpy(cv.theta.p, theta0, 4 * MLP_NPARAMS, hipMemcpyHostToDevice));
   CV_TRY(ctx, hipMemsetAsync(cv.adam_m.p, 0, 4 * MLP_NPARAMS, s));
   CV_TRY(ctx, hipMemsetAsync(cv.adam_v.p, 0, 4 * MLP_NPARAMS, s));
+  CV_TRY(ctx, cv.image.ensure(MLP_IMAGE_BYTES));
+  CV_TRY(ctx, launch_mlp_pack(cv.theta.as<float>(), cv.image.p, s));
   const uint64_t batches = (n_fit + hp.batch - 1) / hp.batch;
   const uint64_t steps = batches * hp.epochs;
   CV_TRY(ctx, cv.loss_hist.ensure(4 * steps));
@@ -386,14 +392,15 @@ mrip_status mrip_cv_train(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n,
       const uint64_t r0 = b * hp.batch;
       const uint64_t nb = std::min<uint64_t>(hp.batch, n_fit - r0);
       ++step;
-      CV_TRY(ctx, launch_mlp_grad(cv.theta.as<float>(), cv.xn.as<float>() + r0 * 10,
+      CV_TRY(ctx, launch_mlp_grad(cv.image.p, cv.xn.as<float>() + r0 * 10,
                                   cv.zn.as<float>() + r0 * 4, cv.yn.as<float>() + r0, nb,
                                   cv.partial.as<float>(), s));
       CV_TRY(ctx, launch_grad_reduce(cv.partial.as<float>(), (uint32_t)mlp_partial_rows(nb), nb,
                                      nullptr, cv.loss_hist.as<float>() + (step - 1),
                                      cv.theta.as<float>(), cv.adam_m.as<float>(),
                                      cv.adam_v.as<float>(),
-                                     adam_args(hp.lr, hp.beta1, hp.beta2, hp.eps, step), s));
+                                     adam_args(hp.lr, hp.beta1, hp.beta2, hp.eps, step),
+                                     cv.image.p, s));
     }
   }
   CV_TRY(ctx, hipEventRecord(e1, s));

@@ -39,22 +39,38 @@ constexpr int SP = TS + 8;                       // padded row of the staging ar
 
 constexpr int DOUT = MLP_DOUT;
 
+// The weights as the products read them from LDS. b1 .. b3 are contiguous
+// fp32 in the order of the flat parameters (b2, W3 and b3 are one run there).
 struct FwdLds {
   __bf16 w2[H][H + 8];   // W2[h2][h1]
   __bf16 w1[H][32 + 8];  // W1[h][f], f >= 10 zero
-  float b1[H], b2[H], w3[DOUT][H];
+  float b1[H], b2[H], w3[DOUT][H], b3[DOUT];  // w3 bf16-rounded
 };
-
-struct BwdLds {
+// The gradient kernel's weights: FwdLds and W2^T, all in bf16 where a
+// product reads them. Kept in global memory in exactly this layout (the
+// training's Adam step rewrites it with the weights) and staged into LDS by
+// a flat 16-byte copy.
+struct MlpImage {
   FwdLds f;
   __bf16 w2t[H][H + 8];  // W2^T[h1][h2]
+};
+static_assert(sizeof(FwdLds) % 16 == 0 && sizeof(MlpImage) == MLP_IMAGE_BYTES,
+              "16-byte copies of the image");
+static_assert(offsetof(FwdLds, w3) == offsetof(FwdLds, b2) + 4 * H &&
+                  offsetof(FwdLds, b3) == offsetof(FwdLds, w3) + 4 * DOUT * H,
+              "b2, W3, b3 contiguous as in the flat parameters");
+
+struct BwdLds {
+  MlpImage m;            // m.f.w2 is reused for H2^T[h2][s] once the forward pass is done
   __bf16 h1t[H][SP];     // H1^T[h1][s]
   __bf16 dz2t[H][SP];    // dZ2^T[h2][s]
   __bf16 dz1t[H][SP];    // dZ1^T[h1][s]
   __bf16 xt[16][SP];     // X^T[f][s], f < 16
-  float red[2 + DOUT][4][H];  // per-wave sums of db1, db2, dW3[k]
-  float red_s[1 + DOUT][4];   // per-wave sums of loss and db3[k]
+  __bf16 dyt[DOUT][SP];  // dY^T[k][s]
+  float red[2][4][H];    // per-wave sums of db1, db2
+  float red_s[1 + DOUT][4];  // per-wave sums of loss and db3[k]
 };
+static_assert(sizeof(__bf16) * H * SP <= sizeof(__bf16) * H * (H + 8), "H2^T fits in W2's place");
 
 __device__ __forceinline__ __bf16 bf(float v) { return (__bf16)v; }
 __device__ __forceinline__ float bfr(float v) { return (float)(__bf16)v; }
@@ -71,24 +87,98 @@ __device__ __forceinline__ bf16x8 load_perm(const __bf16 *row, int j, int g) {
   return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
-// Stage W1, W2 (bf16), b1, b2, bf16-rounded W3 into LDS.
-__device__ void stage_weights(const float *theta, FwdLds &L, BwdLds *B) {
+// The image value of flat parameter p (bf16 where a product reads it).
+__device__ __forceinline__ void image_put(MlpImage &m, uint32_t p, float v) {
+  if (p < (uint32_t)MLP_OFF_B1) {
+    m.f.w1[p / DIN][p % DIN] = bf(v);
+  } else if (p < (uint32_t)MLP_OFF_W2) {
+    m.f.b1[p - MLP_OFF_B1] = v;
+  } else if (p < (uint32_t)MLP_OFF_B2) {
+    const uint32_t q = p - MLP_OFF_W2, r = q / H, c = q % H;
+    m.f.w2[r][c] = bf(v);
+    m.w2t[c][r] = bf(v);
+  } else if (p < (uint32_t)MLP_OFF_W3) {
+    m.f.b2[p - MLP_OFF_B2] = v;
+  } else if (p < (uint32_t)MLP_OFF_B3) {
+    const uint32_t q = p - MLP_OFF_W3;
+    m.f.w3[q / H][q % H] = bfr(v);
+  } else {
+    m.f.b3[p - MLP_OFF_B3] = v;
+  }
+}
+
+// Stage FwdLds from the flat fp32 parameters (16-byte aligned), 256
+// threads: every thread issues all of its 16-byte loads before its first
+// store.
+__device__ __forceinline__ void stage_theta(const float *__restrict__ theta, FwdLds &L) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < H * H; e += blockDim.x) {
-    const int r = e / H, c = e % H;
-    const __bf16 v = bf(theta[MLP_OFF_W2 + e]);
-    L.w2[r][c] = v;
-    if (B) B->w2t[c][r] = v;
+  const float4 *t4 = reinterpret_cast<const float4 *>(theta);
+  constexpr int W2V = H * H / 4 / 256;  // 16 vectors of W2 per thread
+  constexpr int W1V = H * DIN / 4;      // 320 vectors of W1
+  constexpr int TAILV = (H + DOUT * H + DOUT) / 4;  // b2, W3, b3: 161 vectors
+  static_assert(MLP_OFF_W2 % 4 == 0 && MLP_OFF_B1 % 4 == 0 && MLP_OFF_B2 % 4 == 0, "float4 runs");
+  float4 w2v[W2V];
+#pragma unroll
+  for (int k = 0; k < W2V; ++k) w2v[k] = t4[MLP_OFF_W2 / 4 + tid + 256 * k];
+  const float4 zero4 = {0.f, 0.f, 0.f, 0.f};
+  const float4 w1a = t4[MLP_OFF_W1 / 4 + tid];
+  const float4 w1b = tid + 256 < W1V ? t4[MLP_OFF_W1 / 4 + 256 + tid] : zero4;
+  const float4 b1v = tid < H / 4 ? t4[MLP_OFF_B1 / 4 + tid] : zero4;
+  const float4 tv = tid < TAILV ? t4[MLP_OFF_B2 / 4 + tid] : zero4;
+#pragma unroll
+  for (int k = 0; k < W2V; ++k) {
+    const int e = tid + 256 * k, r = e >> 5, c0 = 4 * (e & 31);
+    *(bf16x4 *)&L.w2[r][c0] = bf16x4{bf(w2v[k].x), bf(w2v[k].y), bf(w2v[k].z), bf(w2v[k].w)};
   }
-  for (int e = tid; e < H * 32; e += blockDim.x) {
-    const int r = e / 32, f = e % 32;
-    L.w1[r][f] = f < DIN ? bf(theta[MLP_OFF_W1 + r * DIN + f]) : bf(0.0f);
+  auto put_w1 = [&](int q, float4 v) {
+    const float f4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L.w1[(q + i) / DIN][(q + i) % DIN] = bf(f4[i]);
+  };
+  put_w1(4 * tid, w1a);
+  if (tid + 256 < W1V) put_w1(4 * (256 + tid), w1b);
+  {  // zero columns 10..31 of row tid/2: 10..15 by even threads, 16..31 by odd ones
+    const int r = tid >> 1;
+    if (tid & 1) {
+      *(uint4 *)&L.w1[r][16] = uint4{0u, 0u, 0u, 0u};
+      *(uint4 *)&L.w1[r][24] = uint4{0u, 0u, 0u, 0u};
+    } else {
+      *(uint32_t *)&L.w1[r][10] = 0u;
+      *(uint2 *)&L.w1[r][12] = uint2{0u, 0u};
+    }
   }
-  for (int e = tid; e < H; e += blockDim.x) {
-    L.b1[e] = theta[MLP_OFF_B1 + e];
-    L.b2[e] = theta[MLP_OFF_B2 + e];
+  if (tid < H / 4) *(float4 *)&L.b1[4 * tid] = b1v;
+  if (tid < TAILV) {
+    float4 v = tv;
+    if (tid >= H / 4 && tid < (H + DOUT * H) / 4) {  // W3 enters its product as bf16
+      v.x = bfr(v.x);
+      v.y = bfr(v.y);
+      v.z = bfr(v.z);
+      v.w = bfr(v.w);
+    }
+    reinterpret_cast<float4 *>(reinterpret_cast<char *>(&L) + offsetof(FwdLds, b2))[tid] = v;
   }
-  for (int e = tid; e < DOUT * H; e += blockDim.x) L.w3[e / H][e % H] = bfr(theta[MLP_OFF_W3 + e]);
+}
+
+// Flat copy of BYTES (a multiple of 16) from global memory into LDS, 256
+// threads, all loads of a thread issued before its first store.
+template <int BYTES>
+__device__ __forceinline__ void copy_to_lds(const void *__restrict__ src, void *dst) {
+  constexpr int V = BYTES / 16, PER = (V + 255) / 256;
+  const int tid = threadIdx.x;
+  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+  uint4 v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = tid + 256 * k;
+    v[k] = e < V ? s4[e] : uint4{0u, 0u, 0u, 0u};
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = tid + 256 * k;
+    if (e < V) d4[e] = v[k];
+  }
 }
 
 struct Out4 {
@@ -98,8 +188,7 @@ struct Out4 {
 // Forward pass of the wave's 16 samples. On return z1, z2 hold the
 // pre-activations of this lane's units (16t + 4g + i) for its sample, and
 // the return value is the four outputs for the sample of column l%16.
-__device__ Out4 forward_wave(const FwdLds &L, bf16x8 xb, const float *b3, float z1[8][4],
-                             float z2[8][4]) {
+__device__ Out4 forward_wave(const FwdLds &L, bf16x8 xb, float z1[8][4], float z2[8][4]) {
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
@@ -135,18 +224,30 @@ __device__ Out4 forward_wave(const FwdLds &L, bf16x8 xb, const float *b3, float 
         part = fmaf(L.w3[k][16 * t + 4 * g + i], bfr(fmaxf(z2[t][i], 0.0f)), part);
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);
-    o.v[k] = part + b3[k];
+    o.v[k] = part + L.b3[k];
   }
   return o;
 }
 
-__device__ __forceinline__ bf16x8 load_x(const float *x, uint64_t s, bool valid, int g) {
-  bf16x8 xb;
+// The features of sample s for k-slots 8g..8g+7 (zero beyond the 10th, and
+// for an invalid sample), optionally z-scored. Every load is issued
+// unconditionally from a clamped address, so that they are all in flight at
+// once.
+__device__ __forceinline__ bf16x8 load_x(const float *x, uint64_t s, bool valid, int g,
+                                         const float *mean = nullptr,
+                                         const float *inv_std = nullptr) {
+  float v[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int f = 8 * g + i;
-    xb[i] = bf((valid && f < DIN) ? x[s * DIN + f] : 0.0f);
+    const bool ok = valid && f < DIN;
+    v[i] = x[ok ? s * DIN + f : 0];
+    if (mean) v[i] = (v[i] - mean[ok ? f : 0]) * inv_std[ok ? f : 0];
+    v[i] = ok ? v[i] : 0.0f;
   }
+  bf16x8 xb;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) xb[i] = bf(v[i]);
   return xb;
 }
 
@@ -157,11 +258,11 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *theta, co
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const uint64_t s = (uint64_t)blockIdx.x * TS + 16 * w + c;
   const bool valid = s < n;
-  stage_weights(theta, L, nullptr);
   const bf16x8 xb = load_x(x, s, valid, g);
+  stage_theta(theta, L);
   __syncthreads();
   float z1[8][4], z2[8][4];
-  const Out4 yh = forward_wave(L, xb, theta + MLP_OFF_B3, z1, z2);
+  const Out4 yh = forward_wave(L, xb, z1, z2);
   if (g == 0 && valid) *(float4 *)(y + 4 * s) = float4{yh.v[0], yh.v[1], yh.v[2], yh.v[3]};
 }
 
@@ -178,16 +279,11 @@ __global__ __launch_bounds__(256) void cv_infer_kernel(const float *theta, const
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const uint64_t s = (uint64_t)blockIdx.x * TS + 16 * w + c;
   const bool valid = s < n;
-  stage_weights(theta, L, nullptr);
-  bf16x8 xb;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int f = 8 * g + i;
-    xb[i] = bf((valid && f < DIN) ? (x[s * DIN + f] - a.mean[f]) * a.inv_std[f] : 0.0f);
-  }
+  const bf16x8 xb = load_x(x, s, valid, g, a.mean, a.inv_std);
+  stage_theta(theta, L);
   __syncthreads();
   float z1[8][4], z2[8][4];
-  const Out4 o = forward_wave(L, xb, theta + MLP_OFF_B3, z1, z2);
+  const Out4 o = forward_wave(L, xb, z1, z2);
   if (g != 0 || !valid) return;
   if (a.g) *(float4 *)(a.g + 4 * s) = float4{o.v[0], o.v[1], o.v[2], o.v[3]};
   const double N = (double)a.customers[s];
@@ -205,10 +301,18 @@ __global__ __launch_bounds__(256) void cv_infer_kernel(const float *theta, const
   a.d[s] = (float)((double)a.y[s] - f);
 }
 
-// Sum over the 16 lanes of a row (same g, every sample column).
+// Sum over the 16 lanes of a row (same g, every sample column), on the
+// DPP network: pairs, quads, then rotations of the row by 4 and 8; every
+// lane of the row ends with the sum.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
 __device__ __forceinline__ float row16_sum(float v) {
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x124>(v);  // row_ror:4
+  v += dpp<0x128>(v);  // row_ror:8
   return v;
 }
 
@@ -216,19 +320,22 @@ __device__ __forceinline__ float row16_sum(float v) {
 // z = e_0): one partial row per workgroup (MLP_PSTRIDE floats: the
 // MLP_NPARAMS gradients, then the loss sum). The output gradient
 // dy_k = 2 (pred - y) z_k / n is formed in fp32 and enters the products as
-// bf16.
-__global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const float *x,
+// bf16. The weights come from their image (MlpImage).
+__global__ __launch_bounds__(256) void mlp_grad_kernel(const MlpImage *img, const float *x,
                                                        const float *z, const float *y, uint64_t n,
                                                        float inv_n, float *partial) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   BwdLds &B = *reinterpret_cast<BwdLds *>(smem);
-  FwdLds &L = B.f;
+  FwdLds &L = B.m.f;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
   const int sl = 16 * w + c;  // sample within the workgroup
   const uint64_t s = (uint64_t)blockIdx.x * TS + sl;
   const bool valid = s < n;
-  stage_weights(theta, L, &B);
+  const uint64_t sc = valid ? s : 0;  // a readable row for the unconditional loads
   const bf16x8 xb = load_x(x, s, valid, g);
+  const float4 zv = z ? *(const float4 *)(z + 4 * sc) : float4{1.0f, 0.0f, 0.0f, 0.0f};
+  const float yv = y[sc];
+  copy_to_lds<sizeof(MlpImage)>(img, &B.m);
   if (g < 2) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) B.xt[8 * g + i][sl] = xb[i];
@@ -236,19 +343,12 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
   __syncthreads();
 
   float z1[8][4], z2[8][4];
-  const Out4 yh = forward_wave(L, xb, theta + MLP_OFF_B3, z1, z2);
-  float zz[DOUT] = {1.0f, 0.0f, 0.0f, 0.0f};
-  if (z && valid) {
-    const float4 zv = *(const float4 *)(z + 4 * s);
-    zz[0] = zv.x;
-    zz[1] = zv.y;
-    zz[2] = zv.z;
-    zz[3] = zv.w;
-  }
+  const Out4 yh = forward_wave(L, xb, z1, z2);
+  const float zz[DOUT] = {zv.x, zv.y, zv.z, zv.w};
   float pred = 0.0f;
 #pragma unroll
   for (int k = 0; k < DOUT; ++k) pred = fmaf(yh.v[k], zz[k], pred);
-  const float err = valid ? pred - y[s] : 0.0f;
+  const float err = valid ? pred - yv : 0.0f;
   const float e2 = 2.0f * err * inv_n;
   float dy[DOUT], dyb[DOUT];
 #pragma unroll
@@ -257,8 +357,7 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
     dyb[k] = bfr(dy[k]);
   }
 
-  // last layer: dW3[k] partial sums over the wave's samples, and the ReLU of
-  // the second layer
+  // the ReLU of the second layer
   float dz2[8][4];
 #pragma unroll
   for (int t = 0; t < 8; ++t)
@@ -269,12 +368,6 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
 #pragma unroll
       for (int k = 0; k < DOUT; ++k) d = fmaf(L.w3[k][h], dyb[k], d);
       dz2[t][i] = z2[t][i] > 0.0f ? d : 0.0f;
-      const float h2 = bfr(fmaxf(z2[t][i], 0.0f));
-#pragma unroll
-      for (int k = 0; k < DOUT; ++k) {
-        const float v = row16_sum(dyb[k] * h2);
-        if (c == 0) B.red[2 + k][w][h] = v;
-      }
     }
   // dH1^T = W2^T . dZ2^T, then the ReLU of the first layer
   bf16x8 db[4];
@@ -290,21 +383,28 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
   for (int t = 0; t < 8; ++t) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc = mfma(load_perm(&B.w2t[16 * t + c][0], j, g), db[j], acc);
+    for (int j = 0; j < 4; ++j) acc = mfma(load_perm(&B.m.w2t[16 * t + c][0], j, g), db[j], acc);
 #pragma unroll
     for (int i = 0; i < 4; ++i) dz1[t][i] = z1[t][i] > 0.0f ? acc[i] : 0.0f;
   }
+  __syncthreads();  // every wave is past its forward pass: W2's place takes H2^T
 
-  // stage operands of the weight gradients ([unit][sample])
+  // stage the operands of the weight gradients ([unit][sample])
+  __bf16(*h2t)[SP] = reinterpret_cast<__bf16(*)[SP]>(&L.w2[0][0]);
 #pragma unroll
   for (int t = 0; t < 8; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int h = 16 * t + 4 * g + i;
       B.h1t[h][sl] = bf(fmaxf(z1[t][i], 0.0f));
+      h2t[h][sl] = bf(fmaxf(z2[t][i], 0.0f));
       B.dz2t[h][sl] = bf(dz2[t][i]);
       B.dz1t[h][sl] = bf(dz1[t][i]);
     }
+  if (g == 0) {
+#pragma unroll
+    for (int k = 0; k < DOUT; ++k) B.dyt[k][sl] = bf(dy[k]);
+  }
   // per-wave sums over samples of db1, db2, db3 and the loss
 #pragma unroll
   for (int t = 0; t < 8; ++t)
@@ -348,28 +448,36 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
         out[MLP_OFF_W2 + (16 * t2 + 4 * g + i) * H + 16 * t1 + c] = acc[i];
     }
   }
-  // dW1[h1][f] = sum_s dZ1^T[h1][s] X^T[f][s]: wave w owns h1 tiles 2w, 2w+1
+  // dW1[h1][f] = sum_s dZ1^T[h1][s] X^T[f][s] and
+  // dW3^T[h2][k] = sum_s H2^T[h2][s] dY^T[k][s]: wave w owns tiles 2w, 2w+1
+  const bf16x8 zero8 = {};
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) {
-    const int t1 = 2 * w + tt;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int t = 2 * w + tt;
+    f32x4 acc1 = {0.f, 0.f, 0.f, 0.f}, acc3 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const bf16x8 a = *(const bf16x8 *)&B.dz1t[16 * t1 + c][32 * j + 8 * g];
-      const bf16x8 b = *(const bf16x8 *)&B.xt[c][32 * j + 8 * g];
-      acc = mfma(a, b, acc);
+      const bf16x8 a1 = *(const bf16x8 *)&B.dz1t[16 * t + c][32 * j + 8 * g];
+      const bf16x8 b1 = *(const bf16x8 *)&B.xt[c][32 * j + 8 * g];
+      acc1 = mfma(a1, b1, acc1);
+      const bf16x8 a3 = *(const bf16x8 *)&h2t[16 * t + c][32 * j + 8 * g];
+      const bf16x8 b3 = c < DOUT ? *(const bf16x8 *)&B.dyt[c][32 * j + 8 * g] : zero8;
+      acc3 = mfma(a3, b3, acc3);
     }
     if (c < DIN) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out[MLP_OFF_W1 + (16 * t1 + 4 * g + i) * DIN + c] = acc[i];
+      for (int i = 0; i < 4; ++i) out[MLP_OFF_W1 + (16 * t + 4 * g + i) * DIN + c] = acc1[i];
+    }
+    if (c < DOUT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[MLP_OFF_W3 + c * H + 16 * t + 4 * g + i] = acc3[i];
     }
   }
-  // fixed-order sums of the four waves' rows: db1, db2, then dW3[k]
-  for (int e = tid; e < (2 + DOUT) * H; e += blockDim.x) {
+  // fixed-order sums of the four waves' rows: db1, db2
+  for (int e = tid; e < 2 * H; e += blockDim.x) {
     const int r = e / H, h = e % H;
     const float v = ((B.red[r][0][h] + B.red[r][1][h]) + B.red[r][2][h]) + B.red[r][3][h];
-    const int off = r == 0 ? MLP_OFF_B1 + h : r == 1 ? MLP_OFF_B2 + h : MLP_OFF_W3 + (r - 2) * H + h;
-    out[off] = v;
+    out[(r == 0 ? MLP_OFF_B1 : MLP_OFF_B2) + h] = v;
   }
   if (tid <= DOUT) {
     const float v = ((B.red_s[tid][0] + B.red_s[tid][1]) + B.red_s[tid][2]) + B.red_s[tid][3];
@@ -377,14 +485,44 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *theta, const
   }
 }
 
-// grad[p] = sum over workgroups of partial[wg][p] in a fixed order; the loss
-// slot becomes the mean squared error. With `adam` set, also one Adam step.
+// The image of the flat parameters: one thread per parameter, through the
+// same image_put the Adam step uses, then one per padding element (zero).
+__global__ void mlp_pack_kernel(const float *theta, MlpImage *img) {
+  constexpr uint32_t RP = 8, FP = 40 - DIN;  // padding per row of W2 / W2^T, of W1
+  constexpr uint32_t PADS = 2 * H * RP + H * FP;
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (uint32_t)MLP_NPARAMS) {
+    image_put(*img, e, theta[e]);
+    return;
+  }
+  const uint32_t q = e - MLP_NPARAMS;
+  if (q < H * RP)
+    img->f.w2[q / RP][H + q % RP] = bf(0.0f);
+  else if (q < 2 * H * RP)
+    img->w2t[(q - H * RP) / RP][H + (q - H * RP) % RP] = bf(0.0f);
+  else if (q < PADS)
+    img->f.w1[(q - 2 * H * RP) / FP][DIN + (q - 2 * H * RP) % FP] = bf(0.0f);
+}
+
+// grad[p] = sum over workgroups of partial[wg][p] in a fixed order (row 0
+// first; the loads of eight rows are issued together); the loss slot
+// becomes the mean squared error. With `theta` set, also one Adam step, and
+// with `img` set, the updated weights' image.
 __global__ void grad_reduce_kernel(const float *partial, uint32_t n_wg, float inv_n, float *grad,
-                                   float *loss, float *theta, float *m, float *v, AdamArgs ad) {
+                                   float *loss, float *theta, float *m, float *v, AdamArgs ad,
+                                   MlpImage *img) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > (uint32_t)MLP_NPARAMS) return;
   float s = 0.0f;
-  for (uint32_t k = 0; k < n_wg; ++k) s += partial[(uint64_t)k * MLP_PSTRIDE + p];
+  uint32_t k = 0;
+  for (; k + 8 <= n_wg; k += 8) {
+    float t[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) t[j] = partial[(uint64_t)(k + j) * MLP_PSTRIDE + p];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += t[j];
+  }
+  for (; k < n_wg; ++k) s += partial[(uint64_t)k * MLP_PSTRIDE + p];
   if (p == (uint32_t)MLP_NPARAMS) {
     if (loss) *loss = s * inv_n;
     return;
@@ -395,7 +533,9 @@ __global__ void grad_reduce_kernel(const float *partial, uint32_t n_wg, float in
     const float vv = ad.beta2 * v[p] + (1.0f - ad.beta2) * s * s;
     m[p] = mm;
     v[p] = vv;
-    theta[p] -= ad.lr * (mm / ad.bc1) / (sqrtf(vv / ad.bc2) + ad.eps);
+    const float nt = theta[p] - ad.lr * (mm / ad.bc1) / (sqrtf(vv / ad.bc2) + ad.eps);
+    theta[p] = nt;
+    if (img) image_put(*img, p, nt);
   }
 }
 
@@ -448,23 +588,30 @@ hipError_t launch_cv_infer(const float *theta, const float *x, uint64_t n, const
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const float *theta, const float *x, const float *z, const float *y,
+hipError_t launch_mlp_pack(const float *theta, void *img, hipStream_t s) {
+  constexpr uint32_t cells = MLP_NPARAMS + 2 * H * 8 + H * (40 - DIN);
+  hipLaunchKernelGGL(mlp_pack_kernel, dim3((cells + 255) / 256), dim3(256), 0, s, theta,
+                     (MlpImage *)img);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const void *img, const float *x, const float *z, const float *y,
                            uint64_t n, float *partial, hipStream_t s) {
   const size_t lds = sizeof(BwdLds);
   hipError_t e = allow_lds(mlp_grad_kernel, lds);
   if (e != hipSuccess) return e;
   const uint64_t blocks = (n + TS - 1) / TS;
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3((uint32_t)blocks), dim3(256), lds, s, theta, x, z, y,
-                     n, 1.0f / (float)n, partial);
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3((uint32_t)blocks), dim3(256), lds, s,
+                     (const MlpImage *)img, x, z, y, n, 1.0f / (float)n, partial);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_reduce(const float *partial, uint32_t n_wg, uint64_t n, float *grad,
                               float *loss, float *theta, float *m, float *v, const AdamArgs &ad,
-                              hipStream_t s) {
+                              void *img, hipStream_t s) {
   const uint32_t threads = 256, blocks = (MLP_NPARAMS + 1 + threads - 1) / threads;
   hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks), dim3(threads), 0, s, partial, n_wg,
-                     1.0f / (float)n, grad, loss, theta, m, v, ad);
+                     1.0f / (float)n, grad, loss, theta, m, v, ad, (MlpImage *)img);
   return hipGetLastError();
 }
 
@@ -489,7 +636,10 @@ constexpr uint64_t NOALLOC_MAX_N = MRIP_MLP_GRAD_NOALLOC_MAX;
 constexpr uint64_t NOALLOC_ROWS = NOALLOC_MAX_N / TS;
 static_assert(NOALLOC_MAX_N % TS == 0, "whole partial rows");
 
-__device__ __align__(256) float scratch[NOALLOC_ROWS * MLP_PSTRIDE];
+// the partial rows, then the weights' image
+constexpr uint64_t NOALLOC_IMAGE_OFF = NOALLOC_ROWS * MLP_PSTRIDE;  // floats
+static_assert(NOALLOC_IMAGE_OFF % 4 == 0 && MLP_IMAGE_BYTES % 4 == 0, "16-byte aligned image");
+__device__ __align__(256) float scratch[NOALLOC_IMAGE_OFF + MLP_IMAGE_BYTES / 4];
 
 constexpr int MAX_DEVICES = 64;
 std::mutex g_scratch_mu;
@@ -523,16 +673,19 @@ extern "C" MRIP_API mrip_status mrip_mlp_grad_noalloc(const float *theta_dev, co
   using namespace mrip;
   if (n == 0 || !theta_dev || !x_dev || !y_dev || !grad_dev) return MRIP_E_INVAL;
   if (n > NOALLOC_MAX_N) return MRIP_E_INVAL;  // beyond the scratch array
-  if (z_dev && ((uintptr_t)z_dev & 15u)) return MRIP_E_INVAL;
+  if (((uintptr_t)theta_dev & 15u) || (z_dev && ((uintptr_t)z_dev & 15u))) return MRIP_E_INVAL;
   float *part = nullptr;
   if (scratch_on_device(&part) != hipSuccess) return MRIP_E_HIP;
   hipStream_t s = (hipStream_t)hip_stream;
   const uint64_t rows = (n + TS - 1) / TS;
-  // every row the reduction reads is written first by the gradient kernel
-  if (launch_mlp_grad(theta_dev, x_dev, z_dev, y_dev, n, part, s) != hipSuccess) return MRIP_E_HIP;
+  float *img = part + NOALLOC_IMAGE_OFF;
+  // every element of the image and every row the reduction reads is
+  // written first, by the pack and the gradient kernels
+  if (launch_mlp_pack(theta_dev, img, s) != hipSuccess) return MRIP_E_HIP;
+  if (launch_mlp_grad(img, x_dev, z_dev, y_dev, n, part, s) != hipSuccess) return MRIP_E_HIP;
   AdamArgs none{};
   if (launch_grad_reduce(part, (uint32_t)rows, n, grad_dev, loss_dev, nullptr, nullptr, nullptr,
-                         none, s) != hipSuccess)
+                         none, nullptr, s) != hipSuccess)
     return MRIP_E_HIP;
   return MRIP_OK;
 }

@@ -2,6 +2,7 @@
 // launchers of mlp.hip.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace mrip {
@@ -16,6 +17,10 @@ constexpr int MLP_OFF_W3 = MLP_OFF_B2 + MLP_H;             // 17920
 constexpr int MLP_OFF_B3 = MLP_OFF_W3 + MLP_DOUT * MLP_H;  // 18432
 constexpr int MLP_NPARAMS = MLP_OFF_B3 + MLP_DOUT;         // 18436
 constexpr int MLP_PSTRIDE = 18440;  // partial-gradient row: params, loss, padding
+// Bytes of the weights' image the gradient kernel stages (bf16 W2, W1
+// padded to 32 features, fp32 b1, b2, bf16-rounded W3, b3, then bf16 W2^T,
+// rows padded to 136), 16-byte aligned.
+constexpr size_t MLP_IMAGE_BYTES = 82960;
 
 struct AdamArgs {
   float lr, beta1, beta2, eps;
@@ -25,6 +30,7 @@ struct AdamArgs {
 // rows of partial gradients mlp_grad writes for n samples (one per 64)
 size_t mlp_partial_rows(uint64_t n);
 
+// theta (16-byte aligned) everywhere below
 // y[4i..4i+3] = g(x_i), the network's four outputs
 hipError_t launch_mlp_forward(const float *theta, const float *x, uint64_t n, float *y,
                               hipStream_t s);
@@ -47,16 +53,19 @@ struct CvInferArgs {
 // d = y - coef[bin] . (h, z_4..z_7) with z the multipliers of the controls
 hipError_t launch_cv_infer(const float *theta, const float *x, uint64_t n, const CvInferArgs &a,
                            hipStream_t s);
-// Partial gradients of mean((sum_k g_k(x_i) z_ik - y_i)^2): one row per 64
-// samples. z: n x 4 per-sample multipliers, nullptr for z_i = e_0 (the first
-// output alone).
-hipError_t launch_mlp_grad(const float *theta, const float *x, const float *z, const float *y,
+// img (MLP_IMAGE_BYTES, 16-byte aligned) = the image of theta
+hipError_t launch_mlp_pack(const float *theta, void *img, hipStream_t s);
+// Partial gradients of mean((sum_k g_k(x_i) z_ik - y_i)^2) at the weights
+// whose image is img: one row per 64 samples. z: n x 4 per-sample
+// multipliers, nullptr for z_i = e_0 (the first output alone).
+hipError_t launch_mlp_grad(const void *img, const float *x, const float *z, const float *y,
                            uint64_t n, float *partial, hipStream_t s);
 // Fixed-order sum of the partial rows into grad / loss (either nullable);
-// with theta non-null, also one Adam step on theta, m, v.
+// with theta non-null, also one Adam step on theta, m, v, and with img
+// non-null the image of the updated theta.
 hipError_t launch_grad_reduce(const float *partial, uint32_t n_wg, uint64_t n, float *grad,
                               float *loss, float *theta, float *m, float *v, const AdamArgs &ad,
-                              hipStream_t s);
+                              void *img, hipStream_t s);
 hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint64_t n,
                        const AdamArgs &ad, hipStream_t s);
 

@@ -104,6 +104,16 @@ def test_misaligned_output_is_refused(gpu):
     y = torch.zeros(20, dtype=torch.float32, device="cuda")
     with pytest.raises(mrip.MripError):
         mrip.mrip_mlp_forward(theta, x, 4, y[1:], mrip.current_stream())
+    # the weights are read as 16-byte vectors
+    t1 = torch.zeros(mrip.MRIP_MLP_PARAMS + 4, dtype=torch.float32, device="cuda")[1:]
+    with pytest.raises(mrip.MripError):
+        mrip.mrip_mlp_forward(t1, x, 4, y[:16], mrip.current_stream())
+    grad = torch.zeros(mrip.MRIP_MLP_PARAMS, dtype=torch.float32, device="cuda")
+    yt = torch.zeros(4, dtype=torch.float32, device="cuda")
+    with pytest.raises(mrip.MripError):
+        mrip.mrip_mlp_grad(t1, x, None, yt, 4, grad, None, mrip.current_stream())
+    with pytest.raises(mrip.MripError):
+        mrip.mrip_mlp_grad_noalloc(t1, x, None, yt, 4, grad, None, mrip.current_stream())
 
 
 def test_adam_matches_oracle(gpu):
