@@ -26,7 +26,7 @@ SPLIT = 4  # wavefronts per replication (four per SIMD at 1024 replications)
 # WRITE_SIZE, each scaled by the same counter on a 256 MiB copy
 # (profiles/mm1_split_hbm_counters.md); to be re-measured (or set to None)
 # whenever the kernel changes.
-TRAFFIC_BYTES = (122.5 * 2.00 + 96.0 * 1.00) * 1024  # taken at SPLIT = 4
+TRAFFIC_BYTES = (169.0 * 2.00 + 96.0 * 1.00) * 1024  # taken at SPLIT = 4
 # Peak vector issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz, the rate
 # behind the published fp32 vector figure (157.3 TFLOP/s counts an FMA as 2).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9

@@ -26,7 +26,10 @@
     }                                                                             \
   } while (0)
 
-enum Op { MAD_U64, MUL_HI, MUL_LO, LOG, XOR, XOR3, ADD_F32, FMA_F32, ADD_U32, CVT_F32, FMA_F64 };
+enum Op {
+  MAD_U64, MUL_HI, MUL_LO, LOG, XOR, XOR3, ADD_F32, FMA_F32, ADD_U32, CVT_F32, FMA_F64,
+  BFE_I32, AND_OR, LSHL_OR, LSHL_ADD, LSHLREV
+};
 
 template <int OP>
 __global__ void rate_kernel(uint32_t *out, uint32_t seed) {
@@ -72,6 +75,16 @@ __global__ void rate_kernel(uint32_t *out, uint32_t seed) {
       } else if (OP == CVT_F32) {
         asm volatile("v_cvt_f32_u32 %0, %1" : "=v"(f[c]) : "v"(u[c]));
         u[c] += 1u;
+      } else if (OP == BFE_I32) {
+        asm volatile("v_bfe_i32 %0, %1, %2, 2" : "=v"(u[c]) : "v"(u[c]), "v"(k));
+      } else if (OP == AND_OR) {
+        asm volatile("v_and_or_b32 %0, %1, %2, %3" : "=v"(u[c]) : "v"(u[c]), "v"(k), "v"(c));
+      } else if (OP == LSHL_OR) {
+        asm volatile("v_lshl_or_b32 %0, %1, 2, %2" : "=v"(u[c]) : "v"(u[c]), "v"(k));
+      } else if (OP == LSHL_ADD) {
+        asm volatile("v_lshl_add_u32 %0, %1, 3, %2" : "=v"(u[c]) : "v"(u[c]), "v"(k));
+      } else if (OP == LSHLREV) {
+        asm volatile("v_lshlrev_b32 %0, %1, %2" : "=v"(u[c]) : "v"(k), "v"(u[c]));
       } else if (OP == FMA_F64) {
         asm volatile("v_fma_f64 %0, %1, %2, %3" : "=v"(d[c]) : "v"(d[c]), "v"((double)fk), "v"(d[c]));
       }
@@ -166,7 +179,9 @@ int main(int argc, char **argv) {
       {"v_xor_b32", measure<XOR>},         {"v_bitop3_b32(xor3)", measure<XOR3>},
       {"v_add_f32", measure<ADD_F32>},     {"v_fma_f32", measure<FMA_F32>},
       {"v_add_u32", measure<ADD_U32>},     {"v_cvt_f32_u32(+add)", measure<CVT_F32>},
-      {"v_fma_f64", measure<FMA_F64>},
+      {"v_fma_f64", measure<FMA_F64>},     {"v_bfe_i32", measure<BFE_I32>},
+      {"v_and_or_b32", measure<AND_OR>},   {"v_lshl_or_b32", measure<LSHL_OR>},
+      {"v_lshl_add_u32", measure<LSHL_ADD>}, {"v_lshlrev_b32", measure<LSHLREV>},
   };
   for (const Row &r : rows) {
     const Rate m = r.fn(out, blocks, threads);
