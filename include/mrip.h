@@ -310,6 +310,30 @@ MRIP_API mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream
 MRIP_API mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *skip_done,
                                           void *hip_stream);
 
+/* Stopping and resuming a plan (section 1: an experimental plan is a set
+ * of replication runs; a long one may be stopped and restarted). Every
+ * replication is a pure function of (seed, item), so recovery is running
+ * the items that did not finish.
+ *
+ * mrip_set_plan_limit: with max_items > 0, every later plan run
+ * (mrip_run_plan, mrip_run_plan_resume) stops after the first max_items
+ * items of its longest-first order, as a run interrupted there would: those
+ * items' outputs and done flags are written, the other items' are left as
+ * they were, and no statistics are computed (mrip_stats and
+ * mrip_plan_stats return MRIP_E_STATE until a run completes). For fault
+ * injection and for splitting a plan over several launches. 0 = no limit
+ * (the default). */
+MRIP_API mrip_status mrip_set_plan_limit(mrip_ctx ctx, uint64_t max_items);
+
+/* The per-item done flags of the last plan run, set by the device as each
+ * item's outputs are stored: done[i] = 1 if item i's outputs in the output
+ * buffers are final (run by that plan run, or flagged in the skip_done
+ * mask it resumed from), else 0. done: host array of n bytes, n = the
+ * plan's item count (MRIP_E_INVAL otherwise); MRIP_E_STATE before a plan
+ * run. Synchronises. The flags of a stopped run can be passed as skip_done
+ * to mrip_run_plan_resume. */
+MRIP_API mrip_status mrip_plan_done(mrip_ctx ctx, uint8_t *done, uint64_t n);
+
 /* Stats of output 0 (mean W) over the items of design point `dp` in the
  * last plan run. Synchronises. */
 MRIP_API mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_stats_t *out);

@@ -569,6 +569,8 @@ mrip_status mrip_stats_back(mrip_ctx ctx, uint32_t back, uint32_t output, double
   if (!ctx || !out) return MRIP_E_INVAL;
   if (!(confidence > 0.0 && confidence < 1.0)) return inval(ctx, "confidence must be in (0, 1)");
   if (ctx->last == RUN_NONE || ctx->stats_runs == 0) return (ctx->err = "no run yet"), MRIP_E_STATE;
+  if (ctx->last == RUN_PLAN_PARTIAL)
+    return (ctx->err = "the last plan run stopped at its item limit: no statistics"), MRIP_E_STATE;
   if (output >= scalar_outputs(ctx)) return inval(ctx, "no such scalar output");
   if (back >= mrip_ctx_s::STATS_RING || back >= ctx->stats_runs)
     return (ctx->err = "no statistics kept for that run"), MRIP_E_STATE;
@@ -703,13 +705,18 @@ static uint64_t count_long(const std::vector<uint64_t> &lpt, uint64_t n, uint64_
   return k;
 }
 
+// done (nullable): the per-item done flags the kernels set, cleared first
+// on the stream when clear_done is set.
 static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, const uint32_t *order,
                                  uint64_t n, uint64_t n_long, uint32_t rpw, uint32_t wg,
-                                 uint32_t split, bool reduce) {
+                                 uint32_t split, bool reduce, uint8_t *done = nullptr,
+                                 bool clear_done = false) {
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
   st = order_after_last(ctx, s);  // before the queue reset below
   if (st != MRIP_OK) return st;
+  if (done && clear_done)
+    HIP_TRY(ctx, launch_zero_u32((uint32_t *)done, (uint32_t)((ctx->n_items + 3) / 4), s));
   st = claim_set(ctx, 0, s);
   if (st != MRIP_OK) return st;
   void *outp[mrip_ctx_s::MAX_OUT] = {};
@@ -735,6 +742,7 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
   a.items.mu = ctx->it_mu.as<float>();
   a.items.order = order;
   a.queue_head = ctx->queue.as<uint32_t>();
+  a.done = done;
   a.mean_w = (float *)outp[0];
   a.mean_t = (float *)outp[1];
   a.mean_i = (float *)outp[2];
@@ -769,16 +777,31 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
   return MRIP_OK;
 }
 
+// The done flags, one byte per item (rounded up to whole words for the
+// clearing kernel).
+static mrip_status done_flags(mrip_ctx ctx, uint8_t **out) {
+  HIP_TRY(ctx, ctx->item_done.ensure((ctx->n_items + 3) / 4 * 4));
+  *out = ctx->item_done.as<uint8_t>();
+  return MRIP_OK;
+}
+
 mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
   if (!ctx) return MRIP_E_INVAL;
   if (philox_only(ctx) != MRIP_OK) return MRIP_E_UNSUPPORTED;
   if (ctx->n_items == 0) return (ctx->err = "no plan uploaded"), MRIP_E_STATE;
-  const uint64_t n_long = count_long(ctx->lpt_customers, ctx->n_items, ctx->long_min);
-  mrip_status st = run_plan_impl(ctx, seed, (hipStream_t)hip_stream, ctx->it_order.as<uint32_t>(),
-                                 ctx->n_items, n_long, ctx->plan_rpw, ctx->plan_wg, ctx->plan_split,
-                                 true);
+  // the item limit stops the run after a prefix of the longest-first order
+  const uint64_t n_run =
+      ctx->plan_limit ? std::min<uint64_t>(ctx->n_items, ctx->plan_limit) : ctx->n_items;
+  const uint64_t n_long =
+      std::min<uint64_t>(count_long(ctx->lpt_customers, ctx->n_items, ctx->long_min), n_run);
+  const bool whole = n_run == ctx->n_items;
+  uint8_t *done = nullptr;
+  mrip_status st = done_flags(ctx, &done);
   if (st != MRIP_OK) return st;
-  ctx->last = RUN_PLAN;
+  st = run_plan_impl(ctx, seed, (hipStream_t)hip_stream, ctx->it_order.as<uint32_t>(), n_run,
+                     n_long, ctx->plan_rpw, ctx->plan_wg, ctx->plan_split, whole, done, true);
+  if (st != MRIP_OK) return st;
+  ctx->last = whole ? RUN_PLAN : RUN_PLAN_PARTIAL;
   ctx->last_n = ctx->n_items;
   return MRIP_OK;
 }
@@ -801,8 +824,14 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
       todo_n.push_back(ctx->lpt_customers[j]);
     }
   }
+  // the item limit stops the run after a prefix of the remaining items
+  const bool whole = !ctx->plan_limit || todo.size() <= ctx->plan_limit;
+  if (!whole) {
+    todo.resize(ctx->plan_limit);
+    todo_n.resize(ctx->plan_limit);
+  }
   // an earlier plan run (on this stream or the last one) may still read the
-  // resume queue
+  // resume queue and the done flags
   HIP_TRY(ctx, hipStreamSynchronize(s));
   if (ctx->last_stream && ctx->last_stream != s) HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
   if (!todo.empty()) {
@@ -810,12 +839,35 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
     HIP_TRY(ctx, hipMemcpy(ctx->resume_order.p, todo.data(), 4 * todo.size(),
                            hipMemcpyHostToDevice));
   }
-  const uint64_t n_long = count_long(todo_n, todo.size(), ctx->long_min);
-  mrip_status st = run_plan_impl(ctx, seed, s, ctx->resume_order.as<uint32_t>(), todo.size(),
-                                 n_long, ctx->plan_rpw, ctx->plan_wg, ctx->plan_split, true);
+  // the items the caller reports done start flagged; the run flags the rest
+  uint8_t *done = nullptr;
+  mrip_status st = done_flags(ctx, &done);
   if (st != MRIP_OK) return st;
-  ctx->last = RUN_PLAN;
+  std::vector<uint8_t> flags(ctx->n_items);
+  for (uint64_t i = 0; i < ctx->n_items; ++i) flags[i] = skip_done[i] ? 1 : 0;
+  HIP_TRY(ctx, hipMemcpy(done, flags.data(), ctx->n_items, hipMemcpyHostToDevice));
+  const uint64_t n_long = count_long(todo_n, todo.size(), ctx->long_min);
+  st = run_plan_impl(ctx, seed, s, ctx->resume_order.as<uint32_t>(), todo.size(), n_long,
+                     ctx->plan_rpw, ctx->plan_wg, ctx->plan_split, whole, done, false);
+  if (st != MRIP_OK) return st;
+  ctx->last = whole ? RUN_PLAN : RUN_PLAN_PARTIAL;
   ctx->last_n = ctx->n_items;
+  return MRIP_OK;
+}
+
+mrip_status mrip_set_plan_limit(mrip_ctx ctx, uint64_t max_items) {
+  if (!ctx) return MRIP_E_INVAL;
+  ctx->plan_limit = max_items;
+  return MRIP_OK;
+}
+
+mrip_status mrip_plan_done(mrip_ctx ctx, uint8_t *done, uint64_t n) {
+  if (!ctx || !done) return MRIP_E_INVAL;
+  if (ctx->last != RUN_PLAN && ctx->last != RUN_PLAN_PARTIAL)
+    return (ctx->err = "no plan run yet"), MRIP_E_STATE;
+  if (n != ctx->n_items) return inval(ctx, "n must be the plan's item count");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  HIP_TRY(ctx, hipMemcpy(done, ctx->item_done.p, n, hipMemcpyDeviceToHost));
   return MRIP_OK;
 }
 
@@ -833,6 +885,8 @@ mrip_status mrip_bind_output(mrip_ctx ctx, uint32_t output, void *ptr_dev, uint6
 mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidence, mrip_stats_t *out) {
   if (!ctx || !out) return MRIP_E_INVAL;
   if (!(confidence > 0.0 && confidence < 1.0)) return inval(ctx, "confidence must be in (0, 1)");
+  if (ctx->last == RUN_PLAN_PARTIAL)
+    return (ctx->err = "the last plan run stopped at its item limit: no statistics"), MRIP_E_STATE;
   if (ctx->last != RUN_PLAN) return (ctx->err = "no plan run yet"), MRIP_E_STATE;
   auto it = std::lower_bound(ctx->dp_ids.begin(), ctx->dp_ids.end(), dp);
   if (it == ctx->dp_ids.end() || *it != dp) return inval(ctx, "no such design point");

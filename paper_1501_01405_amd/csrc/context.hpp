@@ -41,7 +41,9 @@ struct DevBuf {
   }
 };
 
-enum RunKind { RUN_NONE = 0, RUN_UNIFORM = 1, RUN_PLAN = 2 };
+// RUN_PLAN_PARTIAL: a plan run stopped by the item limit; its outputs and
+// done flags are readable, its statistics were not computed.
+enum RunKind { RUN_NONE = 0, RUN_UNIFORM = 1, RUN_PLAN = 2, RUN_PLAN_PARTIAL = 3 };
 
 // An item table on the device (structure of arrays) with its queue order
 // (longest first) and its grouping by design point (index + offsets).
@@ -160,6 +162,8 @@ struct mrip_ctx_s {
   std::vector<uint64_t> lpt_customers;  // customers in longest-first order
   std::vector<uint32_t> lpt_order;      // item indices in longest-first order
   mrip::DevBuf resume_order;            // the queue of a resumed plan
+  mrip::DevBuf item_done;               // per item: 1 once the last plan run wrote its outputs
+  uint64_t plan_limit = 0;              // plan runs stop after this many items (0 = none)
   mrip::DevBuf it_dp, it_rep, it_n, it_lambda, it_mu, it_order, queue, dp_index, dp_offsets,
       dp_stats;
   std::vector<uint32_t> dp_ids;

@@ -377,6 +377,7 @@ __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a)
 #pragma unroll
       for (int k = 0; k < 8; ++k) a.controls[d.out * 8 + k] = cl[k];
     }
+    if (a.done) a.done[d.out] = 1;
   }
 }
 
@@ -846,6 +847,7 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
         a.controls[d.out * 8 + 4 + k] = pcs[k];
       }
     }
+    if (a.done) a.done[d.out] = 1;
   }
 }
 
@@ -982,6 +984,7 @@ __device__ void simt_replication(const Rep &d, uint64_t K, uint32_t k0, uint32_t
 #pragma unroll
     for (int k = 0; k < 8; ++k) a.controls[d.out * 8 + k] = ctl[k].value();
   }
+  if (a.done) a.done[d.out] = 1;
 }
 
 // STRIDE = 1: one replication per lane. STRIDE = 64: one per wavefront with
@@ -1011,7 +1014,8 @@ __global__ void mm1_plan_simt_kernel(Mm1Args a, uint64_t n_items) {
 }
 
 __global__ void zero_u32_kernel(uint32_t *p, uint32_t n) {
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
 }
 
 float host_neg_mean_ln2(float rate) {
@@ -1210,7 +1214,8 @@ hipError_t launch_mm1_plan_split(const Mm1Args &a_in, uint64_t n_items, uint64_t
 }
 
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s) {
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, p, n);
+  const uint32_t blocks = n <= 64 ? 1u : std::min<uint32_t>(1024u, (n + 255u) / 256u);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks), dim3(n <= 64 ? 64 : 256), 0, s, p, n);
   return hipGetLastError();
 }
 

@@ -102,6 +102,8 @@ _SIGS = {
     "mrip_plan_set": (st, [ctx_t, vp, u64]),
     "mrip_run_plan": (st, [ctx_t, u64, vp]),
     "mrip_plan_stats": (st, [ctx_t, u32, f64, C.POINTER(mrip_stats_t)]),
+    "mrip_set_plan_limit": (st, [ctx_t, u64]),
+    "mrip_plan_done": (st, [ctx_t, vp, u64]),
     "mrip_autotune": (st, [ctx_t, u64, u64, vp, C.POINTER(u32), C.POINTER(u32),
                            C.POINTER(f32)]),
     "mrip_tune_key": (st, [C.c_int, C.c_int, u64, u64, u64, C.c_char_p, u32, C.c_char_p, u64]),
@@ -280,6 +282,16 @@ def mrip_run_plan_resume(ctx, seed, skip_done, stream=None):
     if skip_done is not None:
         skip = np.ascontiguousarray(skip_done, dtype=np.uint8)
     check(load().mrip_run_plan_resume(ctx, seed, _ptr(skip), stream), ctx)
+
+
+def mrip_set_plan_limit(ctx, max_items):
+    check(load().mrip_set_plan_limit(ctx, max_items), ctx)
+
+
+def mrip_plan_done(ctx, n):
+    out = np.zeros(n, np.uint8)
+    check(load().mrip_plan_done(ctx, out.ctypes.data, n), ctx)
+    return out
 
 
 def mrip_plan_stats(ctx, dp, confidence=0.95):
@@ -516,6 +528,12 @@ class Context:
 
     def plan_stats(self, dp, confidence=0.95):
         return mrip_plan_stats(self.ctx, dp, confidence)
+
+    def set_plan_limit(self, max_items):
+        mrip_set_plan_limit(self.ctx, max_items)
+
+    def plan_done(self):
+        return mrip_plan_done(self.ctx, self.n)
 
     def autotune(self, seed=42, calib_items=0):
         return mrip_autotune(self.ctx, seed, calib_items, current_stream())

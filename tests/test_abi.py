@@ -160,6 +160,11 @@ def test_bind_output_and_resume_checks():
     assert L.mrip_create(C.byref(ctx), mrip.MRIP_MM1, C.byref(mrip.mm1_params()), 0) == 0
     assert L.mrip_bind_output(ctx, 3, None, 0) == mrip.MRIP_OK  # features are output 3
     assert L.mrip_run_plan_resume(ctx, 42, None, None) == mrip.MRIP_E_STATE  # no plan
+    flags = (C.c_uint8 * 4)()
+    assert L.mrip_plan_done(ctx, flags, 4) == mrip.MRIP_E_STATE  # no plan run
+    assert L.mrip_plan_done(ctx, None, 4) == mrip.MRIP_E_INVAL
+    assert L.mrip_set_plan_limit(ctx, 3) == mrip.MRIP_OK
+    assert L.mrip_set_plan_limit(ctx, 0) == mrip.MRIP_OK
     L.mrip_destroy(ctx)
 
 

@@ -1,14 +1,18 @@
 """GPU tests of the boundary's caller-owned outputs and plan resume: a bound
 torch buffer receives exactly the outputs (and statistics) of an unbound
 run, and a plan resumed from saved outputs of its finished items gives the
-outputs and per-design-point statistics of an uninterrupted run; runs of one
-context on two streams are ordered on the device."""
+outputs and per-design-point statistics of an uninterrupted run; a plan
+stopped by its item limit has run exactly the items the oracle's plan runner
+runs, flags them done on the device, and resumes from those flags to the
+uninterrupted run; runs of one context on two streams are ordered on the
+device."""
 import numpy as np
 import pytest
 import torch
 
 from gpu_util import SIMT, WAVE, announce
 from oracle import core
+from oracle import plan as oplan
 from paper_1501_01405_amd import inputs, mrip
 
 pytestmark = pytest.mark.gpu
@@ -101,6 +105,58 @@ def test_resumed_plan_equals_uninterrupted_plan(gpu):
     # nothing done: the whole plan
     ctx.run_plan_resume(np.zeros(n, np.uint8), seed=9)
     assert np.array_equal(bufs[0].cpu().numpy(), want[0])
+
+
+def _tuples(items):
+    return [(int(r["dp"]), int(r["rep"]), int(r["customers"]), float(r["lambda_"]),
+             float(r["mu"])) for r in items]
+
+
+@pytest.mark.parametrize("mapping,limit,split", [(WAVE, 5, 8), (WAVE, 40, 8), (WAVE, 40, 1),
+                                                 (SIMT, 7, 8)])
+def test_plan_stopped_at_its_item_limit_resumes_to_the_uninterrupted_plan(gpu, mapping, limit,
+                                                                          split):
+    announce("plan item limit", mapping, limit, split)
+    items = _plan()
+    n = len(items)
+    full = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), mapping)
+    full.set_plan_split(split)
+    full.plan_set(items)
+    full.run_plan(seed=9)
+    assert np.all(full.plan_done() == 1)
+    want = [full.output(o).cpu().numpy() for o in range(3)]
+    dps = sorted(set(items["dp"].tolist()))
+    want_stats = {dp: full.plan_stats(dp) for dp in dps}
+
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), mapping)
+    ctx.set_plan_split(split)
+    ctx.plan_set(items)
+    ctx.set_plan_limit(limit)
+    ctx.run_plan(seed=9)
+    done = ctx.plan_done()
+    ref_out, ref_done = oplan.plan_run(9, _tuples(items), max_items=limit, threads=8)
+    assert np.array_equal(done, ref_done)  # the `limit` longest items, nothing else
+    run = done == 1
+    got = ctx.output(0).cpu().numpy()
+    assert np.array_equal(got[run], want[0][run])
+    assert np.max(np.abs(got[run] - ref_out[run, 0]) / np.abs(ref_out[run, 0])) <= 1e-5
+    with pytest.raises(mrip.MripError):  # a stopped run has no statistics
+        ctx.plan_stats(dps[0])
+    # resumed under the same limit: stops again after `limit` more items
+    ctx.run_plan_resume(done, seed=9)
+    done2 = ctx.plan_done()
+    _, ref_done2 = oplan.plan_run(9, _tuples(items), max_items=limit, skip_done=ref_done,
+                                  prev=ref_out)
+    assert np.array_equal(done2, ref_done2)
+    # then finished without the limit
+    ctx.set_plan_limit(0)
+    ctx.run_plan_resume(done2, seed=9)
+    assert np.all(ctx.plan_done() == 1)
+    for o in range(3):
+        assert np.array_equal(ctx.output(o).cpu().numpy(), want[o])
+    for dp in dps:
+        assert ctx.plan_stats(dp) == want_stats[dp]
+    assert n > 2 * limit
 
 
 def test_runs_on_two_streams_share_scratch_in_order(gpu):
