@@ -233,7 +233,14 @@ MRIP_API mrip_status mrip_set_rng(mrip_ctx ctx, mrip_rng rng);
  * n_reps times the lanes of a replication (1 in SIMT; 64 in LANE0 and
  * WAVE, 64 / reps_per_wave with mrip_set_shape, 64 x waves_per_rep with
  * mrip_set_split) must stay below 2^32 - 1024, else MRIP_E_INVAL (about
- * 67 million replications per call in WAVE). */
+ * 67 million replications per call in WAVE). In the split M/M/1 form
+ * (WAVE, 2 or 4 wavefronts per replication, Philox, no feature prefix,
+ * outputs not bound) the reduction is deferred: the next such run on the
+ * same stream computes it in one extra workgroup of its own kernel, so
+ * consecutive runs have no event or extra launch between their kernels;
+ * asking for the statistics (mrip_stats, mrip_stats_back) or any other
+ * launching call computes a reduction still pending. The statistics are
+ * the same either way. */
 MRIP_API mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_stream);
 
 /* Mean, unbiased variance and Student-t interval of output `output` of the
@@ -270,11 +277,18 @@ MRIP_API mrip_status mrip_bind_output(mrip_ctx ctx, uint32_t output, void *ptr_d
  * run or mrip_destroy); for zero-copy readers on the same stream. */
 MRIP_API mrip_status mrip_output_ptr(mrip_ctx ctx, uint32_t output, const void **ptr_dev);
 
-/* Milliseconds of the last run's simulation kernel (hipEvents around the
- * launch on its stream). Synchronises. */
+/* Time one simulation launch of the deferred split M/M/1 form in `every`
+ * (1 = every launch, the default; 0 = none) with the HIP events its
+ * dispatch records; the other forms time every launch. Each timed launch
+ * costs a dispatch gap before the next kernel (about 9 us on MI355X), so a
+ * pipelined loop of short runs times a sample. Restarts the count. */
+MRIP_API mrip_status mrip_set_timing(mrip_ctx ctx, uint32_t every);
+
+/* Milliseconds of the last timed simulation kernel (hipEvents around the
+ * launch on its stream; MRIP_E_STATE if none). Synchronises. */
 MRIP_API mrip_status mrip_last_run_ms(mrip_ctx ctx, float *ms);
 
-/* Kernel milliseconds of the last min(max_n, launches, 256) simulation
+/* Kernel milliseconds of the last min(max_n, launches, 256) timed simulation
  * launches of this context (mrip_run, mrip_run_plan, autotune), oldest
  * first, into ms[0..*n_out). Synchronises on those launches. */
 MRIP_API mrip_status mrip_run_history_ms(mrip_ctx ctx, float *ms, uint32_t max_n,

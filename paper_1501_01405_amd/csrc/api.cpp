@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mrip.h"
@@ -93,6 +94,13 @@ mrip_status ensure_events(mrip_ctx c) {
     HIP_TRY(c, hipHostMalloc((void **)&c->stats_host, bytes, hipHostMallocMapped));
     HIP_TRY(c, hipHostGetDevicePointer((void **)&c->stats_view, c->stats_host, 0));
   }
+  if (!c->seq_host) {
+    HIP_TRY(c, hipHostMalloc((void **)&c->seq_host, sizeof(uint64_t) * mrip_ctx_s::STATS_RING,
+                             hipHostMallocMapped));
+    for (uint32_t i = 0; i < mrip_ctx_s::STATS_RING; ++i) c->seq_host[i] = 0;
+    HIP_TRY(c, hipHostGetDevicePointer((void **)&c->seq_view, c->seq_host, 0));
+  }
+  if (!c->switch_ev) HIP_TRY(c, hipEventCreateWithFlags(&c->switch_ev, hipEventDisableTiming));
   return MRIP_OK;
 }
 
@@ -122,6 +130,7 @@ mrip_status claim_set(mrip_ctx c, uint32_t set, hipStream_t s) {
 mrip_status commit_stats_slot(mrip_ctx c, hipStream_t s) {
   const uint32_t slot = (uint32_t)(c->stats_runs % mrip_ctx_s::STATS_RING);
   HIP_TRY(c, hipEventRecord(c->ev_stats[slot], s));
+  c->slot_by_seq[slot] = false;
   ++c->stats_runs;
   return MRIP_OK;
 }
@@ -133,13 +142,70 @@ mrip_status commit_stats_slot(mrip_ctx c, hipStream_t s) {
 // naming the last event it recorded on its stream (no extra packet between
 // consecutive runs on one stream).
 mrip_status order_after_last(mrip_ctx c, hipStream_t s) {
-  if (c->done_ev && s != c->last_stream) HIP_TRY(c, hipStreamWaitEvent(s, c->done_ev, 0));
+  if (s == c->last_stream) return MRIP_OK;
+  if (c->last_unmarked) {
+    // everything enqueued on last_stream so far
+    HIP_TRY(c, hipEventRecord(c->switch_ev, c->last_stream));
+    HIP_TRY(c, hipStreamWaitEvent(s, c->switch_ev, 0));
+  } else if (c->done_ev) {
+    HIP_TRY(c, hipStreamWaitEvent(s, c->done_ev, 0));
+  }
   return MRIP_OK;
 }
 
 void mark_done(mrip_ctx c, hipStream_t s, hipEvent_t last_on_s) {
   c->done_ev = last_on_s;
   c->last_stream = s;
+  c->last_unmarked = false;
+}
+
+// The call enqueued work on s after its last event (or recorded none).
+void mark_unmarked(mrip_ctx c, hipStream_t s) {
+  c->done_ev = nullptr;
+  c->last_stream = s;
+  c->last_unmarked = true;
+}
+
+// Launch the deferred reduction of the last uniform run on its stream (no
+// later run of the same form on that stream will carry it) and signal its
+// statistics slot by event, as a run that reduces at once does.
+mrip_status flush_pending(mrip_ctx c) {
+  if (!c->pend.active) return MRIP_OK;
+  const mrip_ctx_s::Pending p = c->pend;
+  c->pend.active = false;
+  ReduceSet rs{};
+  for (uint32_t o = 0; o < 3; ++o) {
+    rs.x[o] = c->out[p.set][o].p;
+    rs.dtype[o] = 1;
+  }
+  const uint32_t slot = (uint32_t)(p.stats_index % mrip_ctx_s::STATS_RING);
+  HIP_TRY(c, launch_reduce_f64_multi(rs, 3, p.n,
+                                     c->stats_view + (size_t)slot * mrip_ctx_s::STATS_SLOT, p.stream));
+  HIP_TRY(c, hipEventRecord(c->ev_stats[slot], p.stream));
+  c->slot_by_seq[slot] = false;
+  // the pending run was the last call's (any call flushes before its own work)
+  mark_done(c, p.stream, c->ev_stats[slot]);
+  return MRIP_OK;
+}
+
+// Wait for the statistics a kernel publishes by sequence number: poll the
+// slot's number in pinned memory; a stream that has drained without
+// publishing it, or reports an error, ends the wait with an error.
+mrip_status wait_seq(mrip_ctx c, uint32_t slot, uint64_t value) {
+  for (uint32_t spin = 1;; ++spin) {
+    if (__atomic_load_n(c->seq_host + slot, __ATOMIC_ACQUIRE) >= value) return MRIP_OK;
+    if ((spin & 255) == 0) {
+      const hipError_t q = hipStreamQuery(c->seq_stream[slot]);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(c->seq_host + slot, __ATOMIC_ACQUIRE) >= value) return MRIP_OK;
+        c->err = "a run's statistics were not published";
+        return MRIP_E_HIP;
+      }
+      if (q != hipErrorNotReady) return hip_fail(c, q, "hipStreamQuery");
+      (void)hipGetLastError();  // "not ready" is an answer, not a failure to keep
+      std::this_thread::yield();
+    }
+  }
 }
 
 // The last run-history and statistics events recorded.
@@ -178,6 +244,7 @@ mrip_status record_end(mrip_ctx c, hipStream_t s, bool markers = true) {
 
 // Kernel milliseconds of the context's last simulation launch.
 mrip_status last_launch_ms(mrip_ctx c, float *ms) {
+  if (c->launches == 0) return (c->err = "no timed launch yet"), MRIP_E_STATE;
   const uint32_t slot = (uint32_t)((c->launches - 1) % mrip_ctx_s::RING);
   HIP_TRY(c, hipEventSynchronize(c->ring1[slot]));
   HIP_TRY(c, hipEventElapsedTime(ms, c->ring0[slot], c->ring1[slot]));
@@ -415,14 +482,27 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
   hipStream_t s = (hipStream_t)hip_stream;
   mrip_status st = ensure_events(ctx);
   if (st != MRIP_OK) return st;
-  st = order_after_last(ctx, s);
-  if (st != MRIP_OK) return st;
   const uint32_t nout = scalar_outputs(ctx);
   // With the outputs in the context's buffers, the reduction runs on the
   // library's own stream, so the next run's simulation need not wait for
   // it: runs alternate between two output sets.
   bool overlap = true;
   for (uint32_t o = 0; o < mrip_ctx_s::MAX_OUT; ++o) overlap = overlap && !ctx->bound[o].p;
+  const bool wave = ctx->mapping == MRIP_MAP_WAVE;
+  // the headline form, one kernel per run, times itself
+  const bool self_timed = kSelfTimedLaunch && ctx->model == MRIP_MM1 && wave && ctx->split > 1 &&
+                          ctx->rng == MRIP_RNG_PHILOX;
+  // ... and leaves its statistics to the next run of the same form on the
+  // same stream, whose kernel reduces them in one extra workgroup: no event
+  // or reduction launch between consecutive simulation kernels
+  const bool deferred = self_timed && overlap && ctx->mm1.feature_prefix == 0 &&
+                        (ctx->split == 2 || ctx->split == 4);
+  if (ctx->pend.active && !(deferred && ctx->pend.stream == s)) {
+    st = flush_pending(ctx);
+    if (st != MRIP_OK) return st;
+  }
+  st = order_after_last(ctx, s);
+  if (st != MRIP_OK) return st;
   const uint32_t set = overlap ? ctx->next_set : 0u;
   st = claim_set(ctx, set, s);
   if (st != MRIP_OK) return st;
@@ -431,10 +511,57 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     st = output_buffer(ctx, set, o, n_reps * 4, &outp[o]);
     if (st != MRIP_OK) return st;
   }
-  const bool wave = ctx->mapping == MRIP_MAP_WAVE;
-  // the headline form, one kernel per run, times itself
-  const bool self_timed = kSelfTimedLaunch && ctx->model == MRIP_MM1 && wave && ctx->split > 1 &&
-                          ctx->rng == MRIP_RNG_PHILOX;
+  if (deferred) {
+    // one launch in timing_every records the kernel's own events
+    const bool timed = ctx->timing_every > 0 && ctx->timing_count % ctx->timing_every == 0;
+    ++ctx->timing_count;
+    KernelEvents ev{};
+    if (timed) {
+      st = record_begin(ctx, s, false);
+      if (st != MRIP_OK) return st;
+      ev = kernel_events(ctx);
+    }
+    Mm1Args a{};
+    a.seed = seed;
+    a.n_reps = n_reps;
+    a.lambda = ctx->mm1.lambda;
+    a.mu = ctx->mm1.mu;
+    a.customers = ctx->mm1.customers;
+    a.mean_w = (float *)outp[0];
+    a.mean_t = (float *)outp[1];
+    a.mean_i = (float *)outp[2];
+    a.rng = ctx->rng;
+    if (ctx->pend.active) {  // the previous run's statistics, in this launch
+      const mrip_ctx_s::Pending &p = ctx->pend;
+      const uint32_t slot = (uint32_t)(p.stats_index % mrip_ctx_s::STATS_RING);
+      for (uint32_t o = 0; o < 3; ++o) a.prev_x[o] = ctx->out[p.set][o].as<float>();
+      a.prev_n = p.n;
+      a.prev_out = ctx->stats_view + (size_t)slot * mrip_ctx_s::STATS_SLOT;
+      a.prev_seq = ctx->seq_view + slot;
+      a.prev_seq_value = p.stats_index + 1;
+      ctx->slot_by_seq[slot] = true;
+      ctx->seq_stream[slot] = s;
+      ctx->pend.active = false;
+    }
+    HIP_TRY(ctx, launch_mm1_split(a, ctx->split, s, timed ? &ev : nullptr));
+    if (timed) {
+      st = record_end(ctx, s, false);
+      if (st != MRIP_OK) return st;
+    }
+    ctx->pend.active = true;
+    ctx->pend.stream = s;
+    ctx->pend.set = set;
+    ctx->pend.n = n_reps;
+    ctx->pend.stats_index = ctx->stats_runs++;
+    // the set's next writer follows on s, after the kernel that reduces it
+    ctx->set_pending[set] = false;
+    ctx->next_set = set ^ 1u;
+    if (timed) mark_done(ctx, s, last_ring_event(ctx));
+    else mark_unmarked(ctx, s);
+    ctx->last = RUN_UNIFORM;
+    ctx->last_n = n_reps;
+    return MRIP_OK;
+  }
 
   st = record_begin(ctx, s, !self_timed);
   if (st != MRIP_OK) return st;
@@ -574,8 +701,18 @@ mrip_status mrip_stats_back(mrip_ctx ctx, uint32_t back, uint32_t output, double
   if (output >= scalar_outputs(ctx)) return inval(ctx, "no such scalar output");
   if (back >= mrip_ctx_s::STATS_RING || back >= ctx->stats_runs)
     return (ctx->err = "no statistics kept for that run"), MRIP_E_STATE;
-  const uint32_t slot = (uint32_t)((ctx->stats_runs - 1 - back) % mrip_ctx_s::STATS_RING);
-  HIP_TRY(ctx, hipEventSynchronize(ctx->ev_stats[slot]));
+  const uint64_t idx = ctx->stats_runs - 1 - back;
+  const uint32_t slot = (uint32_t)(idx % mrip_ctx_s::STATS_RING);
+  if (ctx->pend.active && ctx->pend.stats_index == idx) {
+    mrip_status st = flush_pending(ctx);  // no later run has reduced it yet
+    if (st != MRIP_OK) return st;
+  }
+  if (ctx->slot_by_seq[slot]) {
+    mrip_status st = wait_seq(ctx, slot, idx + 1);
+    if (st != MRIP_OK) return st;
+  } else {
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev_stats[slot]));
+  }
   double nmv[3];
   std::memcpy(nmv, ctx->stats_host + (size_t)slot * mrip_ctx_s::STATS_SLOT + 3 * output,
               sizeof(nmv));
@@ -625,6 +762,13 @@ mrip_status mrip_run_history_ms(mrip_ctx ctx, float *ms, uint32_t max_n, uint32_
   return MRIP_OK;
 }
 
+mrip_status mrip_set_timing(mrip_ctx ctx, uint32_t every) {
+  if (!ctx) return MRIP_E_INVAL;
+  ctx->timing_every = every;
+  ctx->timing_count = 0;
+  return MRIP_OK;
+}
+
 mrip_status mrip_last_run_ms(mrip_ctx ctx, float *ms) {
   if (!ctx || !ms) return MRIP_E_INVAL;
   if (ctx->last == RUN_NONE) return (ctx->err = "no run yet"), MRIP_E_STATE;
@@ -671,7 +815,7 @@ mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n)
   }
   offsets.push_back(n);
   // an earlier plan run may still read the item buffers
-  if (ctx->launches > 0) HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  if (ctx->last_stream) HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
   HIP_TRY(ctx, ctx->it_dp.ensure(4 * n));
   HIP_TRY(ctx, ctx->it_rep.ensure(4 * n));
   HIP_TRY(ctx, ctx->it_n.ensure(8 * n));
@@ -712,6 +856,8 @@ static mrip_status run_plan_impl(mrip_ctx ctx, uint64_t seed, hipStream_t s, con
                                  uint32_t split, bool reduce, uint8_t *done = nullptr,
                                  bool clear_done = false) {
   mrip_status st = ensure_events(ctx);
+  if (st != MRIP_OK) return st;
+  st = flush_pending(ctx);  // a deferred reduction may read output set 0
   if (st != MRIP_OK) return st;
   st = order_after_last(ctx, s);  // before the queue reset below
   if (st != MRIP_OK) return st;

@@ -151,6 +151,32 @@ struct mrip_ctx_s {
   // stream waits for it first)
   hipStream_t last_stream = nullptr;
   hipEvent_t done_ev = nullptr;
+  // set when that call recorded no event after its work (a run whose
+  // statistics are deferred): a call on another stream then records one on
+  // last_stream first (switch_ev)
+  bool last_unmarked = false;
+  hipEvent_t switch_ev = nullptr;
+  // Deferred statistics: a uniform run in the split headline form leaves
+  // its reduction to the next such run on the same stream, whose kernel
+  // reduces it in one extra workgroup, so no event or reduction launch sits
+  // between consecutive simulation kernels; any other call launches the
+  // reduction first (flush_pending).
+  struct Pending {
+    bool active = false;
+    hipStream_t stream = nullptr;
+    uint32_t set = 0;          // the output set it wrote
+    uint64_t n = 0;            // its replications
+    uint64_t stats_index = 0;  // its place in the statistics ring
+  } pend;
+  // per ring slot: the statistics are signalled by a sequence number the
+  // reducing kernel stores (seq_host[slot] >= stats index + 1) on
+  // seq_stream[slot], instead of by ev_stats[slot]
+  bool slot_by_seq[STATS_RING] = {};
+  hipStream_t seq_stream[STATS_RING] = {};
+  uint64_t *seq_host = nullptr, *seq_view = nullptr;
+  // time one simulation launch in timing_every with HIP events (0 = none)
+  uint32_t timing_every = 1;
+  uint64_t timing_count = 0;
   // event pairs of the last RING simulation-kernel launches (run history)
   static constexpr uint32_t RING = 256;
   hipEvent_t ring0[RING] = {}, ring1[RING] = {};
@@ -173,6 +199,8 @@ struct mrip_ctx_s {
 
   ~mrip_ctx_s() {
     if (stats_host) (void)hipHostFree(stats_host);
+    if (seq_host) (void)hipHostFree(seq_host);
+    if (switch_ev) (void)hipEventDestroy(switch_ev);
     for (uint32_t i = 0; i < STATS_RING; ++i)
       if (ev_stats[i]) (void)hipEventDestroy(ev_stats[i]);
     for (uint32_t i = 0; i < 2; ++i)

@@ -71,6 +71,16 @@ struct Mm1Args {
   double log_grid_mean;
   int rng;                      // uniform mode only; plans use Philox
   const uint32_t *taus;
+  // Split kernels of 256-thread workgroups (uniform mode): with prev_n > 0
+  // one extra workgroup reduces the previous run's three fp32 outputs
+  // (prev_n replications each) into prev_out, 3 x (n, mean, variance) as
+  // the reduction kernel writes them, then stores prev_seq_value to
+  // *prev_seq (host-visible) once they are visible.
+  const float *prev_x[3];
+  uint64_t prev_n;
+  double *prev_out;
+  uint64_t *prev_seq;
+  uint64_t prev_seq_value;
 };
 // Mean of -ln u over the 24-bit grid of u, {k 2^-24 : k = 1..2^24}, and
 // the fp32 mean of the exponential variate of `rate` as drawn, (float)(1 /

@@ -32,6 +32,7 @@
 
 #include "device.hpp"
 #include "kernels.hpp"
+#include "reduce_dev.hpp"
 #include "taus.hpp"
 
 namespace mrip {
@@ -851,8 +852,26 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
   }
 }
 
+// The extra workgroup of a split launch: the previous run's statistics,
+// the same bits as the reduction kernel's, then the sequence number that
+// tells the host they are there.
+__device__ void reduce_previous_run(const Mm1Args &a) {
+  __shared__ RedShared sh;
+  for (int o = 0; o < 3; ++o) reduce_output(a.prev_x[o], 1, a.prev_n, a.prev_out + 3 * o, sh);
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    __hip_atomic_store(a.prev_seq, a.prev_seq_value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 template <int X, bool FT>
 __global__ __launch_bounds__(split_wg<X>()) void mm1_split_kernel(Mm1Args a, float ca, float cs) {
+  if constexpr (split_wg<X>() == RED_THREADS) {
+    if (a.prev_n > 0 && blockIdx.x == gridDim.x - 1) {  // uniform across the workgroup
+      reduce_previous_run(a);
+      return;
+    }
+  }
   constexpr int SLOTS = split_slots<X>();  // replications per workgroup
   __shared__ SplitShared<X> sh;
   const int wave = threadIdx.x >> 6;
@@ -1089,7 +1108,10 @@ hipError_t launch_mm1_wave(const Mm1Args &a_in, uint32_t rpw, uint32_t wg, hipSt
 template <int X, bool FT>
 hipError_t split_launch_as(const Mm1Args &a, float ca, float cs, hipStream_t s,
                            const KernelEvents *ev) {
-  const uint64_t blocks = (a.n_reps + split_slots<X>() - 1) / split_slots<X>();
+  if (a.prev_n > 0 && split_wg<X>() != RED_THREADS) return hipErrorInvalidValue;
+  // one more workgroup when it reduces the previous run
+  const uint64_t blocks =
+      (a.n_reps + split_slots<X>() - 1) / split_slots<X>() + (a.prev_n > 0 ? 1 : 0);
   const dim3 g((uint32_t)blocks), b(split_wg<X>());
   if (ev)
     hipExtLaunchKernelGGL((mm1_split_kernel<X, FT>), g, b, 0, s, ev->start, ev->stop, 0, a, ca,

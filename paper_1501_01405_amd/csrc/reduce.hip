@@ -6,6 +6,7 @@
 // in int64 for the mean.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "reduce_dev.hpp"
 #include "taus.hpp"
 
 namespace mrip {
@@ -85,32 +86,9 @@ __global__ void reduce_kernel(const void *x, int dtype, const uint32_t *index,
 
 // One workgroup per output: the same fixed-order two-pass reduction.
 __global__ void reduce_multi_kernel(ReduceSet set, uint64_t n, double *out) {
-  __shared__ double shd[RB];
-  __shared__ long long shl[RB];
+  __shared__ RedShared sh;
   const uint32_t o = blockIdx.x;
-  const void *x = set.x[o];
-  const int dtype = set.dtype[o];
-  double mean;
-  if (dtype == 0) {
-    long long s = 0;
-    for (uint64_t j = threadIdx.x; j < n; j += RB) s += ((const int32_t *)x)[j];
-    mean = (double)block_sum_ll(s, shl) / (double)n;
-  } else {
-    double s = 0.0;
-    for (uint64_t j = threadIdx.x; j < n; j += RB) s += load_x(x, dtype, j);
-    mean = block_sum(s, shd) / (double)n;
-  }
-  double ss = 0.0;
-  for (uint64_t j = threadIdx.x; j < n; j += RB) {
-    const double d = load_x(x, dtype, j) - mean;
-    ss += d * d;
-  }
-  ss = block_sum(ss, shd);
-  if (threadIdx.x == 0) {
-    out[3 * o + 0] = (double)n;
-    out[3 * o + 1] = n > 0 ? mean : 0.0;
-    out[3 * o + 2] = n > 1 ? ss / (double)(n - 1) : 0.0;
-  }
+  reduce_output(set.x[o], set.dtype[o], n, out + 3 * o, sh);
 }
 
 __global__ void philox_dump_kernel(uint64_t seed, const uint32_t *ctr, uint64_t n,

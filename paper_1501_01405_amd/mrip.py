@@ -98,6 +98,7 @@ _SIGS = {
     "mrip_bind_output": (st, [ctx_t, u32, vp, u64]),
     "mrip_run_plan_resume": (st, [ctx_t, u64, vp, vp]),
     "mrip_last_run_ms": (st, [ctx_t, C.POINTER(f32)]),
+    "mrip_set_timing": (st, [ctx_t, u32]),
     "mrip_run_history_ms": (st, [ctx_t, C.POINTER(f32), u32, C.POINTER(u32)]),
     "mrip_plan_set": (st, [ctx_t, vp, u64]),
     "mrip_run_plan": (st, [ctx_t, u64, vp]),
@@ -244,6 +245,10 @@ def mrip_outputs(ctx, output, dst, dst_is_device):
     nbytes = dst.numel() * dst.element_size() if hasattr(dst, "numel") else dst.nbytes
     check(load().mrip_outputs(ctx, output, _ptr(dst), nbytes, int(dst_is_device)), ctx)
     return dst
+
+
+def mrip_set_timing(ctx, every):
+    check(load().mrip_set_timing(ctx, every), ctx)
 
 
 def mrip_last_run_ms(ctx):
@@ -503,6 +508,9 @@ class Context:
             dt = getattr(torch, _OUT_DTYPES[self.model][output])
             t = torch.empty(n, dtype=dt, device="cuda")
         return mrip_outputs(self.ctx, output, t, True)
+
+    def set_timing(self, every):
+        mrip_set_timing(self.ctx, every)
 
     def last_ms(self):
         return mrip_last_run_ms(self.ctx)
