@@ -22,11 +22,12 @@ sys.path.insert(0, ROOT)
 
 R, N, LAM, MU = 1024, 100000, 0.9, 1.0
 SPLIT = 4  # wavefronts per replication (four per SIMD at 1024 replications)
-# HBM bytes per launch of mm1_split_kernel<4, false> from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, each scaled by the same counter on a 256 MiB copy
+# HBM bytes per launch of mm1_split_kernel<4, false> (reducing the previous
+# run, the steady state) from rocprofv3 FETCH_SIZE and WRITE_SIZE, each
+# scaled by the same counter on a 256 MiB copy
 # (profiles/mm1_split_hbm_counters.md); to be re-measured (or set to None)
 # whenever the kernel changes.
-TRAFFIC_BYTES = (169.0 * 2.00 + 96.0 * 1.00) * 1024  # taken at SPLIT = 4
+TRAFFIC_BYTES = (175.6 * 2.00 + 96.1 * 1.00) * 1024  # taken at SPLIT = 4
 # One headline launch in TIMING_EVERY records its kernel's HIP events (the
 # kernel duration the roofline uses); the others carry no event.
 TIMING_EVERY = 8
