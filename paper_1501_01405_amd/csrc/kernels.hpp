@@ -58,7 +58,6 @@ struct Mm1Args {
   uint64_t feature_prefix;      // K (0 = no features)
   Mm1Items items;               // plan mode (items.dp != nullptr)
   uint32_t *queue_head;         // plan mode: device counter, zero at launch
-  uint8_t *done;                // plan mode (nullable): done[i] = 1 once item i's outputs are written
   float *mean_w, *mean_t, *mean_i;
   float *features;              // n x 10 when feature_prefix > 0
   // n x 8 when feature_prefix > 0: the martingale controls over customers
@@ -81,6 +80,7 @@ struct Mm1Args {
   double *prev_out;
   uint64_t *prev_seq;
   uint64_t prev_seq_value;
+  uint8_t *done;                // plan mode (nullable): done[i] = 1 once item i's outputs are written
 };
 // Mean of -ln u over the 24-bit grid of u, {k 2^-24 : k = 1..2^24}, and
 // the fp32 mean of the exponential variate of `rate` as drawn, (float)(1 /

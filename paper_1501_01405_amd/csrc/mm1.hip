@@ -378,7 +378,6 @@ __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a)
 #pragma unroll
       for (int k = 0; k < 8; ++k) a.controls[d.out * 8 + k] = cl[k];
     }
-    if (a.done) a.done[d.out] = 1;
   }
 }
 
@@ -667,7 +666,10 @@ __global__ __launch_bounds__(ft_max_wg<FT>()) void mm1_plan_kernel(Mm1Args a, ui
     unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)unit, 0, 64));
     if (unit >= n_units) break;
     PhiloxSource src{k0, k1};
-    wave_group<RPW, FT>(item_rep(a, (uint64_t)unit * RPW + q, n_items), src, a.feature_prefix, a);
+    const Rep d = item_rep(a, (uint64_t)unit * RPW + q, n_items);
+    wave_group<RPW, FT>(d, src, a.feature_prefix, a);
+    // the lane that stored the item's outputs flags it
+    if (a.done && (lane % (16 * S)) == 0 && d.n > 0) a.done[d.out] = 1;
   }
 }
 
@@ -848,7 +850,6 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
         a.controls[d.out * 8 + 4 + k] = pcs[k];
       }
     }
-    if (a.done) a.done[d.out] = 1;
   }
 }
 
@@ -910,6 +911,7 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a
     const uint64_t idx = first + slot;
     const Rep d = item_rep(a, idx, idx < n_long ? n_long : 0);
     split_replication<X, FT>(d, slot, h, k0, k1, a.feature_prefix, a, sh);
+    if (a.done && h == 0 && lane == 0 && d.n > 0) a.done[d.out] = 1;  // after its outputs
   }
   __builtin_amdgcn_s_setprio(0);
   const int q = (lane >> 4) / S;
@@ -922,8 +924,9 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a
     if (unit >= n_units) break;
     const uint64_t j = (uint64_t)unit * RPW + q;
     PhiloxSource src{k0, k1};
-    wave_group<RPW, FT>(item_rep(a, n_long + j, j < n_short ? n_items : 0), src, a.feature_prefix,
-                        a);
+    const Rep d = item_rep(a, n_long + j, j < n_short ? n_items : 0);
+    wave_group<RPW, FT>(d, src, a.feature_prefix, a);
+    if (a.done && (lane % (16 * S)) == 0 && d.n > 0) a.done[d.out] = 1;
   }
 }
 
