@@ -698,6 +698,11 @@ template <int X>
 struct SplitShared {
   float spec[split_slots<X>()][X], fin[split_slots<X>()][X];
   float sum[split_slots<X>()][X][7];  // W, T, I, then the four controls
+  // Parts h >= 1 only compose and scan their first chunk in phase 1 and
+  // apply it once, from the true start, in phase 2: its variates and scan
+  // per lane ([value][lane]: lane-contiguous) and the segment totals.
+  float first[split_slots<X>()][X - 1][2 * MM1_P + 2][64];
+  float first_t[split_slots<X>()][X - 1][8];
 };
 
 // Part h of replication d (slot `slot` of the workgroup); every thread of
@@ -739,6 +744,35 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
   Sums acc;
   Feat ft;
   uint32_t c = cb;
+  // parts h >= 1: their first chunk (full, after any feature prefix: a split
+  // part holds at least two chunks and the prefix lies in part 0) is only
+  // composed and scanned here, which gives the speculative carry after it;
+  // phase 2 applies it from the true start
+  const bool stash = split && h >= 1;
+  float spec0 = 0.0f;  // the speculative carry after the first chunk
+  if (stash) {
+    const Draw<P> dr = draw_chunk<1, P>((uint64_t)c * CHUNK, d, k0, k1);
+    const ChunkScan cs = compose_scan<P>(dr);
+    float tin;
+    carry = carry_through<1>(cs, carry, tin);
+    spec0 = carry;
+    float(*st)[64] = sh.first[slot][h - 1];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      st[j][lane] = dr.A[j];
+      st[P + j][lane] = dr.S[j];
+    }
+    st[2 * P][lane] = cs.ea;
+    st[2 * P + 1][lane] = cs.eb;
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sh.first_t[slot][h - 1][j] = cs.ta[j];
+        sh.first_t[slot][h - 1][4 + j] = cs.tb[j];
+      }
+    }
+    ++c;
+  }
 #define MRIP_CHUNK(F, TL)                                                          \
   {                                                                                \
     const Draw<P> dr = draw_chunk<1, P>((uint64_t)c * CHUNK, d, k0, k1);          \
@@ -752,13 +786,47 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
   if (lane == 0) sh.spec[slot][h] = carry;
   __syncthreads();
 
-  // the part's correction from true start `cin`; returns its true end
+  // the part's correction from true start `cin`: its first chunk applied
+  // from cin, then fix-up chunks until the true and speculative carries
+  // meet; returns its true end
   Sums fix;
   auto correct = [&](float cin) -> float {
     fix = Sums();
-    float ct = cin, cs = 0.0f;
-    bool coupled = false;
-    for (uint32_t cc = cb; cc < ce && !coupled; ++cc) {
+    Draw<P> dr;
+    ChunkScan scan;
+    const float(*st)[64] = sh.first[slot][h - 1];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      dr.A[j] = st[j][lane];
+      dr.S[j] = st[P + j][lane];
+    }
+    scan.ea = st[2 * P][lane];
+    scan.eb = st[2 * P + 1][lane];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      scan.ta[j] = sh.first_t[slot][h - 1][j];
+      scan.tb[j] = sh.first_t[slot][h - 1][4 + j];
+    }
+    float tin;
+    float ct = carry_through<1>(scan, cin, tin);
+    {
+      Feat none;
+      float sw, stt, si, cl[4];
+      apply_lane<P, false, false, FT>(fmaxf(scan.ea, tin + scan.eb), dr,
+                                      lane_first_customer<1, P>((uint64_t)cb * CHUNK), d.n, 0,
+                                      d.ea, d.es, sw, stt, si, none, cl);
+      fix.w.add(sw);
+      fix.t.add(stt);
+      fix.i.add(si);
+      if (FT) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fix.c[k].add(cl[k]);
+      }
+    }
+    float cs = spec0;
+    bool coupled =
+        __builtin_amdgcn_readfirstlane((int)(__float_as_uint(ct) == __float_as_uint(cs))) != 0;
+    for (uint32_t cc = cb + 1; cc < ce && !coupled; ++cc) {
       const Draw<P> dr = draw_chunk<1, P>((uint64_t)cc * CHUNK, d, k0, k1);
       if (cc < full) fixup_chunk<P, false, FT>((uint64_t)cc * CHUNK, dr, d, ct, cs, fix);
       else fixup_chunk<P, true, FT>((uint64_t)cc * CHUNK, dr, d, ct, cs, fix);
@@ -788,8 +856,8 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
   acc.t.add(fix.t.value());
   acc.i.add(fix.i.value());
   if (FT) {
-    acc.c[2].add(fix.c[2].value());
-    acc.c[3].add(fix.c[3].value());
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc.c[k].add(fix.c[k].value());
   }
 
   // phase 3: part sums, then the replication's means in part order
@@ -866,7 +934,8 @@ __device__ void reduce_previous_run(const Mm1Args &a) {
 }
 
 template <int X, bool FT>
-__global__ __launch_bounds__(split_wg<X>()) void mm1_split_kernel(Mm1Args a, float ca, float cs) {
+__global__ __launch_bounds__(split_wg<X>(), FT ? 1 : 4) void mm1_split_kernel(Mm1Args a, float ca,
+                                                                           float cs) {
   if constexpr (split_wg<X>() == RED_THREADS) {
     if (a.prev_n > 0 && blockIdx.x == gridDim.x - 1) {  // uniform across the workgroup
       reduce_previous_run(a);
