@@ -694,15 +694,18 @@ constexpr int split_slots() {
   return split_wg<X>() / (64 * X);
 }
 
-template <int X>
+// Parts h >= 1 only compose and scan their first chunk in phase 1 and
+// apply it once, from the true start, in phase 2. STASH: its variates and
+// scan per lane ([value][lane]: lane-contiguous) and the segment totals
+// wait in LDS; without it (the kernels with the controls, whose registers
+// are full) phase 2 draws the chunk again, to the same bits.
+template <int X, bool STASH>
 struct SplitShared {
+  static constexpr int NF = STASH ? X - 1 : 1;
   float spec[split_slots<X>()][X], fin[split_slots<X>()][X];
   float sum[split_slots<X>()][X][7];  // W, T, I, then the four controls
-  // Parts h >= 1 only compose and scan their first chunk in phase 1 and
-  // apply it once, from the true start, in phase 2: its variates and scan
-  // per lane ([value][lane]: lane-contiguous) and the segment totals.
-  float first[split_slots<X>()][X - 1][2 * MM1_P + 2][64];
-  float first_t[split_slots<X>()][X - 1][8];
+  float first[split_slots<X>()][NF][STASH ? 2 * MM1_P + 2 : 1][64];
+  float first_t[split_slots<X>()][NF][8];
 };
 
 // Part h of replication d (slot `slot` of the workgroup); every thread of
@@ -726,8 +729,10 @@ struct SplitShared {
 // the prefix except in part 0's feature chunks); a correction adds the
 // difference of the two T-weighted controls between its two starts.
 template <int X, bool FT>
-__device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, uint32_t k1,
-                                  uint64_t K, const Mm1Args &a, SplitShared<X> &sh) {
+__device__ __forceinline__ void split_replication(const Rep &d, int slot, int h, uint32_t k0,
+                                                  uint32_t k1, uint64_t K, const Mm1Args &a,
+                                                  SplitShared<X, !FT> &sh) {
+  constexpr bool STASH = !FT;
   if (!FT) K = 0;
   constexpr int P = MM1_P;
   constexpr uint64_t CHUNK = 16u * P * 4;
@@ -748,27 +753,29 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
   // part holds at least two chunks and the prefix lies in part 0) is only
   // composed and scanned here, which gives the speculative carry after it;
   // phase 2 applies it from the true start
-  const bool stash = split && h >= 1;
+  const bool deferred_first = split && h >= 1;
   float spec0 = 0.0f;  // the speculative carry after the first chunk
-  if (stash) {
+  if (deferred_first) {
     const Draw<P> dr = draw_chunk<1, P>((uint64_t)c * CHUNK, d, k0, k1);
     const ChunkScan cs = compose_scan<P>(dr);
     float tin;
     carry = carry_through<1>(cs, carry, tin);
     spec0 = carry;
-    float(*st)[64] = sh.first[slot][h - 1];
+    if constexpr (STASH) {
+      float(*st)[64] = sh.first[slot][h - 1];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      st[j][lane] = dr.A[j];
-      st[P + j][lane] = dr.S[j];
-    }
-    st[2 * P][lane] = cs.ea;
-    st[2 * P + 1][lane] = cs.eb;
-    if (lane == 0) {
+      for (int j = 0; j < P; ++j) {
+        st[j][lane] = dr.A[j];
+        st[P + j][lane] = dr.S[j];
+      }
+      st[2 * P][lane] = cs.ea;
+      st[2 * P + 1][lane] = cs.eb;
+      if (lane == 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        sh.first_t[slot][h - 1][j] = cs.ta[j];
-        sh.first_t[slot][h - 1][4 + j] = cs.tb[j];
+        for (int j = 0; j < 4; ++j) {
+          sh.first_t[slot][h - 1][j] = cs.ta[j];
+          sh.first_t[slot][h - 1][4 + j] = cs.tb[j];
+        }
       }
     }
     ++c;
@@ -794,18 +801,23 @@ __device__ void split_replication(const Rep &d, int slot, int h, uint32_t k0, ui
     fix = Sums();
     Draw<P> dr;
     ChunkScan scan;
-    const float(*st)[64] = sh.first[slot][h - 1];
+    if constexpr (STASH) {
+      const float(*st)[64] = sh.first[slot][h - 1];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      dr.A[j] = st[j][lane];
-      dr.S[j] = st[P + j][lane];
-    }
-    scan.ea = st[2 * P][lane];
-    scan.eb = st[2 * P + 1][lane];
+      for (int j = 0; j < P; ++j) {
+        dr.A[j] = st[j][lane];
+        dr.S[j] = st[P + j][lane];
+      }
+      scan.ea = st[2 * P][lane];
+      scan.eb = st[2 * P + 1][lane];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      scan.ta[j] = sh.first_t[slot][h - 1][j];
-      scan.tb[j] = sh.first_t[slot][h - 1][4 + j];
+      for (int j = 0; j < 4; ++j) {
+        scan.ta[j] = sh.first_t[slot][h - 1][j];
+        scan.tb[j] = sh.first_t[slot][h - 1][4 + j];
+      }
+    } else {  // the same chunk drawn and scanned again: the same bits
+      dr = draw_chunk<1, P>((uint64_t)cb * CHUNK, d, k0, k1);
+      scan = compose_scan<P>(dr);
     }
     float tin;
     float ct = carry_through<1>(scan, cin, tin);
@@ -943,7 +955,7 @@ __global__ __launch_bounds__(split_wg<X>(), FT ? 1 : 4) void mm1_split_kernel(Mm
     }
   }
   constexpr int SLOTS = split_slots<X>();  // replications per workgroup
-  __shared__ SplitShared<X> sh;
+  __shared__ SplitShared<X, !FT> sh;
   const int wave = threadIdx.x >> 6;
   const int slot = wave / X, h = wave % X;
   const uint64_t r = (uint64_t)blockIdx.x * SLOTS + slot;
@@ -965,7 +977,7 @@ __global__ __launch_bounds__(split_wg<X>()) void mm1_plan_split_kernel(Mm1Args a
   constexpr int SLOTS = split_slots<X>();
   static_assert(X == 2 || X == 4 || X == 8, "plans split over 2, 4 or 8 wavefronts");
   constexpr int S = 4 / RPW;
-  __shared__ SplitShared<X> sh;
+  __shared__ SplitShared<X, !FT> sh;
   __shared__ uint32_t sh_pop;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int slot = wave / X, h = wave % X;
