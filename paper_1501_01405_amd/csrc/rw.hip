@@ -128,6 +128,18 @@ __device__ __forceinline__ void lds_or(uint32_t addr, uint32_t mask) {
 // the lane's pending word (paddr, pmask) while the walker stays in that
 // word (an x move does, 31 times in 32) and reach LDS, as one or, when it
 // leaves: about half the moves need no LDS operation.
+// LDS byte address of the bitmap word holding site (X, Y) of the lean
+// forms, from X and YB = Y * GRID / 8 (both unwrapped).
+template <int GRID>
+__device__ __forceinline__ uint32_t lean_word_addr(int X, int YB, uint32_t base) {
+  constexpr int ROWB = GRID / 8;
+  constexpr uint32_t ROWS = (uint32_t)(GRID * ROWB - 1) & ~(uint32_t)(ROWB - 1);
+  constexpr uint32_t COLS = (uint32_t)(ROWB - 1) & ~3u;
+  constexpr int LOG_COLW = GRID == 128 ? 2 : 1;
+  const uint32_t row = ((uint32_t)YB & ROWS) | base;
+  return COLS ? lshl_or<2>(__builtin_amdgcn_ubfe((uint32_t)X, 5, LOG_COLW), row) : row;
+}
+
 template <int GRID>
 __device__ __forceinline__ void walk16_full(uint32_t word, uint32_t g, uint32_t steps, int &X,
                                            int &YB, uint32_t base, uint32_t &paddr,
@@ -192,6 +204,45 @@ __device__ __forceinline__ bool lean_walk(const RwArgs &a, uint64_t r, uint32_t 
     return true;
   } else {
     (void)a, (void)r, (void)w, (void)k0, (void)k1, (void)bm, (void)X, (void)Y;
+    return false;
+  }
+}
+
+// Pass 2 of the segmented walk in the lean form (every lane one segment of
+// a walker, Philox, GRID >= 32, no per-walker bitmaps): the segment's moves
+// from its start (X, Y), marking through the lane's pending word, which
+// starts empty (the start site is the previous segment's last one, or the
+// walker's start, marked apart); false when the form does not apply and
+// nothing was done. `first`: the words of the segment's first 64 moves.
+template <int GRID, int RNG, bool PW>
+__device__ __forceinline__ bool lean_segment(const RwArgs &a, uint64_t r, uint32_t w, uint32_t k0,
+                                             uint32_t k1, uint32_t t0, uint32_t t1,
+                                             const uint32_t (&first)[4], uint32_t *bm, int X,
+                                             int Y) {
+  if constexpr (GRID >= 32 && !PW && RNG == RNG_PHILOX) {
+    if (a.walkers != 64u) return false;
+    constexpr int LOG_ROWB = GRID == 32 ? 2 : GRID == 64 ? 3 : 4;
+    typedef __attribute__((address_space(3))) uint32_t lds_u32;
+    const uint32_t base = (uint32_t)(uintptr_t)(lds_u32 *)bm;
+    int YB = (int)((uint32_t)Y << LOG_ROWB);
+    uint32_t paddr = lean_word_addr<GRID>(X, YB, base), pmask = 0u;
+    if (t0 < t1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        walk16_full<GRID>(first[j], t0 + 16u * j, t1, X, YB, base, paddr, pmask);
+      for (uint32_t g = t0 + 64; g < t1; g += 64) {
+        const Block4 b = philox(g >> 6, w, (uint32_t)(a.rep0 + r), TAG_RW, k0, k1);
+        walk16_full<GRID>(b.x, g, t1, X, YB, base, paddr, pmask);
+        walk16_full<GRID>(b.y, g + 16, t1, X, YB, base, paddr, pmask);
+        walk16_full<GRID>(b.z, g + 32, t1, X, YB, base, paddr, pmask);
+        walk16_full<GRID>(b.w, g + 48, t1, X, YB, base, paddr, pmask);
+      }
+    }
+    lds_or(paddr, pmask);
+    return true;
+  } else {
+    (void)a, (void)r, (void)w, (void)k0, (void)k1, (void)t0, (void)t1, (void)first, (void)bm,
+        (void)X, (void)Y;
     return false;
   }
 }
@@ -341,7 +392,9 @@ template <int GRID, int RNG, bool PW>
 __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
   constexpr int WORDS = GRID * GRID / 32;
   constexpr int WB = PW ? WB_SHARED : WB_NONE;
-  __shared__ uint32_t bm[WORDS + 1];  // + the inactive lanes' spare word
+  // + the inactive lanes' spare word; aligned to the largest bitmap (128 x
+  // 128 bits), so that the lean form can or a site's offset into its address
+  __shared__ __attribute__((aligned(2048))) uint32_t bm[WORDS + 1];
   __shared__ int sh_red[16];
   const int tid = threadIdx.x;
   const uint32_t w = (uint32_t)tid >> 4, sgi = (uint32_t)tid & 15u;
@@ -411,6 +464,9 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
   int X = x0 + (sx - dx), Y = y0 + (sy - dy);
 
   // pass 2: replay the segment's moves from its start
+  if (lean_segment<GRID, RNG, PW>(a, r, w, k0, k1, t0, t1, first, bm, X, Y)) {
+    // every lane a walker's segment: done in the lean form
+  } else {
   if (t0 < t1) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -432,6 +488,7 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       walk16<GRID, true, WB>(wd[j], g + 16u * j, t1, active, X, Y, bm, &bm[WORDS], wb);
+  }
   }
   __syncthreads();
 
