@@ -723,11 +723,12 @@ struct SplitShared {
 // from that end.
 //
 // FT = false is the form for runs without prefix features (K = 0): the
-// feature chunks, the controls and their registers are compiled out (74
-// VGPRs instead of 105 for the uniform kernel), which the kernels take when
-// K = 0. With FT every part adds the controls of its customers (all after
-// the prefix except in part 0's feature chunks); a correction adds the
-// difference of the two T-weighted controls between its two starts.
+// feature chunks, the controls and their registers are compiled out (about
+// half the registers of the FT form), which the kernels take when K = 0.
+// With FT every part adds the controls of its customers (all after the
+// prefix except in part 0's feature chunks); the deferred first chunk adds
+// all four of its controls, a later correction chunk the difference of the
+// two T-weighted ones between its two starts.
 template <int X, bool FT>
 __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h, uint32_t k0,
                                                   uint32_t k1, uint64_t K, const Mm1Args &a,
