@@ -50,12 +50,18 @@ struct Rep {
   uint64_t out;      // output index
 };
 
-// Sums of W, T and I, and of the four martingale controls over customers
+// Sums of T, S and I, and of the four martingale controls over customers
 // n >= K (FT forms only): S_n - E S, A_n - E A, and both weighted by T_{n-1}.
+// The waits follow as W_n = T_n - S_n: their sum is that of T less that of S.
 struct Sums {
-  Kahan w, t, i;
+  Kahan t, s, i;
   Kahan c[4];
 };
+
+// A lane's sum of waits from its sums of T and S.
+__device__ __forceinline__ float wait_sum(const Sums &x) {
+  return (x.t.sum - x.s.sum) - (x.t.comp - x.s.comp);
+}
 
 // Prefix features, and the four controls over the prefix customers (n < K:
 // a lane holds about K / 64 of them, plain fp32 sums suffice).
@@ -178,18 +184,21 @@ __device__ __forceinline__ float carry_through(const ChunkScan &cs, float carry,
   return cur;
 }
 
-// The lane's P customers in order, from the system time T before the first;
-// sums of W, T and I (TAIL: only customers < n) and, with FT, the prefix
-// features and prefix controls (customers < K, FEAT chunks only) and the
-// partial sums of the four controls after the prefix (customers >= K).
-// A_n and S_n are drawn independently of T_{n-1}, the system time the lane
-// holds when it reaches customer n, so every control term has mean zero
-// given the past.
+// The lane's P customers in order, from the system time T before the first.
+// Each customer applies its map: x = T + b with b = S - A, T <- max(x, S)
+// (Lindley's W = max(0, T - A), T = W + S with one rounding less), and its
+// idle time is I = T - x, exactly 0 whenever the server is busy. The lane
+// sums T, S and I (TAIL: only customers < n); the waits follow as T - S.
+// With FT: the prefix features and prefix controls (customers < K, FEAT
+// chunks only) and the partial sums of the four controls after the prefix
+// (customers >= K). A_n and S_n are drawn independently of T_{n-1}, the
+// system time the lane holds when it reaches customer n, so every control
+// term has mean zero given the past.
 template <int P, bool FEAT, bool TAIL, bool FT>
 __device__ __forceinline__ void apply_lane(float T, const Draw<P> &dr, uint64_t n0, uint64_t n,
-                                           uint64_t K, float ea, float es, float &sw, float &st,
+                                           uint64_t K, float ea, float es, float &st, float &ss,
                                            float &si, Feat &ft, float (&cl)[4]) {
-  sw = st = si = 0.0f;
+  st = ss = si = 0.0f;
   if (FT) cl[0] = cl[1] = cl[2] = cl[3] = 0.0f;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -217,31 +226,35 @@ __device__ __forceinline__ void apply_lane(float T, const Draw<P> &dr, uint64_t 
         cl[3] = __builtin_fmaf(T, da, cl[3]);
       }
     }
-    // I = max(0, A - T) = W - (T - A) exactly: A - T = -(T - A) in IEEE
-    // arithmetic, and W is either 0 or T - A
-    const float dlt = T - dr.A[j];
-    const float W = fmaxf(0.0f, dlt);
-    const float I = W - dlt;
-    T = W + dr.S[j];
+    if (FEAT) {  // the prefix features, from their definitions
+      const bool f = n0 + j < K;
+      // I = max(0, A - T) = W - (T - A) exactly: A - T = -(T - A) in IEEE
+      // arithmetic, and W is either 0 or T - A
+      const float dlt = T - dr.A[j];
+      const float W = fmaxf(0.0f, dlt);
+      ft.sa += f ? dr.A[j] : 0.0f;
+      ft.ss += f ? dr.S[j] : 0.0f;
+      ft.sw += f ? W : 0.0f;
+      ft.si += f ? W - dlt : 0.0f;
+      ft.zeros += (f && W == 0.0f);
+      ft.wmax = fmaxf(ft.wmax, f ? W : 0.0f);
+    }
+    const float x = T + (dr.S[j] - dr.A[j]);
+    T = fmaxf(x, dr.S[j]);
+    const float I = T - x;
     if (TAIL) {
       const bool v = n0 + j < n;
-      sw += v ? W : 0.0f;
       st += v ? T : 0.0f;
+      ss += v ? dr.S[j] : 0.0f;
       si += v ? I : 0.0f;
     } else {
-      sw += W;
       st += T;
+      ss += dr.S[j];
       si += I;
     }
     if (FEAT) {
       const bool f = n0 + j < K;
-      ft.sa += f ? dr.A[j] : 0.0f;
-      ft.ss += f ? dr.S[j] : 0.0f;
-      ft.sw += f ? W : 0.0f;
       ft.st += f ? T : 0.0f;
-      ft.si += f ? I : 0.0f;
-      ft.zeros += (f && W == 0.0f);
-      ft.wmax = fmaxf(ft.wmax, f ? W : 0.0f);
       if (n0 + j + 1 == K) ft.tlast = T;
     }
   }
@@ -265,11 +278,11 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, con
   const ChunkScan cs = compose_scan<P>(dr);
   float tin;
   carry = carry_through<RPW>(cs, carry, tin);
-  float sw, st, si, cl[4];
+  float st, ss, si, cl[4];
   apply_lane<P, FEAT, TAIL, FT>(fmaxf(cs.ea, tin + cs.eb), dr, lane_first_customer<RPW, P>(base),
-                                d.n, K, d.ea, d.es, sw, st, si, ft, cl);
-  acc.w.add(sw);
+                                d.n, K, d.ea, d.es, st, ss, si, ft, cl);
   acc.t.add(st);
+  acc.s.add(ss);
   acc.i.add(si);
   if (FT) {
 #pragma unroll
@@ -279,9 +292,9 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, con
 
 // Fix-up chunk of a split replication: the same customers from two carries
 // (the true one and the speculative one the part started from); adds the
-// difference of their sums. Fix-up chunks lie after the feature prefix, so
-// with FT every customer counts for the controls; the two unweighted ones
-// do not depend on the carry.
+// difference of their sums (S and the two unweighted controls do not depend
+// on the carry). Fix-up chunks lie after the feature prefix, so with FT
+// every customer counts for the controls.
 template <int P, bool TAIL, bool FT>
 __device__ __forceinline__ void fixup_chunk(uint64_t base, const Draw<P> &dr, const Rep &d,
                                             float &c_true, float &c_spec, Sums &acc) {
@@ -291,12 +304,11 @@ __device__ __forceinline__ void fixup_chunk(uint64_t base, const Draw<P> &dr, co
   c_spec = carry_through<1>(cs, c_spec, tin_s);
   const uint64_t n0 = lane_first_customer<1, P>(base);
   Feat none;
-  float wt, tt, it, ws, ts, is, clt[4], cls[4];
-  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_t + cs.eb), dr, n0, d.n, 0, d.ea, d.es, wt, tt,
+  float tt, st_, it, ts, ss_, is, clt[4], cls[4];
+  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_t + cs.eb), dr, n0, d.n, 0, d.ea, d.es, tt, st_,
                                  it, none, clt);
-  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_s + cs.eb), dr, n0, d.n, 0, d.ea, d.es, ws, ts,
+  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_s + cs.eb), dr, n0, d.n, 0, d.ea, d.es, ts, ss_,
                                  is, none, cls);
-  acc.w.add(wt - ws);
   acc.t.add(tt - ts);
   acc.i.add(it - is);
   if (FT) {
@@ -345,7 +357,7 @@ __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a)
   for (; c < chunks; ++c) MRIP_CHUNK(false, true)
 #undef MRIP_CHUNK
 
-  const float sw = group_sum_compensated(acc.w.value(), WIDTH);
+  const float sw = group_sum_compensated(wait_sum(acc), WIDTH);
   const float st = group_sum_compensated(acc.t.value(), WIDTH);
   const float si = group_sum_compensated(acc.i.value(), WIDTH);
   float f[10], cl[8];
@@ -824,12 +836,12 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
     float ct = carry_through<1>(scan, cin, tin);
     {
       Feat none;
-      float sw, stt, si, cl[4];
+      float stt, ss, si, cl[4];
       apply_lane<P, false, false, FT>(fmaxf(scan.ea, tin + scan.eb), dr,
                                       lane_first_customer<1, P>((uint64_t)cb * CHUNK), d.n, 0,
-                                      d.ea, d.es, sw, stt, si, none, cl);
-      fix.w.add(sw);
+                                      d.ea, d.es, stt, ss, si, none, cl);
       fix.t.add(stt);
+      fix.s.add(ss);
       fix.i.add(si);
       if (FT) {
 #pragma unroll
@@ -865,8 +877,8 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
     }
     __syncthreads();
   }
-  acc.w.add(fix.w.value());
   acc.t.add(fix.t.value());
+  acc.s.add(fix.s.value());
   acc.i.add(fix.i.value());
   if (FT) {
 #pragma unroll
@@ -876,7 +888,7 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
   // phase 3: part sums, then the replication's means in part order
   constexpr int NS = FT ? 7 : 3;
   float part[NS];
-  part[0] = group_sum_compensated(acc.w.value(), 64);
+  part[0] = group_sum_compensated(wait_sum(acc), 64);
   part[1] = group_sum_compensated(acc.t.value(), 64);
   part[2] = group_sum_compensated(acc.i.value(), 64);
   if (FT) {
