@@ -115,24 +115,32 @@ struct PhiloxSource {
   }
 };
 
-// The scanned maps of one chunk: this lane's exclusive prefix (ea, eb) and
-// the four segment totals.
+// The scanned maps of one chunk: this lane's exclusive prefix (ea, eb), the
+// map of its first P / 2 customers (ha, hb) and the four segment totals.
 struct ChunkScan {
-  float ea, eb;
+  float ea, eb, ha, hb;
   float ta[4], tb[4];
 };
 
-// Compose this lane's P customers in order, then scan the 16-lane segment.
+// Compose this lane's P customers (its two halves side by side, in order
+// within each, then the second half after the first), then scan the
+// 16-lane segment.
 template <int P>
 __device__ __forceinline__ ChunkScan compose_scan(const Draw<P> &dr) {
-  float a = dr.S[0];
-  float bb = dr.S[0] - dr.A[0];
+  constexpr int H = P / 2;
+  float a0 = dr.S[0], b0 = dr.S[0] - dr.A[0];
+  float a1 = dr.S[H], b1 = dr.S[H] - dr.A[H];
 #pragma unroll
-  for (int j = 1; j < P; ++j) {
-    const float bj = dr.S[j] - dr.A[j];
-    a = fmaxf(dr.S[j], a + bj);
-    bb = bb + bj;
+  for (int j = 1; j < H; ++j) {
+    const float c0 = dr.S[j] - dr.A[j];
+    a0 = fmaxf(dr.S[j], a0 + c0);
+    b0 = b0 + c0;
+    const float c1 = dr.S[H + j] - dr.A[H + j];
+    a1 = fmaxf(dr.S[H + j], a1 + c1);
+    b1 = b1 + c1;
   }
+  float a = fmaxf(a1, a0 + b1);
+  float bb = b0 + b1;
 #define MRIP_SCAN_STEP(N)                              \
   {                                                    \
     const float as = row_shr<N>(a, kNegInf);           \
@@ -146,6 +154,8 @@ __device__ __forceinline__ ChunkScan compose_scan(const Draw<P> &dr) {
   MRIP_SCAN_STEP(8)
 #undef MRIP_SCAN_STEP
   ChunkScan r;
+  r.ha = a0;
+  r.hb = b0;
   r.ea = row_shr<1>(a, kNegInf);
   r.eb = row_shr<1>(bb, 0.0f);
   r.ta[0] = readlane_f(a, 15);
@@ -195,13 +205,20 @@ __device__ __forceinline__ float carry_through(const ChunkScan &cs, float carry,
 // system time the lane holds when it reaches customer n, so every control
 // term has mean zero given the past.
 template <int P, bool FEAT, bool TAIL, bool FT>
-__device__ __forceinline__ void apply_lane(float T, const Draw<P> &dr, uint64_t n0, uint64_t n,
-                                           uint64_t K, float ea, float es, float &st, float &ss,
-                                           float &si, Feat &ft, float (&cl)[4]) {
-  st = ss = si = 0.0f;
+__device__ __forceinline__ void apply_lane(float T0, const ChunkScan &cs, const Draw<P> &dr,
+                                           uint64_t n0, uint64_t n, uint64_t K, float ea, float es,
+                                           float &st, float &ss, float &si, Feat &ft,
+                                           float (&cl)[4]) {
+  constexpr int H = P / 2;
+  // the two halves side by side, the second from max(ha, T0 + hb), the
+  // system time the first half's map gives; each half sums on its own
+  float Th[2] = {T0, fmaxf(cs.ha, T0 + cs.hb)};
+  float sth[2] = {0.0f, 0.0f}, ssh[2] = {0.0f, 0.0f}, sih[2] = {0.0f, 0.0f};
   if (FT) cl[0] = cl[1] = cl[2] = cl[3] = 0.0f;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
+    const int h = j >= H;
+    float &T = Th[h];
     if (FT) {
       bool v = true;
       if (FEAT) v = n0 + j >= K;
@@ -244,13 +261,13 @@ __device__ __forceinline__ void apply_lane(float T, const Draw<P> &dr, uint64_t 
     const float I = T - x;
     if (TAIL) {
       const bool v = n0 + j < n;
-      st += v ? T : 0.0f;
-      ss += v ? dr.S[j] : 0.0f;
-      si += v ? I : 0.0f;
+      sth[h] += v ? T : 0.0f;
+      ssh[h] += v ? dr.S[j] : 0.0f;
+      sih[h] += v ? I : 0.0f;
     } else {
-      st += T;
-      ss += dr.S[j];
-      si += I;
+      sth[h] += T;
+      ssh[h] += dr.S[j];
+      sih[h] += I;
     }
     if (FEAT) {
       const bool f = n0 + j < K;
@@ -258,6 +275,9 @@ __device__ __forceinline__ void apply_lane(float T, const Draw<P> &dr, uint64_t 
       if (n0 + j + 1 == K) ft.tlast = T;
     }
   }
+  st = sth[0] + sth[1];
+  ss = ssh[0] + ssh[1];
+  si = sih[0] + sih[1];
 }
 
 template <int RPW, int P>
@@ -279,7 +299,7 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, con
   float tin;
   carry = carry_through<RPW>(cs, carry, tin);
   float st, ss, si, cl[4];
-  apply_lane<P, FEAT, TAIL, FT>(fmaxf(cs.ea, tin + cs.eb), dr, lane_first_customer<RPW, P>(base),
+  apply_lane<P, FEAT, TAIL, FT>(fmaxf(cs.ea, tin + cs.eb), cs, dr, lane_first_customer<RPW, P>(base),
                                 d.n, K, d.ea, d.es, st, ss, si, ft, cl);
   acc.t.add(st);
   acc.s.add(ss);
@@ -305,9 +325,9 @@ __device__ __forceinline__ void fixup_chunk(uint64_t base, const Draw<P> &dr, co
   const uint64_t n0 = lane_first_customer<1, P>(base);
   Feat none;
   float tt, st_, it, ts, ss_, is, clt[4], cls[4];
-  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_t + cs.eb), dr, n0, d.n, 0, d.ea, d.es, tt, st_,
+  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_t + cs.eb), cs, dr, n0, d.n, 0, d.ea, d.es, tt, st_,
                                  it, none, clt);
-  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_s + cs.eb), dr, n0, d.n, 0, d.ea, d.es, ts, ss_,
+  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_s + cs.eb), cs, dr, n0, d.n, 0, d.ea, d.es, ts, ss_,
                                  is, none, cls);
   acc.t.add(tt - ts);
   acc.i.add(it - is);
@@ -716,7 +736,7 @@ struct SplitShared {
   static constexpr int NF = STASH ? X - 1 : 1;
   float spec[split_slots<X>()][X], fin[split_slots<X>()][X];
   float sum[split_slots<X>()][X][7];  // W, T, I, then the four controls
-  float first[split_slots<X>()][NF][STASH ? 2 * MM1_P + 2 : 1][64];
+  float first[split_slots<X>()][NF][STASH ? 2 * MM1_P + 4 : 1][64];
   float first_t[split_slots<X>()][NF][8];
 };
 
@@ -783,6 +803,8 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
       }
       st[2 * P][lane] = cs.ea;
       st[2 * P + 1][lane] = cs.eb;
+      st[2 * P + 2][lane] = cs.ha;
+      st[2 * P + 3][lane] = cs.hb;
       if (lane == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -823,6 +845,8 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
       }
       scan.ea = st[2 * P][lane];
       scan.eb = st[2 * P + 1][lane];
+      scan.ha = st[2 * P + 2][lane];
+      scan.hb = st[2 * P + 3][lane];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         scan.ta[j] = sh.first_t[slot][h - 1][j];
@@ -837,7 +861,7 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
     {
       Feat none;
       float stt, ss, si, cl[4];
-      apply_lane<P, false, false, FT>(fmaxf(scan.ea, tin + scan.eb), dr,
+      apply_lane<P, false, false, FT>(fmaxf(scan.ea, tin + scan.eb), scan, dr,
                                       lane_first_customer<1, P>((uint64_t)cb * CHUNK), d.n, 0,
                                       d.ea, d.es, stt, ss, si, none, cl);
       fix.t.add(stt);
