@@ -56,9 +56,12 @@ __device__ __forceinline__ uint32_t word_of(const Block4 &b, uint32_t j) {
 // significant bits), and the fused multiply-add is exact because its result
 // k * 2^-24, k <= 2^24, is representable; one instruction fewer than shift,
 // add, convert, scale.
-__device__ __forceinline__ float exp_variate(uint32_t x, float neg_mean_ln2) {
+__device__ __forceinline__ float log2_u01(uint32_t x) {
   const float u = __builtin_fmaf((float)(x & 0xFFFFFF00u), 0x1p-32f, 0x1p-24f);
-  return neg_mean_ln2 * __builtin_amdgcn_logf(u);
+  return __builtin_amdgcn_logf(u);
+}
+__device__ __forceinline__ float exp_variate(uint32_t x, float neg_mean_ln2) {
+  return neg_mean_ln2 * log2_u01(x);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

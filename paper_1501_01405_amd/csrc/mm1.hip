@@ -41,10 +41,23 @@ namespace {
 
 constexpr float kNegInf = -__builtin_huge_valf();
 
+// The later of two times counted in the wavefront engines' negative unit,
+// and the value there of a time before all others (the constant part of
+// the identity map).
+__device__ __forceinline__ float later(float a, float b) { return fminf(a, b); }
+constexpr float kBeforeAll = __builtin_huge_valf();
+
 struct Rep {
   uint32_t dp, rep;
   uint64_t n;        // customers (0 = empty slot)
   float ca, cs;      // -(1/lambda) ln 2, -(1/mu) ln 2
+  // The wavefront engines count time in units of cs (negative): a service
+  // time is then S = log2 u exactly and an interarrival time A = qa log2 u
+  // with qa = ca / cs, one multiplication per customer fewer. The unit's
+  // sign turns every maximum of times into a minimum of their values
+  // (`later`); sums, the largest wait and the T-weighted controls are
+  // scaled back by cs when written.
+  float qa;
   float lambda, mu;
   float ea, es;      // means of the A and S variates as drawn (control centring)
   uint64_t out;      // output index
@@ -98,10 +111,10 @@ __device__ __forceinline__ Draw<P> draw_chunk(uint64_t base, const Rep &d, uint3
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const Block4 b = philox((uint32_t)(kb + j), d.dp, d.rep, TAG_MM1, k0, k1);
-    r.A[2 * j] = exp_variate(b.x, d.ca);
-    r.S[2 * j] = exp_variate(b.y, d.cs);
-    r.A[2 * j + 1] = exp_variate(b.z, d.ca);
-    r.S[2 * j + 1] = exp_variate(b.w, d.cs);
+    r.A[2 * j] = d.qa * log2_u01(b.x);
+    r.S[2 * j] = log2_u01(b.y);
+    r.A[2 * j + 1] = d.qa * log2_u01(b.z);
+    r.S[2 * j + 1] = log2_u01(b.w);
   }
   return r;
 }
@@ -133,19 +146,19 @@ __device__ __forceinline__ ChunkScan compose_scan(const Draw<P> &dr) {
 #pragma unroll
   for (int j = 1; j < H; ++j) {
     const float c0 = dr.S[j] - dr.A[j];
-    a0 = fmaxf(dr.S[j], a0 + c0);
+    a0 = later(dr.S[j], a0 + c0);
     b0 = b0 + c0;
     const float c1 = dr.S[H + j] - dr.A[H + j];
-    a1 = fmaxf(dr.S[H + j], a1 + c1);
+    a1 = later(dr.S[H + j], a1 + c1);
     b1 = b1 + c1;
   }
-  float a = fmaxf(a1, a0 + b1);
+  float a = later(a1, a0 + b1);
   float bb = b0 + b1;
 #define MRIP_SCAN_STEP(N)                              \
   {                                                    \
-    const float as = row_shr<N>(a, kNegInf);           \
+    const float as = row_shr<N>(a, kBeforeAll);        \
     const float bs = row_shr<N>(bb, 0.0f);             \
-    a = fmaxf(a, as + bb);                             \
+    a = later(a, as + bb);                             \
     bb = bs + bb;                                      \
   }
   MRIP_SCAN_STEP(1)
@@ -156,7 +169,7 @@ __device__ __forceinline__ ChunkScan compose_scan(const Draw<P> &dr) {
   ChunkScan r;
   r.ha = a0;
   r.hb = b0;
-  r.ea = row_shr<1>(a, kNegInf);
+  r.ea = row_shr<1>(a, kBeforeAll);
   r.eb = row_shr<1>(bb, 0.0f);
   r.ta[0] = readlane_f(a, 15);
   r.ta[1] = readlane_f(a, 31);
@@ -189,7 +202,7 @@ __device__ __forceinline__ float carry_through(const ChunkScan &cs, float carry,
       tb = pick4(q * S + j, cs.tb[0], cs.tb[1], cs.tb[2], cs.tb[3]);
     }
     tin = (j == s) ? cur : tin;
-    cur = fmaxf(ta, cur + tb);
+    cur = later(ta, cur + tb);
   }
   return cur;
 }
@@ -206,13 +219,13 @@ __device__ __forceinline__ float carry_through(const ChunkScan &cs, float carry,
 // term has mean zero given the past.
 template <int P, bool FEAT, bool TAIL, bool FT>
 __device__ __forceinline__ void apply_lane(float T0, const ChunkScan &cs, const Draw<P> &dr,
-                                           uint64_t n0, uint64_t n, uint64_t K, float ea, float es,
-                                           float &st, float &ss, float &si, Feat &ft,
-                                           float (&cl)[4]) {
+                                           uint64_t n0, uint64_t n, uint64_t K, float unit,
+                                           float ea, float es, float &st, float &ss, float &si,
+                                           Feat &ft, float (&cl)[4]) {
   constexpr int H = P / 2;
   // the two halves side by side, the second from max(ha, T0 + hb), the
   // system time the first half's map gives; each half sums on its own
-  float Th[2] = {T0, fmaxf(cs.ha, T0 + cs.hb)};
+  float Th[2] = {T0, later(cs.ha, T0 + cs.hb)};
   float sth[2] = {0.0f, 0.0f}, ssh[2] = {0.0f, 0.0f}, sih[2] = {0.0f, 0.0f};
   if (FT) cl[0] = cl[1] = cl[2] = cl[3] = 0.0f;
 #pragma unroll
@@ -223,7 +236,8 @@ __device__ __forceinline__ void apply_lane(float T0, const ChunkScan &cs, const 
       bool v = true;
       if (FEAT) v = n0 + j >= K;
       if (TAIL) v = v && n0 + j < n;
-      const float da = dr.A[j] - ea, ds = dr.S[j] - es;
+      // the centred variates in time (T-weighted sums stay in the unit)
+      const float da = __builtin_fmaf(unit, dr.A[j], -ea), ds = __builtin_fmaf(unit, dr.S[j], -es);
       if (FEAT) {  // customers < K <= n: the prefix four
         const bool p = n0 + j < K;
         ft.pc[0] += p ? ds : 0.0f;
@@ -248,16 +262,16 @@ __device__ __forceinline__ void apply_lane(float T0, const ChunkScan &cs, const 
       // I = max(0, A - T) = W - (T - A) exactly: A - T = -(T - A) in IEEE
       // arithmetic, and W is either 0 or T - A
       const float dlt = T - dr.A[j];
-      const float W = fmaxf(0.0f, dlt);
+      const float W = later(0.0f, dlt);
       ft.sa += f ? dr.A[j] : 0.0f;
       ft.ss += f ? dr.S[j] : 0.0f;
       ft.sw += f ? W : 0.0f;
       ft.si += f ? W - dlt : 0.0f;
       ft.zeros += (f && W == 0.0f);
-      ft.wmax = fmaxf(ft.wmax, f ? W : 0.0f);
+      ft.wmax = later(ft.wmax, f ? W : 0.0f);
     }
     const float x = T + (dr.S[j] - dr.A[j]);
-    T = fmaxf(x, dr.S[j]);
+    T = later(x, dr.S[j]);
     const float I = T - x;
     if (TAIL) {
       const bool v = n0 + j < n;
@@ -299,8 +313,8 @@ __device__ __forceinline__ void wave_chunk(uint64_t base, const Draw<P> &dr, con
   float tin;
   carry = carry_through<RPW>(cs, carry, tin);
   float st, ss, si, cl[4];
-  apply_lane<P, FEAT, TAIL, FT>(fmaxf(cs.ea, tin + cs.eb), cs, dr, lane_first_customer<RPW, P>(base),
-                                d.n, K, d.ea, d.es, st, ss, si, ft, cl);
+  apply_lane<P, FEAT, TAIL, FT>(later(cs.ea, tin + cs.eb), cs, dr, lane_first_customer<RPW, P>(base),
+                                d.n, K, d.cs, d.ea, d.es, st, ss, si, ft, cl);
   acc.t.add(st);
   acc.s.add(ss);
   acc.i.add(si);
@@ -325,9 +339,9 @@ __device__ __forceinline__ void fixup_chunk(uint64_t base, const Draw<P> &dr, co
   const uint64_t n0 = lane_first_customer<1, P>(base);
   Feat none;
   float tt, st_, it, ts, ss_, is, clt[4], cls[4];
-  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_t + cs.eb), cs, dr, n0, d.n, 0, d.ea, d.es, tt, st_,
+  apply_lane<P, false, TAIL, FT>(later(cs.ea, tin_t + cs.eb), cs, dr, n0, d.n, 0, d.cs, d.ea, d.es, tt, st_,
                                  it, none, clt);
-  apply_lane<P, false, TAIL, FT>(fmaxf(cs.ea, tin_s + cs.eb), cs, dr, n0, d.n, 0, d.ea, d.es, ts, ss_,
+  apply_lane<P, false, TAIL, FT>(later(cs.ea, tin_s + cs.eb), cs, dr, n0, d.n, 0, d.cs, d.ea, d.es, ts, ss_,
                                  is, none, cls);
   acc.t.add(tt - ts);
   acc.i.add(it - is);
@@ -385,25 +399,30 @@ __device__ void wave_group(const Rep &d, Src &src, uint64_t K, const Mm1Args &a)
     const float kf = (float)K;
     f[0] = d.lambda / d.mu;
     f[1] = d.mu;
-    f[2] = group_sum_compensated(ft.sa, WIDTH) / kf;
-    f[3] = group_sum_compensated(ft.ss, WIDTH) / kf;
-    f[4] = group_sum_compensated(ft.sw, WIDTH) / kf;
-    f[5] = group_sum_compensated(ft.st, WIDTH) / kf;
+    f[2] = group_sum_compensated(ft.sa, WIDTH) * d.cs / kf;
+    f[3] = group_sum_compensated(ft.ss, WIDTH) * d.cs / kf;
+    f[4] = group_sum_compensated(ft.sw, WIDTH) * d.cs / kf;
+    f[5] = group_sum_compensated(ft.st, WIDTH) * d.cs / kf;
     f[6] = (float)group_sum_i(ft.zeros, WIDTH) / kf;
-    f[7] = group_max(ft.wmax, WIDTH);
-    f[8] = group_sum_compensated(ft.si, WIDTH) / kf;
-    f[9] = group_sum_compensated(ft.tlast, WIDTH);
+    f[7] = group_max(-ft.wmax, WIDTH) * -d.cs;  // the latest of the waits
+    f[8] = group_sum_compensated(ft.si, WIDTH) * d.cs / kf;
+    f[9] = group_sum_compensated(ft.tlast, WIDTH) * d.cs;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       cl[k] = group_sum_compensated(acc.c[k].value(), WIDTH);
       cl[4 + k] = group_sum_compensated(ft.pc[k], WIDTH);
     }
+    // the T-weighted controls, from the unit
+    cl[2] *= d.cs;
+    cl[3] *= d.cs;
+    cl[6] *= d.cs;
+    cl[7] *= d.cs;
   }
   if ((lane % WIDTH) == 0 && d.n > 0) {
     const float nf = (float)d.n;
-    a.mean_w[d.out] = sw / nf;
-    a.mean_t[d.out] = st / nf;
-    a.mean_i[d.out] = si / nf;
+    a.mean_w[d.out] = sw * d.cs / nf;
+    a.mean_t[d.out] = st * d.cs / nf;
+    a.mean_i[d.out] = si * d.cs / nf;
     if (FT) {
 #pragma unroll
       for (int j = 0; j < 10; ++j) a.features[d.out * 10 + j] = f[j];
@@ -431,6 +450,7 @@ __device__ __forceinline__ Rep uniform_rep(const Mm1Args &a, uint64_t r, float c
   d.n = r < a.n_reps ? a.customers : 0;
   d.ca = ca;
   d.cs = cs;
+  d.qa = ca / cs;
   d.lambda = a.lambda;
   d.mu = a.mu;
   d.ea = a.ea;
@@ -457,6 +477,7 @@ __device__ __forceinline__ Rep item_rep(const Mm1Args &a, uint64_t slot, uint64_
   }
   d.ca = neg_mean_ln2(d.lambda);
   d.cs = neg_mean_ln2(d.mu);
+  d.qa = d.ca / d.cs;
   d.ea = d.es = 0.0f;
   if (a.feature_prefix > 0) {
     d.ea = variate_mean(d.lambda, a.log_grid_mean);
@@ -861,9 +882,9 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
     {
       Feat none;
       float stt, ss, si, cl[4];
-      apply_lane<P, false, false, FT>(fmaxf(scan.ea, tin + scan.eb), scan, dr,
+      apply_lane<P, false, false, FT>(later(scan.ea, tin + scan.eb), scan, dr,
                                       lane_first_customer<1, P>((uint64_t)cb * CHUNK), d.n, 0,
-                                      d.ea, d.es, stt, ss, si, none, cl);
+                                      d.cs, d.ea, d.es, stt, ss, si, none, cl);
       fix.t.add(stt);
       fix.s.add(ss);
       fix.i.add(si);
@@ -926,14 +947,14 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
     const float kf = (float)K;
     f[0] = d.lambda / d.mu;
     f[1] = d.mu;
-    f[2] = group_sum_compensated(ft.sa, 64) / kf;
-    f[3] = group_sum_compensated(ft.ss, 64) / kf;
-    f[4] = group_sum_compensated(ft.sw, 64) / kf;
-    f[5] = group_sum_compensated(ft.st, 64) / kf;
+    f[2] = group_sum_compensated(ft.sa, 64) * d.cs / kf;
+    f[3] = group_sum_compensated(ft.ss, 64) * d.cs / kf;
+    f[4] = group_sum_compensated(ft.sw, 64) * d.cs / kf;
+    f[5] = group_sum_compensated(ft.st, 64) * d.cs / kf;
     f[6] = (float)group_sum_i(ft.zeros, 64) / kf;
-    f[7] = group_max(ft.wmax, 64);
-    f[8] = group_sum_compensated(ft.si, 64) / kf;
-    f[9] = group_sum_compensated(ft.tlast, 64);
+    f[7] = group_max(-ft.wmax, 64) * -d.cs;  // the latest of the waits
+    f[8] = group_sum_compensated(ft.si, 64) * d.cs / kf;
+    f[9] = group_sum_compensated(ft.tlast, 64) * d.cs;
   }
   if (lane == 0) {
 #pragma unroll
@@ -955,16 +976,16 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
       tot[k] = hi + lo;
     }
     const float nf = (float)d.n;
-    a.mean_w[d.out] = tot[0] / nf;
-    a.mean_t[d.out] = tot[1] / nf;
-    a.mean_i[d.out] = tot[2] / nf;
+    a.mean_w[d.out] = tot[0] * d.cs / nf;
+    a.mean_t[d.out] = tot[1] * d.cs / nf;
+    a.mean_i[d.out] = tot[2] * d.cs / nf;
     if (FT && K > 0) {
 #pragma unroll
       for (int j = 0; j < 10; ++j) a.features[d.out * 10 + j] = f[j];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        a.controls[d.out * 8 + k] = tot[3 + k];
-        a.controls[d.out * 8 + 4 + k] = pcs[k];
+      for (int k = 0; k < 4; ++k) {  // the T-weighted two from the unit
+        a.controls[d.out * 8 + k] = k >= 2 ? tot[3 + k] * d.cs : tot[3 + k];
+        a.controls[d.out * 8 + 4 + k] = k >= 2 ? pcs[k] * d.cs : pcs[k];
       }
     }
   }
