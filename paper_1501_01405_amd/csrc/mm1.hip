@@ -912,15 +912,25 @@ __device__ __forceinline__ void split_replication(const Rep &d, int slot, int h,
   __syncthreads();
 
   // phase 3: in order, only where the assumed start was not the true one
-  // (kept rolled: one copy of the correction instead of X - 1)
+  // (kept rolled: one copy of the correction instead of X - 1). It runs at
+  // all only if some part of some replication of the workgroup started from
+  // a wrong end, a decision the whole workgroup shares (it holds barriers).
+  bool wrong = false;
+#pragma unroll
+  for (int s2 = 0; s2 < split_slots<X>(); ++s2)
+#pragma unroll
+    for (int j = 1; j < X; ++j)
+      wrong |= __float_as_uint(sh.fin[s2][j - 1]) != __float_as_uint(sh.spec[s2][j - 1]);
+  if (__builtin_amdgcn_readfirstlane((int)wrong)) {
 #pragma unroll 1
-  for (int j = 1; j < X; ++j) {
-    if (split && h == j &&
-        __float_as_uint(sh.fin[slot][j - 1]) != __float_as_uint(sh.spec[slot][j - 1])) {
-      const float f = correct(sh.fin[slot][j - 1]);
-      if (lane == 0) sh.fin[slot][j] = f;
+    for (int j = 1; j < X; ++j) {
+      if (split && h == j &&
+          __float_as_uint(sh.fin[slot][j - 1]) != __float_as_uint(sh.spec[slot][j - 1])) {
+        const float f = correct(sh.fin[slot][j - 1]);
+        if (lane == 0) sh.fin[slot][j] = f;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   acc.t.add(fix.t.value());
   acc.s.add(fix.s.value());
