@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -532,28 +533,44 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
   Taus t0 = taus_seed(TAG_MM1, 0u, (uint32_t)r, k0, k1);
   taus_skip(t0, 2 * n0, a.taus);
 
-  // pass 1: the run's composite map T -> max(ma, T + mb)
-  float ma = kNegInf, mb = 0.0f;
+  // Time is counted in the unit cs < 0, as in the wavefront engines: a
+  // service time is log2 u, an interarrival time qa log2 u, and maxima of
+  // times are minima of their values (`later`).
+  const float qa = ca / cs;
+  const uint32_t m = (uint32_t)(n1 - n0);  // customers of this lane's run
+
+  // pass 1: the run's composite map T -> later(ma, T + mb)
+  float ma = kBeforeAll, mb = 0.0f;
   Taus t = t0;
-  for (uint64_t n = n0; n < n1; ++n) {
-    const float A = exp_variate(taus_next(t), ca);
-    const float S = exp_variate(taus_next(t), cs);
-    const float bj = S - A;
-    ma = fmaxf(S, ma + bj);
-    mb = mb + bj;
+  {
+    auto step = [&]() {
+      const float A = qa * log2_u01(taus_next(t));
+      const float S = log2_u01(taus_next(t));
+      const float bj = S - A;
+      ma = later(S, ma + bj);
+      mb = mb + bj;
+    };
+    uint32_t i = 0;
+    for (; i + 4 <= m; i += 4) {
+      step();
+      step();
+      step();
+      step();
+    }
+    for (; i < m; ++i) step();
   }
   // inclusive scan in lane order (earlier runs first)
 #pragma unroll
   for (int o = 1; o < G; o <<= 1) {
     const float pa = __shfl_up(ma, o, G), pb = __shfl_up(mb, o, G);
     if (g >= o) {
-      ma = fmaxf(ma, pa + mb);
+      ma = later(ma, pa + mb);
       mb = pb + mb;
     }
   }
   float ea = __shfl_up(ma, 1, G), eb = __shfl_up(mb, 1, G);
   if (g == 0) {
-    ea = kNegInf;
+    ea = kBeforeAll;
     eb = 0.0f;
   }
   // system time entering this wavefront's part of the replication
@@ -564,82 +581,97 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
       sh_b[wave] = mb;
     }
     __syncthreads();
-    for (int w = wave - j / 64; w < wave; ++w) carry = fmaxf(sh_a[w], carry + sh_b[w]);
+    for (int w = wave - j / 64; w < wave; ++w) carry = later(sh_a[w], carry + sh_b[w]);
   }
-  float T = fmaxf(ea, carry + eb);
+  float T = later(ea, carry + eb);
 
-  // pass 2: Lindley's recursion over the run, from the saved stream state
+  // pass 2: Lindley's recursion over the run, from the saved stream state,
+  // in the map form of the wavefront engines: x = T + S - A, T <- later(x,
+  // S), I = T - x; sums of T, S and I, the waits as their difference
   t = t0;
-  Kahan kw, kt, ki;
+  Kahan kt, ks, ki;
   Feat ft;
-  uint64_t n = n0;
-  const uint64_t nf = min(n1, max(n0, K));  // customers of the feature prefix
-  for (; n < nf; ++n) {  // the prefix: features and the prefix controls
-    const float A = exp_variate(taus_next(t), ca);
-    const float S = exp_variate(taus_next(t), cs);
-    const float ds = S - a.es, da = A - a.ea;
+  uint32_t i = 0;
+  const uint32_t mf = (uint32_t)(min(n1, max(n0, K)) - n0);  // customers of the feature prefix
+  for (; i < mf; ++i) {  // the prefix: features and the prefix controls
+    const float A = qa * log2_u01(taus_next(t));
+    const float S = log2_u01(taus_next(t));
+    const float ds = __builtin_fmaf(cs, S, -a.es), da = __builtin_fmaf(cs, A, -a.ea);
     ft.pc[0] += ds;
     ft.pc[1] += da;
     ft.pc[2] = __builtin_fmaf(T, ds, ft.pc[2]);
     ft.pc[3] = __builtin_fmaf(T, da, ft.pc[3]);
     const float dlt = T - A;
-    const float W = fmaxf(0.0f, dlt);
-    const float I = W - dlt;
-    T = W + S;
-    kw.add(W);
+    const float W = later(0.0f, dlt);
+    const float x = T + (S - A);
+    T = later(x, S);
     kt.add(T);
-    ki.add(I);
+    ks.add(S);
+    ki.add(T - x);
     ft.sa += A;
     ft.ss += S;
     ft.sw += W;
     ft.st += T;
-    ft.si += I;
+    ft.si += W - dlt;
     ft.zeros += (W == 0.0f);
-    ft.wmax = fmaxf(ft.wmax, W);
-    if (n + 1 == K) ft.tlast = T;
+    ft.wmax = later(ft.wmax, W);
+    if (n0 + i + 1 == K) ft.tlast = T;
   }
   // after the prefix (every customer from here on has n >= K): with K > 0,
-  // also the four controls, weighted by T_{n-1} where they are
+  // also the four controls, weighted by T_{n-1} where they are; plain fp32
+  // sums over 8 customers, then one compensated add each
   Kahan kc[4];
-  const bool ctl = K > 0;
-  while (n < n1) {
-    // plain fp32 sums over up to 8 customers, then one compensated add
-    const uint64_t ne = min(n1, n + 8);
-    float sw = 0.0f, st = 0.0f, si = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
-    for (; n < ne; ++n) {
-      const float A = exp_variate(taus_next(t), ca);
-      const float S = exp_variate(taus_next(t), cs);
-      if (ctl) {
-        const float ds = S - a.es, da = A - a.ea;
-        c0 += ds;
-        c1 += da;
-        c2 = __builtin_fmaf(T, ds, c2);
-        c3 = __builtin_fmaf(T, da, c3);
+  auto rest = [&](auto ctl_tag) {
+    constexpr bool CTL = decltype(ctl_tag)::value;
+    while (i < m) {
+      const uint32_t e = min(m, i + 8);
+      float st = 0.0f, ss = 0.0f, si = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
+      auto step = [&]() {
+        const float A = qa * log2_u01(taus_next(t));
+        const float S = log2_u01(taus_next(t));
+        if (CTL) {
+          const float ds = __builtin_fmaf(cs, S, -a.es), da = __builtin_fmaf(cs, A, -a.ea);
+          c0 += ds;
+          c1 += da;
+          c2 = __builtin_fmaf(T, ds, c2);
+          c3 = __builtin_fmaf(T, da, c3);
+        }
+        const float x = T + (S - A);
+        T = later(x, S);
+        st += T;
+        ss += S;
+        si += T - x;
+      };
+      if (e - i == 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) step();
+        i = e;
+      } else {
+        for (; i < e; ++i) step();
       }
-      const float dlt = T - A;
-      const float W = fmaxf(0.0f, dlt);
-      const float I = W - dlt;
-      T = W + S;
-      sw += W;
-      st += T;
-      si += I;
+      kt.add(st);
+      ks.add(ss);
+      ki.add(si);
+      if (CTL) {
+        kc[0].add(c0);
+        kc[1].add(c1);
+        kc[2].add(c2);
+        kc[3].add(c3);
+      }
     }
-    kw.add(sw);
-    kt.add(st);
-    ki.add(si);
-    if (ctl) {
-      kc[0].add(c0);
-      kc[1].add(c1);
-      kc[2].add(c2);
-      kc[3].add(c3);
-    }
-  }
+  };
+  if (K > 0)
+    rest(std::true_type{});
+  else
+    rest(std::false_type{});
 
-  // the replication's sums: lanes of the wavefront, then its wavefronts in
-  // order. v: W, T, I, then the features' A, S, W, T, zeros, max W, T_{K-1}, I,
-  // then the four controls after the prefix and the four over it
+  // the replication's sums (in the unit, except the count of zero waits and
+  // the largest wait, kept as -wmax so that the largest wait is a maximum):
+  // lanes of the wavefront, then its wavefronts in order. v: W, T, I, then
+  // the features' A, S, W, T, zeros, max W, T_{K-1}, I, then the four
+  // controls after the prefix and the four over it
   float v[19];
-  v[0] = group_sum_compensated(kw.value(), G);
+  v[0] = group_sum_compensated((kt.sum - ks.sum) - (kt.comp - ks.comp), G);
   v[1] = group_sum_compensated(kt.value(), G);
   v[2] = group_sum_compensated(ki.value(), G);
   v[3] = group_sum_compensated(ft.sa, G);
@@ -647,7 +679,7 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
   v[5] = group_sum_compensated(ft.sw, G);
   v[6] = group_sum_compensated(ft.st, G);
   v[7] = (float)group_sum_i(ft.zeros, G);
-  v[8] = group_max(ft.wmax, G);
+  v[8] = group_max(-ft.wmax, G);
   v[9] = group_sum_compensated(ft.tlast, G);
   v[10] = group_sum_compensated(ft.si, G);
 #pragma unroll
@@ -681,24 +713,27 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
   }
   if (j == 0 && N > 0) {
     const float nf_ = (float)N;
-    a.mean_w[r] = v[0] / nf_;
-    a.mean_t[r] = v[1] / nf_;
-    a.mean_i[r] = v[2] / nf_;
+    a.mean_w[r] = v[0] * cs / nf_;
+    a.mean_t[r] = v[1] * cs / nf_;
+    a.mean_i[r] = v[2] * cs / nf_;
     if (K > 0) {
       const float kf = (float)K;
       float *f = a.features + r * 10;
       f[0] = a.lambda / a.mu;
       f[1] = a.mu;
-      f[2] = v[3] / kf;
-      f[3] = v[4] / kf;
-      f[4] = v[5] / kf;
-      f[5] = v[6] / kf;
+      f[2] = v[3] * cs / kf;
+      f[3] = v[4] * cs / kf;
+      f[4] = v[5] * cs / kf;
+      f[5] = v[6] * cs / kf;
       f[6] = v[7] / kf;
-      f[7] = v[8];
-      f[8] = v[10] / kf;
-      f[9] = v[9];
+      f[7] = v[8] * -cs;
+      f[8] = v[10] * cs / kf;
+      f[9] = v[9] * cs;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) a.controls[r * 8 + k] = v[11 + k];
+      for (int k = 0; k < 4; ++k) {  // the T-weighted two from the unit
+        a.controls[r * 8 + k] = k >= 2 ? v[11 + k] * cs : v[11 + k];
+        a.controls[r * 8 + 4 + k] = k >= 2 ? v[15 + k] * cs : v[15 + k];
+      }
     }
   }
 }
