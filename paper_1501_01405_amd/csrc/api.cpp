@@ -296,6 +296,15 @@ mrip_status upload_taus_tables(mrip_ctx c) {
     HIP_TRY(c, hipMemcpy(c->taus_tables.p, host.data(), host.size() * sizeof(uint32_t),
                          hipMemcpyHostToDevice));
   }
+  if (c->model == MRIP_MM1 && !c->taus_run.p) {
+    // each lane of an M/M/1 replication reaches its run with one table per
+    // set bit of its index
+    std::vector<uint32_t> host((size_t)TAUS_RUN_TABLES * TAUS_COLS);
+    taus_build_run_tables(c->mm1.customers, host.data());
+    HIP_TRY(c, c->taus_run.ensure(host.size() * sizeof(uint32_t)));
+    HIP_TRY(c, hipMemcpy(c->taus_run.p, host.data(), host.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice));
+  }
   if (c->model == MRIP_RW && !c->taus_walk.p) {
     // the walk's lanes reach their place with one table per level
     std::vector<uint32_t> host((size_t)TAUS_WALK_TABLES * TAUS_COLS);
@@ -616,6 +625,7 @@ mrip_status mrip_run(mrip_ctx ctx, uint64_t n_reps, uint64_t seed, void *hip_str
     a.mean_i = (float *)outp[2];
     a.rng = ctx->rng;
     a.taus = ctx->taus_tables.as<uint32_t>();
+    a.taus_run = ctx->taus_run.as<uint32_t>();
     if (a.feature_prefix > 0) {
       st = output_buffer(ctx, set, 3, n_reps * 40, &outp[3]);
       if (st != MRIP_OK) return st;

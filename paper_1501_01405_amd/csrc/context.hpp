@@ -136,6 +136,7 @@ struct mrip_ctx_s {
   mrip::DevBuf scratch;
   mrip::DevBuf walker_scratch;  // the walk's per-walker bitmaps
   mrip::DevBuf taus_walk;       // the walk's taus88 jump tables (its steps are fixed)
+  mrip::DevBuf taus_run;        // the M/M/1 runs' taus88 jump tables (customers are fixed)
   // (n, mean, var) per scalar output: pinned host memory written by the
   // reduction kernel through its device view
   // A ring of STATS_RING slots, one per run, so a caller may read run k's

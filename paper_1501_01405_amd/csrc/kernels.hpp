@@ -81,6 +81,7 @@ struct Mm1Args {
   uint64_t *prev_seq;
   uint64_t prev_seq_value;
   uint8_t *done;                // plan mode (nullable): done[i] = 1 once item i's outputs are written
+  const uint32_t *taus_run;     // taus88: the runs' jump tables (taus_build_run_tables)
 };
 // Mean of -ln u over the 24-bit grid of u, {k 2^-24 : k = 1..2^24}, and
 // the fp32 mean of the exponential variate of `rate` as drawn, (float)(1 /

@@ -531,7 +531,14 @@ __global__ __launch_bounds__(256) void mm1_taus_kernel(Mm1Args a, float ca, floa
   const uint64_t n0 = min(N, (uint64_t)j * B), n1 = min(N, n0 + B);
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   Taus t0 = taus_seed(TAG_MM1, 0u, (uint32_t)r, k0, k1);
-  taus_skip(t0, 2 * n0, a.taus);
+  // to the lane's run, 2 j B outputs in: one table per set bit of j (a lane
+  // past the replication's end has no customers, and its place is unused)
+  {
+    const uint32_t *tb = a.taus_run + (uint64_t)taus_run_base(LPR) * TAUS_COLS;
+#pragma unroll
+    for (int i = 0; (1 << i) < LPR; ++i)
+      if ((j >> i) & 1) taus_jump(t0, tb + (uint64_t)i * TAUS_COLS);
+  }
 
   // Time is counted in the unit cs < 0, as in the wavefront engines: a
   // service time is log2 u, an interarrival time qa log2 u, and maxima of

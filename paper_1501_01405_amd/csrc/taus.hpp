@@ -44,6 +44,16 @@ void taus_build_tables(uint32_t *out);
 constexpr uint32_t TAUS_WALK_WALKERS = 64, TAUS_WALK_SEGMENTS = 16;
 constexpr uint32_t TAUS_WALK_TABLES = TAUS_WALK_WALKERS + TAUS_WALK_SEGMENTS;
 void taus_build_walk_tables(uint32_t steps, uint32_t *out);
+// Host: the M/M/1 runs' jump tables for replications of `customers`
+// customers. With L lanes per replication (16, 32, 64, 128 or 256) lane j
+// takes the run of B = ceil(customers / L) customers starting at j B, 2 j B
+// outputs into the stream; table i of L's group advances 2 B 2^i outputs,
+// so a lane reaches its run with one table per set bit of j.
+constexpr uint32_t TAUS_RUN_TABLES = 4 + 5 + 6 + 7 + 8;
+constexpr uint32_t taus_run_base(uint32_t lanes) {
+  return lanes == 16 ? 0u : lanes == 32 ? 4u : lanes == 64 ? 9u : lanes == 128 ? 15u : 22u;
+}
+void taus_build_run_tables(uint64_t customers, uint32_t *out);
 
 #if defined(__HIPCC__)
 struct Taus {

@@ -89,6 +89,14 @@ void store_jump(uint64_t d, uint32_t *out) {
 
 }  // namespace
 
+void taus_build_run_tables(uint64_t customers, uint32_t *out) {
+  for (uint32_t lanes = 16; lanes <= 256; lanes *= 2) {
+    const uint64_t run = (customers + lanes - 1) / lanes;  // customers per lane
+    uint32_t *t = out + (size_t)taus_run_base(lanes) * TAUS_COLS;
+    for (uint32_t i = 0; (1u << i) < lanes; ++i) store_jump(2 * run << i, t + (size_t)i * TAUS_COLS);
+  }
+}
+
 void taus_build_tables(uint32_t *out) {
   const Pow2 &p = pow2();
   for (int j = 0; j < TAUS_POW2; ++j) store(p.m[j], out + (size_t)j * TAUS_COLS);
