@@ -40,8 +40,6 @@ namespace mrip {
 
 namespace {
 
-constexpr float kNegInf = -__builtin_huge_valf();
-
 // The later of two times counted in the wavefront engines' negative unit,
 // and the value there of a time before all others (the constant part of
 // the identity map).

@@ -515,12 +515,17 @@ __global__ __launch_bounds__(1024) void rw_seg_kernel(RwArgs a, uint32_t seg) {
 // Replications up to which the segmented form is used (measured for 64
 // walkers x 1000 steps: 44 against 83 us at 1024 replications, 79 against
 // 87 at 2048, 149 against 146 at 4096): below, the sequential form leaves
-// the chip idle; above, its single pass over the moves is cheaper.
+// the chip idle; above, its single pass over the moves is cheaper. On
+// taus88 streams every segment lane first jumps to its place (two tables
+// of 88 columns), so the sequential form wins earlier (64 x 1000: 39 against
+// 55 us at 128 replications, 57 against 56 at 512, 90 against 56 at 1024,
+// 148 against 78 at 2048).
 constexpr uint64_t RW_SEG_MAX_REPS = 2048;
+constexpr uint64_t RW_SEG_MAX_REPS_TAUS88 = 512;
 
 template <int GRID>
 hipError_t wave_launch(const RwArgs &a, uint32_t wg, hipStream_t s) {
-  if (a.n_reps <= RW_SEG_MAX_REPS) {
+  if (a.n_reps <= (a.rng == RNG_TAUS88 ? RW_SEG_MAX_REPS_TAUS88 : RW_SEG_MAX_REPS)) {
     // 16 lanes per walker; segments of whole Philox blocks (64 moves)
     const uint32_t threads = (16u * a.walkers + 63u) / 64u * 64u;
     const uint32_t seg = (a.steps + 16u * 64u - 1u) / (16u * 64u) * 64u;

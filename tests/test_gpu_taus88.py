@@ -172,11 +172,12 @@ def test_philox_only_paths_refuse_taus88(gpu):
 
 
 @pytest.mark.parametrize("steps", [1024, 1025, 2000])
-@pytest.mark.parametrize("R", [7, 2100])
+@pytest.mark.parametrize("R", [7, 512, 513, 2100])
 def test_rw_long_walks_in_both_wave_forms(gpu, steps, R):
     # segments of 128 moves (steps > 1024), trailing segments that start at
-    # or past the last move, and the one-lane-per-walker form above 2048
-    # replications: each lane reaches its place with one jump per level
+    # or past the last move, and the one-lane-per-walker form above 512
+    # replications on taus88 streams: each lane reaches its place with one
+    # jump per level
     announce("rw taus88 long walks", steps, R)
     ctx = _ctx(mrip.MRIP_RW, mrip.rw_params(64, 64, steps), WAVE)
     ctx.run(R, seed=9)
