@@ -177,31 +177,36 @@ def full_size_counters(mrip):
 
 def timed_steps(ctx, steps, warmup, torch, mrip):
     """K whole MRIP passes (replications, device reduction, interval). Run
-    k + 1 is enqueued before run k's interval is read (the library keeps each
-    run's statistics in its own slot), so the device does not wait for the
-    host between steps; every step's interval is still read."""
+    k's statistics are reduced inside run k + 1's kernel, so reading run k's
+    interval waits for that kernel: run k + 2 is enqueued first (the library
+    keeps each run's statistics in its own slot of a 4-run ring), and the
+    device never waits for the host between steps; every step's interval is
+    still read."""
     stream = torch.cuda.current_stream().cuda_stream
     # the kernel's own HIP events on one launch in TIMING_EVERY: each timed
     # launch costs a dispatch gap before the next kernel, the others run
     # back to back
     ctx.set_timing(TIMING_EVERY)
+
+    def loop(n, seed0):
+        for i in range(n):
+            ctx.run(R, seed=seed0 + i, stream=stream)
+            if i >= 2:
+                ctx.stats_back(2, 0)  # the interval of step i - 2
+        half = None
+        for back in range(min(n, 2) - 1, -1, -1):  # the last one or two
+            half = ctx.stats_back(back, 0)
+        return half
+
     # warm-up in the same pipelined form: under continuous work the kernel
     # settles within ~20 ms (about 130 runs) at its sustained speed, 5-10 %
     # faster than in the first milliseconds
-    for i in range(warmup):
-        ctx.run(R, seed=1000 + i, stream=stream)
-        if i > 0:
-            ctx.stats_back(1, 0)
     if warmup > 0:
-        ctx.stats(0)
+        loop(warmup, 1000)
     torch.cuda.synchronize()
     ctx.set_timing(TIMING_EVERY)  # timed launches: steps 0, TIMING_EVERY, ...
     t0 = time.perf_counter()
-    ctx.run(R, seed=42, stream=stream)
-    for i in range(1, steps):
-        ctx.run(R, seed=42 + i, stream=stream)
-        ctx.stats_back(1, 0)  # the interval of step i - 1
-    half = ctx.stats(0)  # the last step's interval closes the timed region
+    half = loop(steps, 42)  # the last step's interval closes the timed region
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kernel_ms = ctx.history_ms((steps + TIMING_EVERY - 1) // TIMING_EVERY)
