@@ -15,16 +15,19 @@
 // them in order as T <- max(a_tot, T + b_tot). Because every replication is
 // always cut into the same segments and the carry visits them in the same
 // order, the per-customer values do not depend on RPW or on the workgroup
-// size; only the summation order of the means does.
+// size; only the summation order of the means does. The wavefront engines
+// (and the taus88 one) count time in the negative unit -(1/mu) ln 2, in
+// which a service time is log2 u itself; there every maximum above is a
+// minimum (`later`), and results are scaled back when written.
 //
 // SIMT mapping (one replication per lane): the sequential recursion, one
 // customer after the other, as the paper's thread-per-replication form.
 //
 // On taus88 streams customer n takes outputs 2n (A) and 2n+1 (S) of the
 // replication's stream, a sequential generator: the wavefront engine gives
-// every lane a contiguous run of customers instead (mm1_taus_kernel: one
-// jump per lane, two passes over its run); a SIMT lane reads the stream in
-// order.
+// every lane a contiguous run of customers instead (mm1_taus_kernel: a
+// jump of one table per set bit of the lane's index, two passes over its
+// run); a SIMT lane reads the stream in order.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
