@@ -27,7 +27,7 @@ SPLIT = 4  # wavefronts per replication (four per SIMD at 1024 replications)
 # scaled by the same counter on a 256 MiB copy
 # (profiles/mm1_split_hbm_counters.md); to be re-measured (or set to None)
 # whenever the kernel changes.
-TRAFFIC_BYTES = ((216.6 + 208.1) / 2 * 2.00 + 2144.1 * 1.00) * 1024  # taken at SPLIT = 4
+TRAFFIC_BYTES = ((212.6 + 203.6) / 2 * 2.00 + 2144.1 * 1.00) * 1024  # taken at SPLIT = 4
 # One headline launch in TIMING_EVERY records its kernel's HIP events (the
 # kernel duration the roofline uses); the others carry no event.
 TIMING_EVERY = 8
