@@ -209,8 +209,9 @@ __device__ __forceinline__ float carry_through(const ChunkScan &cs, float carry,
   return cur;
 }
 
-// The lane's P customers in order, from the system time T before the first.
-// Each customer applies its map: x = T + b with b = S - A, T <- max(x, S)
+// The lane's P customers in order, from the system time T before the first
+// (times in the engines' unit, where the later of two is `later`). Each
+// customer applies its map: x = T + b with b = S - A, T <- later(x, S)
 // (Lindley's W = max(0, T - A), T = W + S with one rounding less), and its
 // idle time is I = T - x, exactly 0 whenever the server is busy. The lane
 // sums T, S and I (TAIL: only customers < n); the waits follow as T - S.
@@ -225,7 +226,7 @@ __device__ __forceinline__ void apply_lane(float T0, const ChunkScan &cs, const 
                                            float ea, float es, float &st, float &ss, float &si,
                                            Feat &ft, float (&cl)[4]) {
   constexpr int H = P / 2;
-  // the two halves side by side, the second from max(ha, T0 + hb), the
+  // the two halves side by side, the second from later(ha, T0 + hb), the
   // system time the first half's map gives; each half sums on its own
   float Th[2] = {T0, later(cs.ha, T0 + cs.hb)};
   float sth[2] = {0.0f, 0.0f}, ssh[2] = {0.0f, 0.0f}, sih[2] = {0.0f, 0.0f};
