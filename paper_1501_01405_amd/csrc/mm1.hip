@@ -229,8 +229,14 @@ __device__ __forceinline__ void apply_lane(float T0, const ChunkScan &cs, const 
   // the two halves side by side, the second from later(ha, T0 + hb), the
   // system time the first half's map gives; each half sums on its own
   float Th[2] = {T0, later(cs.ha, T0 + cs.hb)};
+  const float Ts[2] = {Th[0], Th[1]};  // the halves' starts
   float sth[2] = {0.0f, 0.0f}, ssh[2] = {0.0f, 0.0f}, sih[2] = {0.0f, 0.0f};
   if (FT) cl[0] = cl[1] = cl[2] = cl[3] = 0.0f;
+  // FT chunks with every customer counted (no feature prefix, no tail):
+  // the controls from raw sums, sum A, sum T_{n-1} S and sum T_{n-1} A,
+  // centred once per chunk (three operations per customer instead of six)
+  constexpr bool RAW = FT && !FEAT && !TAIL;
+  float qa = 0.0f, qts = 0.0f, qta = 0.0f;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int h = j >= H;
@@ -254,10 +260,9 @@ __device__ __forceinline__ void apply_lane(float T0, const ChunkScan &cs, const 
         cl[2] = v ? __builtin_fmaf(T, ds, cl[2]) : cl[2];
         cl[3] = v ? __builtin_fmaf(T, da, cl[3]) : cl[3];
       } else {
-        cl[0] += ds;
-        cl[1] += da;
-        cl[2] = __builtin_fmaf(T, ds, cl[2]);
-        cl[3] = __builtin_fmaf(T, da, cl[3]);
+        qa += dr.A[j];
+        qts = __builtin_fmaf(T, dr.S[j], qts);
+        qta = __builtin_fmaf(T, dr.A[j], qta);
       }
     }
     if (FEAT) {  // the prefix features, from their definitions
@@ -295,6 +300,15 @@ __device__ __forceinline__ void apply_lane(float T0, const ChunkScan &cs, const 
   st = sth[0] + sth[1];
   ss = ssh[0] + ssh[1];
   si = sih[0] + sih[1];
+  if (RAW) {
+    // sum of T_{n-1} over the lane: each half's start, plus its T's but
+    // the last
+    const float tp = (Ts[0] + (sth[0] - Th[0])) + (Ts[1] + (sth[1] - Th[1]));
+    cl[0] = __builtin_fmaf(unit, ss, -(float)P * es);
+    cl[1] = __builtin_fmaf(unit, qa, -(float)P * ea);
+    cl[2] = __builtin_fmaf(unit, qts, -es * tp);
+    cl[3] = __builtin_fmaf(unit, qta, -ea * tp);
+  }
 }
 
 template <int RPW, int P>
