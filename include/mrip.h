@@ -416,7 +416,7 @@ MRIP_API mrip_status mrip_tune_cache_put(const char *path, const char *key,
  * depends on customers 0..K-1 only, E[F] = 0 for any network: Y - a . F,
  * with a fixed beforehand per bin of rho, is unbiased for E[Y], and no
  * extra replications estimate E[F]. The plain estimate stays the fallback
- * and the judge of the error. */
+ * and the reference for its error. */
 
 #define MRIP_MLP_OUT 4        /* network outputs: one coefficient per control */
 #define MRIP_MLP_PARAMS 18436 /* W1[128x10] b1[128] W2[128x128] b2[128] W3[4x128] b3[4] */

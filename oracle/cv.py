@@ -8,7 +8,7 @@ beforehand (fitted on other replications),
 
 is unbiased for E[Y]; its variance estimate is s^2(Y - a . F)/n with a
 t_{n-1} interval. The plain estimate mean(Y) with its t_{n-1} interval is
-the fallback and the judge of the control's error.
+the fallback and the reference for the control's error.
 
 The controls are F = (h, z_pre): h = sum_k g_k(X) z_k with z the four
 martingale controls of the run after its first K customers (below) and
