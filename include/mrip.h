@@ -355,12 +355,18 @@ MRIP_API mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidenc
 /* Plans: items of at least long_min customers (0 = 65536) are each split
  * over waves_per_item (1, 2, 4 or 8) wavefronts of a workgroup, served first
  * (longest first) at raised wavefront priority, since the longest items set
- * the plan's makespan; the rest go reps_per_wave per wavefront. Default 8. */
+ * the plan's makespan; the rest go reps_per_wave per wavefront. Until this
+ * call (or mrip_autotune) fixes it, each plan run takes the fewest
+ * wavefronts per long item, up to 8, that bring its longest item's share
+ * down to the run's average work per wavefront the device holds at once
+ * (16 per compute unit): a plan of many equal long items is not split. */
 MRIP_API mrip_status mrip_set_plan_split(mrip_ctx ctx, uint32_t waves_per_item,
                                          uint64_t long_min);
 
 /* Current launch shape: reps_per_wave, workgroup and wavefronts per
- * replication of mrip_run, wavefronts per long plan item (any may be NULL). */
+ * replication of mrip_run, wavefronts per long plan item (any may be NULL;
+ * before mrip_set_plan_split or mrip_autotune fixes it, the most a plan run
+ * may use). */
 MRIP_API mrip_status mrip_get_shape(mrip_ctx ctx, uint32_t *reps_per_wave, uint32_t *workgroup,
                                     uint32_t *split, uint32_t *plan_split);
 

@@ -365,6 +365,24 @@ mrip_status validate(mrip_model model, const void *params, mrip_mapping map, std
 
 }  // namespace
 
+uint32_t mrip::plan_split_for(mrip_ctx ctx, uint64_t longest, uint64_t total) {
+  if (ctx->plan_split_set) return ctx->plan_split;
+  if (ctx->cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      ctx->cus = (uint32_t)n;
+    else
+      ctx->cus = 256;
+  }
+  // wavefronts the chip holds at once in the feature-free kernels: four
+  // per SIMD, four SIMDs per compute unit
+  const uint64_t slots = 16ull * ctx->cus;
+  uint32_t x = 1;
+  while (x < ctx->plan_split && (double)longest * (double)slots > (double)total * x) x *= 2;
+  return x;
+}
+
 extern "C" {
 
 const char *mrip_version(void) { return "mrip 0.1 (gfx950)"; }
@@ -458,6 +476,7 @@ mrip_status mrip_set_plan_split(mrip_ctx ctx, uint32_t waves_per_item, uint64_t 
     return inval(ctx, "waves_per_item must be 1, 2, 4 or 8");
   if (ctx->model != MRIP_MM1) return inval(ctx, "plans are defined for the M/M/1 engine");
   ctx->plan_split = waves_per_item;
+  ctx->plan_split_set = true;
   ctx->long_min = long_min > 0 ? long_min : 65536;
   return MRIP_OK;
 }
@@ -951,11 +970,14 @@ mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
   const uint64_t n_long =
       std::min<uint64_t>(count_long(ctx->lpt_customers, ctx->n_items, ctx->long_min), n_run);
   const bool whole = n_run == ctx->n_items;
+  uint64_t total = 0;
+  for (uint64_t j = 0; j < n_run; ++j) total += ctx->lpt_customers[j];
+  const uint32_t split = plan_split_for(ctx, ctx->lpt_customers[0], total);
   uint8_t *done = nullptr;
   mrip_status st = done_flags(ctx, &done);
   if (st != MRIP_OK) return st;
   st = run_plan_impl(ctx, seed, (hipStream_t)hip_stream, ctx->it_order.as<uint32_t>(), n_run,
-                     n_long, ctx->plan_rpw, ctx->plan_wg, ctx->plan_split, whole, done, true);
+                     n_long, ctx->plan_rpw, ctx->plan_wg, split, whole, done, true);
   if (st != MRIP_OK) return st;
   ctx->last = whole ? RUN_PLAN : RUN_PLAN_PARTIAL;
   ctx->last_n = ctx->n_items;
@@ -1003,8 +1025,11 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
   for (uint64_t i = 0; i < ctx->n_items; ++i) flags[i] = skip_done[i] ? 1 : 0;
   HIP_TRY(ctx, hipMemcpy(done, flags.data(), ctx->n_items, hipMemcpyHostToDevice));
   const uint64_t n_long = count_long(todo_n, todo.size(), ctx->long_min);
+  uint64_t total = 0;
+  for (uint64_t n : todo_n) total += n;
+  const uint32_t split = todo_n.empty() ? 1u : plan_split_for(ctx, todo_n[0], total);
   st = run_plan_impl(ctx, seed, s, ctx->resume_order.as<uint32_t>(), todo.size(), n_long,
-                     ctx->plan_rpw, ctx->plan_wg, ctx->plan_split, whole, done, false);
+                     ctx->plan_rpw, ctx->plan_wg, split, whole, done, false);
   if (st != MRIP_OK) return st;
   ctx->last = whole ? RUN_PLAN : RUN_PLAN_PARTIAL;
   ctx->last_n = ctx->n_items;
@@ -1107,6 +1132,7 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
       ctx->plan_rpw = e.reps_per_wave;
       ctx->plan_wg = e.workgroup;
       ctx->plan_split = e.plan_split;
+      ctx->plan_split_set = true;
       if (best_rpw) *best_rpw = e.reps_per_wave;
       if (best_wg)
         *best_wg = (e.plan_split > 1 && n_long > 0) ? (e.plan_split == 8 ? 512u : 256u) : e.workgroup;
@@ -1141,6 +1167,7 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
     }
   }
   ctx->plan_split = bx;
+  ctx->plan_split_set = true;
   ctx->plan_rpw = br;
   ctx->plan_wg = bw;
   ctx->last = RUN_NONE;  // outputs of the timing runs are partial

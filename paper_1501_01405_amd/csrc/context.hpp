@@ -49,7 +49,7 @@ enum RunKind { RUN_NONE = 0, RUN_UNIFORM = 1, RUN_PLAN = 2, RUN_PLAN_PARTIAL = 3
 // (longest first) and its grouping by design point (index + offsets).
 struct ItemBufs {
   DevBuf dp, rep, n, lambda, mu, order, index, offsets;
-  uint64_t count = 0, max_customers = 0, n_long = 0;
+  uint64_t count = 0, max_customers = 0, n_long = 0, total_customers = 0;
   std::vector<uint32_t> dp_ids;          // distinct design points, ascending
   std::vector<uint64_t> group_offsets;   // host copy of offsets
   std::vector<uint32_t> index_host;      // host copy of index
@@ -94,6 +94,14 @@ struct CvState {
   float run_ms = 0.f, infer_ms = 0.f;
 };
 
+// Wavefronts per long item for a plan run whose longest item has `longest`
+// customers out of `total`: as fixed by mrip_set_plan_split or the
+// autotuner, else the fewest (up to plan_split) that bring the longest
+// item's share down to the run's average work per wavefront the chip holds
+// at once. Splitting shortens a plan only while its longest item sets the
+// makespan; beyond that its corrections and barriers cost time.
+uint32_t plan_split_for(mrip_ctx ctx, uint64_t longest, uint64_t total);
+
 }  // namespace mrip
 
 struct mrip_ctx_s {
@@ -108,9 +116,13 @@ struct mrip_ctx_s {
   // the plans' shape: mrip_set_shape sets it with the runs' one, the
   // autotuner alone (it never touches the runs' shape)
   uint32_t plan_rpw = 1, plan_wg = 256;
-  // plans: wavefronts per long item (1 = none) and what counts as long
+  // plans: wavefronts per long item (1 = none) and what counts as long;
+  // until mrip_set_plan_split or the autotuner fixes it, plan_split is the
+  // most a run uses (plan_split_for)
   uint32_t plan_split = 8;
   uint64_t long_min = 65536;
+  bool plan_split_set = false;
+  uint32_t cus = 0;  // compute units of the device (queried on first use)
   // stream source of mrip_run (MRIP_RNG_*) and, for taus88, its jump tables
   int rng = MRIP_RNG_PHILOX;
   mrip::DevBuf taus_tables;

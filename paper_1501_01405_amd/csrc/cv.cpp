@@ -94,6 +94,8 @@ mrip_status upload_items(mrip_ctx c, const mrip_plan_item *items, uint64_t n, ui
   b.group_offsets.push_back(n);
   b.index_host = index;
   b.max_customers = *std::max_element(cust.begin(), cust.end());
+  b.total_customers = 0;
+  for (uint64_t i = 0; i < n; ++i) b.total_customers += cust[i];
   b.n_long = 0;  // items of at least long_min customers: a prefix of the order
   while (b.n_long < n && cust[order[b.n_long]] >= long_min) ++b.n_long;
   CV_TRY(c, b.dp.ensure(4 * n));
@@ -118,7 +120,7 @@ mrip_status upload_items(mrip_ctx c, const mrip_plan_item *items, uint64_t n, ui
 }
 
 // Run an item table through the persistent M/M/1 kernels (the plan's form:
-// items of at least long_min customers split over plan_split wavefronts)
+// items of at least long_min customers split over plan_split_for wavefronts)
 // with feature capture over the first K customers and the controls after
 // them; `ms` (nullable) gets the kernel time.
 mrip_status run_items(mrip_ctx c, ItemBufs &b, uint64_t seed, uint64_t K, float *mean_w,
@@ -149,8 +151,9 @@ mrip_status run_items(mrip_ctx c, ItemBufs &b, uint64_t seed, uint64_t K, float 
   }
   CV_TRY(c, launch_zero_u32(a.queue_head, 2, s));
   if (ms) CV_TRY(c, hipEventRecord(e0, s));
-  if (c->plan_split > 1 && b.n_long > 0)
-    CV_TRY(c, launch_mm1_plan_split(a, b.count, b.n_long, c->plan_split, c->plan_rpw, s));
+  const uint32_t split = plan_split_for(c, b.max_customers, b.total_customers);
+  if (split > 1 && b.n_long > 0)
+    CV_TRY(c, launch_mm1_plan_split(a, b.count, b.n_long, split, c->plan_rpw, s));
   else
     CV_TRY(c, launch_mm1_plan(a, b.count, c->plan_rpw, c->plan_wg, s));
   if (ms) {
