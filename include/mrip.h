@@ -356,10 +356,11 @@ MRIP_API mrip_status mrip_plan_stats(mrip_ctx ctx, uint32_t dp, double confidenc
  * over waves_per_item (1, 2, 4 or 8) wavefronts of a workgroup, served first
  * (longest first) at raised wavefront priority, since the longest items set
  * the plan's makespan; the rest go reps_per_wave per wavefront. Until this
- * call (or mrip_autotune) fixes it, each plan run takes the fewest
- * wavefronts per long item, up to 8, that bring its longest item's share
- * down to the run's average work per wavefront the device holds at once
- * (16 per compute unit): a plan of many equal long items is not split. */
+ * call (or mrip_autotune) fixes it, a plan takes the fewest wavefronts per
+ * long item, up to 8, that bring its longest item's share of its customers
+ * down to its average per wavefront the device holds at once (16 per
+ * compute unit), the same in every run of the plan (stopped at an item
+ * limit or resumed): a plan of many equal long items is not split. */
 MRIP_API mrip_status mrip_set_plan_split(mrip_ctx ctx, uint32_t waves_per_item,
                                          uint64_t long_min);
 

@@ -872,6 +872,16 @@ mrip_status mrip_plan_set(mrip_ctx ctx, const mrip_plan_item *items, uint64_t n)
 }
 
 // Items of a longest-first order that count as long (a prefix of it).
+// The split of the uploaded plan's long items: decided on the whole plan
+// (its longest item and all its customers), so a run stopped at an item
+// limit or resumed from saved outputs splits every item as the
+// uninterrupted run does and gives the same bits.
+static uint32_t plan_split_of(mrip_ctx ctx) {
+  uint64_t total = 0;
+  for (uint64_t n : ctx->lpt_customers) total += n;
+  return plan_split_for(ctx, ctx->lpt_customers.empty() ? 0 : ctx->lpt_customers[0], total);
+}
+
 static uint64_t count_long(const std::vector<uint64_t> &lpt, uint64_t n, uint64_t long_min) {
   uint64_t k = 0;
   while (k < n && lpt[k] >= long_min) ++k;
@@ -970,9 +980,7 @@ mrip_status mrip_run_plan(mrip_ctx ctx, uint64_t seed, void *hip_stream) {
   const uint64_t n_long =
       std::min<uint64_t>(count_long(ctx->lpt_customers, ctx->n_items, ctx->long_min), n_run);
   const bool whole = n_run == ctx->n_items;
-  uint64_t total = 0;
-  for (uint64_t j = 0; j < n_run; ++j) total += ctx->lpt_customers[j];
-  const uint32_t split = plan_split_for(ctx, ctx->lpt_customers[0], total);
+  const uint32_t split = plan_split_of(ctx);
   uint8_t *done = nullptr;
   mrip_status st = done_flags(ctx, &done);
   if (st != MRIP_OK) return st;
@@ -1025,9 +1033,7 @@ mrip_status mrip_run_plan_resume(mrip_ctx ctx, uint64_t seed, const uint8_t *ski
   for (uint64_t i = 0; i < ctx->n_items; ++i) flags[i] = skip_done[i] ? 1 : 0;
   HIP_TRY(ctx, hipMemcpy(done, flags.data(), ctx->n_items, hipMemcpyHostToDevice));
   const uint64_t n_long = count_long(todo_n, todo.size(), ctx->long_min);
-  uint64_t total = 0;
-  for (uint64_t n : todo_n) total += n;
-  const uint32_t split = todo_n.empty() ? 1u : plan_split_for(ctx, todo_n[0], total);
+  const uint32_t split = plan_split_of(ctx);
   st = run_plan_impl(ctx, seed, s, ctx->resume_order.as<uint32_t>(), todo.size(), n_long,
                      ctx->plan_rpw, ctx->plan_wg, split, whole, done, false);
   if (st != MRIP_OK) return st;

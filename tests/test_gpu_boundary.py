@@ -107,6 +107,28 @@ def test_resumed_plan_equals_uninterrupted_plan(gpu):
     assert np.array_equal(bufs[0].cpu().numpy(), want[0])
 
 
+def test_resumed_plan_splits_long_items_as_the_whole_plan_does(gpu):
+    # 8192 equal long items: the whole plan holds enough work per wavefront
+    # slot that its long items run unsplit by default; the 5 % left to a
+    # resumed run alone would be split eight ways. The split is the plan's,
+    # so the resumed items come out with the uninterrupted run's bits.
+    announce("plan resume, default split of many long items")
+    items = inputs.uniform_items(64, 128, 70000, np.linspace(0.5, 0.95, 64))
+    n = len(items)
+    full = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), WAVE)
+    full.plan_set(items)
+    full.run_plan(seed=4)
+    want = full.output(0, n=n).cpu().numpy()
+    done = (np.arange(n) % 20 != 7).astype(np.uint8)
+    ctx = mrip.Context(mrip.MRIP_MM1, mrip.mm1_params(), WAVE)
+    ctx.plan_set(items)
+    t = torch.full((n,), float("nan"), device="cuda")
+    ctx.bind_output(0, t)
+    ctx.run_plan_resume(done, seed=4)
+    got = t.cpu().numpy()
+    assert np.array_equal(got[done == 0], want[done == 0])
+
+
 def _tuples(items):
     return [(int(r["dp"]), int(r["rep"]), int(r["customers"]), float(r["lambda_"]),
              float(r["mu"])) for r in items]
