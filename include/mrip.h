@@ -375,7 +375,8 @@ MRIP_API mrip_status mrip_get_shape(mrip_ctx ctx, uint32_t *reps_per_wave, uint3
  * when the plan has long items, every reps_per_wave with long items split
  * over 2, 4 or 8 wavefronts (workgroups of 256 threads, 512 for 8), on the
  * uploaded plan (or on an evenly strided slice of `calib_items` items of
- * its longest-first order, 0 = all); keep the fastest as the context's plan
+ * its longest-first order, 0 = all; each the best of four runs after a
+ * warm-up); keep the fastest as the context's plan
  * shape (mrip_run's shape is left as it is) and report its reps_per_wave,
  * the workgroup size it launches and its time (mrip_get_shape gives the
  * split). WAVE contexts only (MRIP_E_UNSUPPORTED otherwise). Synchronises. */

@@ -1157,7 +1157,9 @@ mrip_status mrip_autotune(mrip_ctx ctx, uint64_t seed, uint64_t calib_items, voi
   uint32_t br = ctx->plan_rpw, bw = ctx->plan_wg, bx = ctx->plan_split;
   for (const Shape &sh : shapes) {
     float t_min = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {  // the first launch warms up
+    // the first launch warms up; the best of four more, since shapes a few
+    // per cent apart swap places in single timings
+    for (int rep = 0; rep < 5; ++rep) {
       mrip_status st = run_plan_impl(ctx, seed, s, order, n, n_long, sh.rpw, sh.wg, sh.split, false);
       if (st != MRIP_OK) return st;
       float ms = 0.f;
